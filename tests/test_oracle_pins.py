@@ -1,0 +1,375 @@
+"""Pins of the FP64 oracle against things other than itself: closed forms,
+independent formulations (product of exponentials, projection distance),
+brute force, central finite differences and textbook library routines."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from scipy.spatial import distance as spd
+from scipy.spatial.transform import Rotation
+
+import oracle as O
+from paper_2411_11833_amd import inputs as I
+
+DT = torch.float64
+
+
+def _robot():
+    return I.make_robot(3, n_spheres=40)
+
+
+# ----------------------------------------------------------------------------- FK
+
+
+def test_fk_zero_pose_closed_form():
+    """At q = 0 the alternating +-90 deg twists cancel pairwise: the tool sits at
+    (0, d2 + d4 + d6, d1 + d3 + d5 + d7 + tool_d) with the identity rotation."""
+    r = _robot()
+    d = r.dh[:, 2]
+    F = O.fk_frames(r, torch.zeros(1, 7, dtype=DT))[-1][0].numpy()
+    want = np.array([0.0, d[1] + d[3] + d[5], d[0] + d[2] + d[4] + d[6] + r.tool_d])
+    np.testing.assert_allclose(F[:3, 3], want, atol=1e-14)
+    np.testing.assert_allclose(F[:3, :3], np.eye(3), atol=1e-14)
+
+
+def test_fk_first_and_last_joint():
+    r = _robot()
+    F0 = O.fk_frames(r, torch.zeros(1, 7, dtype=DT))[-1][0].numpy()
+    phi = 0.7
+    q = torch.zeros(1, 7, dtype=DT)
+    q[0, 0] = phi
+    F1 = O.fk_frames(r, q)[-1][0].numpy()
+    Rz = np.eye(4)
+    Rz[:3, :3] = Rotation.from_rotvec([0, 0, phi]).as_matrix()
+    np.testing.assert_allclose(F1, Rz @ F0, atol=1e-14)
+    q = torch.zeros(1, 7, dtype=DT)
+    q[0, 6] = phi
+    F7 = O.fk_frames(r, q)[-1][0].numpy()
+    np.testing.assert_allclose(F7, F0 @ Rz, atol=1e-14)
+
+
+def _poe_fk(r, q):
+    """Independent FK: product of exponentials with twists read off the zero
+    pose.  For a = 0, theta0 = 0 and twists (-90, 90, -90, 90, -90, 90, 0) deg
+    the joint axes at q = 0 alternate z, y, z, y, z, y, z through the points
+    0, (0,0,d1), (0,d2,d1), (0,d2,d1+d3), ..."""
+    d = r.dh[:, 2]
+    axes = [(0, 0, 1), (0, 1, 0)] * 3 + [(0, 0, 1)]
+    pts, y, z = [], 0.0, 0.0
+    for i in range(7):
+        pts.append((0.0, y, z))
+        if i % 2 == 0:
+            z += d[i]
+        else:
+            y += d[i]
+    F0 = np.eye(4)
+    F0[:3, 3] = (0.0, d[1] + d[3] + d[5], d[0] + d[2] + d[4] + d[6] + r.tool_d)
+    T = np.eye(4)
+    for i in range(7):
+        R = Rotation.from_rotvec(np.array(axes[i], float) * q[i]).as_matrix()
+        E = np.eye(4)
+        E[:3, :3] = R
+        E[:3, 3] = (np.eye(3) - R) @ np.array(pts[i])
+        T = T @ E
+    return T @ F0
+
+
+def test_fk_matches_product_of_exponentials():
+    r = _robot()
+    rng = np.random.default_rng(0)
+    q = rng.uniform(-2.8, 2.8, size=(16, 7))
+    F = O.fk_frames(r, torch.tensor(q))[-1].numpy()
+    for b in range(16):
+        np.testing.assert_allclose(F[b], _poe_fk(r, q[b]), atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- SDF
+
+
+def _box(c=(0.1, -0.2, 0.3), yaw=0.4, h=(0.05, 0.08, 0.03)):
+    T = O.trans(*c) @ O.rz(torch.tensor(yaw, dtype=DT))
+    return T[None], torch.tensor(h, dtype=DT)
+
+
+def _world(T, local):
+    return (T[0, :3, :3].numpy() @ np.asarray(local, float)) + T[0, :3, 3].numpy()
+
+
+def test_sdf_analytic_cases():
+    T, h = _box()
+    hn = h.numpy()
+    pts = [
+        (_world(T, [hn[0] + 0.02, 0, 0]), 0.02),                    # on the x-face normal
+        (_world(T, [0, -(hn[1] + 0.05), 0]), 0.05),                 # on the -y face normal
+        (_world(T, [0, 0, 0]), -hn.min()),                          # centre
+        (_world(T, hn + [0.01, 0.02, 0.02]), 0.03),                 # past a corner: |(1,2,2)| cm
+        (_world(T, [0.0, 0.0, hn[2] - 0.01]), -0.01),               # just inside the top face
+    ]
+    c = torch.tensor(np.array([p for p, _ in pts])[None])
+    got = O.box_sdf(c, T, h)[0].numpy()
+    np.testing.assert_allclose(got, [v for _, v in pts], atol=1e-14)
+
+
+def _brute_sdf(p_local, h, n=161):
+    """Distance to a dense grid on the box surface, signed by an inside test."""
+    g = [np.linspace(-h[i], h[i], n) for i in range(3)]
+    faces = []
+    for ax in range(3):
+        o = [a for a in range(3) if a != ax]
+        A, Bm = np.meshgrid(g[o[0]], g[o[1]], indexing="ij")
+        for s in (-1, 1):
+            f = np.zeros((A.size, 3))
+            f[:, ax] = s * h[ax]
+            f[:, o[0]] = A.ravel()
+            f[:, o[1]] = Bm.ravel()
+            faces.append(f)
+    S = np.concatenate(faces)
+    d = np.sqrt(((S - p_local) ** 2).sum(1)).min()
+    inside = np.all(np.abs(p_local) < h)
+    return -d if inside else d
+
+
+def test_sdf_brute_force():
+    rng = np.random.default_rng(1)
+    h = np.array([0.05, 0.08, 0.03])
+    T, ht = _box(h=tuple(h))
+    spacing = 2 * h.max() / 160
+    for _ in range(40):
+        loc = rng.uniform(-0.15, 0.15, size=3)
+        c = torch.tensor(_world(T, loc)[None, None])
+        got = float(O.box_sdf(c, T, ht)[0, 0])
+        assert abs(got - _brute_sdf(loc, h)) <= spacing, (loc, got)
+
+
+def test_penalty_rigid_motion_invariance():
+    rng = np.random.default_rng(2)
+    T, h = _box()
+    c = torch.tensor(np.array([0.1, -0.2, 0.3]) + rng.uniform(-0.15, 0.15, size=(1, 30, 3)))
+    r = torch.tensor(rng.uniform(0.03, 0.08, size=30))
+    base = O.sphere_box_penalty(c, r, T, h)
+    M = O.trans(0.3, -0.1, 0.05) @ O.rz(torch.tensor(1.1, dtype=DT))
+    c2 = (M[:3, :3] @ c[0].T).T + M[:3, 3]
+    moved = O.sphere_box_penalty(c2[None], r, M[None] @ T, h)
+    np.testing.assert_allclose(moved.numpy(), base.numpy(), atol=1e-14)
+    assert (base > 0).any() and (base == 0).any()
+
+
+# ----------------------------------------------------------------------------- pose error
+
+
+def test_pose_error_closed_forms():
+    rng = np.random.default_rng(3)
+    A = np.eye(4)
+    A[:3, :3] = Rotation.random(random_state=4).as_matrix()
+    A[:3, 3] = rng.normal(size=3)
+    At = torch.tensor(A)[None]
+    p, r = O.pose_error(At, At)
+    assert float(p) == 0.0 and abs(float(r)) < 1e-7
+    delta = np.array([0.01, -0.02, 0.005])
+    Bm = A.copy()
+    Bm[:3, 3] += delta
+    p, r = O.pose_error(At, torch.tensor(Bm)[None])
+    assert abs(float(p) - np.linalg.norm(delta)) < 1e-15 and abs(float(r)) < 1e-7
+    for phi in (0.3, -1.2, 2.9, math.pi - 1e-3):
+        axis = rng.normal(size=3)
+        axis /= np.linalg.norm(axis)
+        Bm = A.copy()
+        Bm[:3, :3] = A[:3, :3] @ Rotation.from_rotvec(axis * phi).as_matrix()
+        p, r = O.pose_error(At, torch.tensor(Bm)[None])
+        assert abs(float(r) - abs(phi)) < 1e-12
+        p2, r2 = O.pose_error(torch.tensor(Bm)[None], At)
+        assert abs(float(r2) - float(r)) < 1e-12     # symmetric
+        # scipy's own geodesic magnitude of R_a^T R_b
+        rel = Rotation.from_matrix(A[:3, :3].T @ Bm[:3, :3]).magnitude()
+        assert abs(float(r) - rel) < 1e-10
+
+
+# ----------------------------------------------------------------------------- bounds / distances
+
+
+def test_dist_from_bounds_is_projection_distance():
+    rng = np.random.default_rng(5)
+    lo, hi = np.array([-1.0, 0.0, 0.5]), np.array([1.0, 0.2, 0.6])
+    v = rng.uniform(-2, 2, size=(200, 3))
+    want = np.linalg.norm(np.clip(v, lo, hi) - v, axis=1)
+    got = O.dist_from_bounds(torch.tensor(v), lo, hi).numpy()
+    np.testing.assert_allclose(got, want, atol=1e-15)
+    inside = rng.uniform(lo, hi, size=(20, 3))
+    assert np.all(O.dist_from_bounds(torch.tensor(inside), lo, hi).numpy() == 0)
+
+
+def test_pairwise_distance_matches_scipy_pdist():
+    rng = np.random.default_rng(6)
+    p = rng.normal(size=(7, 4, 3))
+    got = O.pairwise_dist_sum(torch.tensor(p)).numpy()
+    want = np.array([spd.pdist(p[b]).sum() for b in range(7)])
+    np.testing.assert_allclose(got, want, rtol=1e-15, atol=1e-15)
+    # translation invariance
+    got2 = O.pairwise_dist_sum(torch.tensor(p + np.array([0.3, -2.0, 1.0]))).numpy()
+    np.testing.assert_allclose(got2, want, rtol=1e-13)
+
+
+# ----------------------------------------------------------------------------- Adam
+
+
+def test_adam_matches_torch_optim():
+    rng = np.random.default_rng(7)
+    x0 = rng.normal(size=(5, 6))
+    grads = [rng.normal(size=(5, 6)) for _ in range(4)]
+    p = torch.nn.Parameter(torch.tensor(x0))
+    opt = torch.optim.Adam([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    x, m, v = x0.copy(), np.zeros_like(x0), np.zeros_like(x0)
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        p.grad = torch.tensor(g * 0.25)
+        opt.step()
+        x, m, v = O.adam_step(x, m, v, g, t, grad_scale=0.25)
+        np.testing.assert_allclose(x, p.detach().numpy(), rtol=0, atol=1e-15)
+
+
+def test_adam_frozen_and_skipped():
+    rng = np.random.default_rng(8)
+    x, g = rng.normal(size=(3, 4)), rng.normal(size=(3, 4))
+    frozen = np.array([0, 1, 0, 0], bool)
+    skip = np.array([0, 0, 1], bool)
+    x1, m1, v1 = O.adam_step(x, np.zeros_like(x), np.zeros_like(x), g, 1, frozen=frozen, skip=skip)
+    assert np.all(x1[:, 1] == x[:, 1]) and np.all(x1[2] == x[2]) and np.all(m1[2] == 0)
+    assert np.all(x1[0, [0, 2, 3]] != x[0, [0, 2, 3]])
+
+
+# ----------------------------------------------------------------------------- whole cost
+
+
+def _small_packing(waypoints=0):
+    return I.packing(robot_seed=1, scene_seed=2, n_objects=3, n_obstacles=3, waypoints=waypoints)
+
+
+def test_mask_semantics():
+    prob = I.single_pick_place(0, 0)
+    eps = O.tolerance_vector(prob)
+    nc = prob.n_constraint_terms
+    T = np.zeros((4, prob.n_terms))
+    T[0, :nc] = eps                       # exactly at the tolerance: satisfied (<=)
+    T[1, :nc] = eps
+    T[1, 0] = eps[0] + 1e-12              # just above one tolerance
+    T[2, 4] = np.nan                      # NaN never satisfies
+    T[3, :nc] = eps * 0.5
+    assert O.mask(prob, T).tolist() == [True, False, False, True]
+
+
+def test_far_scene_has_no_collision_cost():
+    """With every box moved far away, the collision terms vanish and the
+    remaining terms are unchanged."""
+    prob = I.single_pick_place(0, 0)
+    X = I.uniform_particles(prob, 32, seed=1).astype(np.float64)
+    T = O.terms(prob, X)
+    far = I.Problem(prob.robot, I.Scene(table=prob.scene.table + np.array([-100, 0, 0, 0, 0, 0, 0]),
+                                        obstacles=prob.scene.obstacles + np.array([100, 0, 0, 0, 0, 0, 0]),
+                                        objects=prob.scene.objects, obj_spheres=prob.scene.obj_spheres,
+                                        region_lo=prob.scene.region_lo, region_hi=prob.scene.region_hi),
+                    prob.skeleton)
+    Tf = O.terms(far, X)
+    coll = [8, 9, 10]
+    assert np.all(Tf[:, coll] == 0)
+    assert np.any(T[:, coll] > 0)
+    other = [i for i in range(11) if i not in coll]
+    np.testing.assert_allclose(Tf[:, other], T[:, other], rtol=0, atol=1e-14)
+
+
+def _rotate_problem_quarter_turn(prob):
+    """The whole world turned by +90 deg about the base's z-axis."""
+    def rot_boxes(b):
+        b = b.copy()
+        x, y = b[:, 0].copy(), b[:, 1].copy()
+        b[:, 0], b[:, 1] = -y, x
+        b[:, 3] = b[:, 3] + math.pi / 2
+        return b
+    sc = prob.scene
+    lo, hi = sc.region_lo, sc.region_hi
+    scene = I.Scene(table=rot_boxes(sc.table[None])[0], obstacles=rot_boxes(sc.obstacles),
+                    objects=rot_boxes(sc.objects), obj_spheres=sc.obj_spheres,
+                    region_lo=np.array([-hi[1], lo[0]]), region_hi=np.array([-lo[1], hi[0]]))
+    return I.Problem(prob.robot, scene, prob.skeleton, prob.weights, prob.tolerances)
+
+
+def _rotate_particles(prob, X):
+    X = X.copy()
+    for k in range(prob.skeleton.n_steps):
+        o = 21 * k
+        X[:, o + 0] += math.pi / 2           # first joint of both configurations
+        X[:, o + 7] += math.pi / 2
+        x, y = X[:, o + 18].copy(), X[:, o + 19].copy()
+        X[:, o + 18], X[:, o + 19] = -y, x
+        X[:, o + 20] += math.pi / 2
+    return X
+
+
+def test_cost_invariant_under_world_rotation():
+    prob = _small_packing()
+    X = I.uniform_particles(prob, 24, seed=3).astype(np.float64)
+    X[:, [21 * k + j for k in range(3) for j in (0, 7)]] *= 0.3     # keep q1 + 90deg inside the limits
+    T = O.terms(prob, X)
+    T2 = O.terms(_rotate_problem_quarter_turn(prob), _rotate_particles(prob, X))
+    np.testing.assert_allclose(T2, T, rtol=1e-10, atol=1e-12)
+    assert np.all(T[:, [8 + 11 * k for k in range(3)]] >= 0)
+
+
+def test_cost_is_weighted_sum_and_particle_permutation():
+    prob = _small_packing()
+    X = I.uniform_particles(prob, 16, seed=4).astype(np.float64)
+    T = O.terms(prob, X)
+    J = O.cost(prob, X)
+    np.testing.assert_allclose(J, T @ O.weights_vector(prob), rtol=1e-15)
+    perm = np.random.default_rng(0).permutation(16)
+    np.testing.assert_array_equal(O.terms(prob, X[perm]), T[perm])
+
+
+@pytest.mark.parametrize("which", ["single", "packing", "motion"])
+def test_gradient_matches_central_differences(which):
+    if which == "single":
+        prob = I.single_pick_place(0, 1)
+    elif which == "packing":
+        prob = _small_packing()
+    else:
+        prob = I.packing(robot_seed=1, scene_seed=2, n_objects=2, n_obstacles=2, waypoints=4)
+    X = I.uniform_particles(prob, 24, seed=5).astype(np.float64)
+    _, kink = O.margins(prob, X)
+    X = X[kink >= 1e-4][:8]
+    assert len(X) >= 4
+    J, G = O.cost_and_grad(prob, X)
+    h = 1e-6
+    Xt = torch.tensor(X)
+    for i in range(prob.dim):
+        xp, xm = Xt.clone(), Xt.clone()
+        xp[:, i] += h
+        xm[:, i] -= h
+        with torch.no_grad():
+            fd = (O.evaluate(prob, xp).cost - O.evaluate(prob, xm).cost).numpy() / (2 * h)
+        err = np.abs(G[:, i] - fd)
+        assert np.all(err <= 1e-5 * np.abs(fd) + 1e-6 * (1 + np.abs(J))), (i, err.max())
+
+
+def test_gradient_independent_of_batch_size():
+    prob = _small_packing()
+    X = I.uniform_particles(prob, 9, seed=6).astype(np.float64)
+    _, G = O.cost_and_grad(prob, X)
+    _, G1 = O.cost_and_grad(prob, X[3:4])
+    np.testing.assert_allclose(G1[0], G[3], rtol=1e-14, atol=1e-15)
+
+
+def test_held_object_follows_the_tool():
+    """The held object's pose is FK(q) * G^-1: with the grasp target met
+    exactly, the held spheres coincide with the object at its pose."""
+    r = _robot()
+    q = torch.tensor(np.random.default_rng(9).uniform(-1, 1, size=(1, 7)))
+    F = O.fk_frames(r, q)[-1]
+    g = torch.tensor([[0.01, -0.005, 0.02, 0.7]], dtype=DT)
+    G = O.grasp_tf(g)
+    obj = F @ torch.linalg.inv(G)
+    # grasp definition: tool z-axis points along -z of the object frame
+    z_tool_in_obj = (torch.linalg.inv(obj) @ F)[0, :3, 2].numpy()
+    np.testing.assert_allclose(z_tool_in_obj, [0, 0, -1], atol=1e-14)
+    np.testing.assert_allclose((torch.linalg.inv(obj) @ F)[0, :3, 3].numpy(), g[0, :3].numpy(), atol=1e-14)
+    p, rr = O.pose_error(F, obj @ G)
+    assert float(p) < 1e-14 and float(rr) < 1e-7

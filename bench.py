@@ -1,0 +1,213 @@
+"""Benchmark of the plain method's particle step on one MI355X.
+
+One *step* = one full plain-method solve of the four-object packing skeleton
+(4 pick-place steps, 84-D particles, 60 robot spheres, 8 obstacle boxes,
+pairwise goal cost): uniform initialization of 8192 particles on the GPU,
+then 500 fused cost + gradient + Adam + mask iterations replayed as one
+captured graph.  The metric is particle-iterations per second.
+
+Also reported on the same JSON line:
+  * time to the first satisfying particle (stop-at-first run, flag polled
+    every 10 iterations) and the satisfied count after 500 iterations;
+  * the roofline position of the fused step kernel: algorithmic flops per
+    launch / its average launch time (HIP events on its stream);
+  * the FP64 CPU oracle timed on the host cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "particle-iters/s (fwd+bwd+Adam); time-to-satisfy: plain vs learned seeds"
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--particles", type=int, default=8192)
+    ap.add_argument("--iters", type=int, default=500)
+    ap.add_argument("--scene-seed", type=int, default=0)
+    ap.add_argument("--robot-seed", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(prob, budget_s: float):
+    """The FP64 oracle (cost, autodiff gradient, Adam) as it stands, on a
+    bounded sample of the same workload: 64-particle batches of the same
+    scene, repeated until ~budget_s of CPU work."""
+    import torch
+    import oracle as O
+    from paper_2411_11833_amd import inputs as I
+
+    n = 64
+    X = I.uniform_particles(prob, n, seed=99).astype(np.float64)
+    M, V = np.zeros_like(X), np.zeros_like(X)
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        _, G = O.cost_and_grad(prob, X)
+        X, M, V = O.adam_step(X, M, V, G, it + 1, grad_scale=1.0 / n)
+        it += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n * it / dt, "unit": "particle-iters/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} particles x {it} iterations of the same 84-D packing CSP, FP64 autodiff, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle path shards "
+              "across GPUs without per-iteration exchange, but no multi-GPU run is part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd import workmodel
+    from paper_2411_11833_amd.planner import GpuProblem, default_adam, plain_solve, INT32_MAX
+
+    q = args.quiet
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prob = I.packing(robot_seed=args.robot_seed, scene_seed=args.scene_seed)
+    gp = GpuProblem(prob, dev)
+    n, iters = args.particles, args.iters
+    adam = default_adam(n)
+    X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
+    cost = torch.empty(n, dtype=torch.float32, device=dev)
+    mask = torch.empty(n, dtype=torch.uint8, device=dev)
+    flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    gp.seed_uniform(1234, X, M, V, n)
+    if args.split:
+        gp.set_split(args.split)
+        split = args.split
+    else:
+        split = gp.autotune(X, n)
+    log(f"[bench] workload ready: N={n} D={gp.dim} iters={iters} split={split}", q)
+
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(nb, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written", q)
+
+    def solve_step(seed):
+        flag.fill_(INT32_MAX)
+        gp.seed_uniform(seed, X, M, V, n)
+        gp.optimize(X, M, V, n, 0, iters, adam, cost=cost, mask=mask, first_sat=flag)
+
+    for w in range(args.warmup):
+        solve_step(10 + w)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} solves)", q)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        solve_step(100 + s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sat_end = int(mask.sum().item())
+    first_iter_full = int(flag.item())
+    value = n * iters * args.steps / elapsed
+    log(f"[bench] timed {args.steps} solves: {elapsed:.3f} s -> {value:.4g} particle-iters/s", q)
+
+    # ---- the fused step kernel alone: HIP events on its stream
+    reps = 200
+    gp.seed_uniform(7, X, M, V, n)
+    for t in range(1, 11):
+        gp.step(X, M, V, n, t, adam)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for t in range(11, 11 + reps):
+        gp.step(X, M, V, n, t, adam)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    kernel_s = e0.elapsed_time(e1) / 1e3 / reps
+    wk = workmodel.per_particle_iteration(prob)
+    achieved = wk.flops * n / kernel_s / 1e12
+    log(f"[bench] step kernel: {kernel_s * 1e6:.1f} us avg over {reps} launches; "
+        f"{achieved:.2f} TFLOP/s (model {wk.flops} flop/particle-iter)", q)
+
+    # ---- time to the first satisfying particle (plain method, stop at first)
+    res = plain_solve(gp, n, iters, seed=4242, check_every=10, stop_at_first=True, adam=adam, X=X)
+    log(f"[bench] time-to-first: {res.time_to_first_s} s at iteration {res.first_sat_iter}", q)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain method, 4-object packing: 4 pick-place steps (84-D particle), 60 robot "
+                        "spheres, 8 obstacle boxes + table, pairwise goal cost; uniform init, "
+                        f"{n} particles x {iters} Adam iterations (lr 1e-2) per step",
+            "particles": n, "iters_per_step": iters, "scene_seed": args.scene_seed,
+            "robot_seed": args.robot_seed, "split": split,
+        },
+        "time_to_first_s": res.time_to_first_s,
+        "first_sat_iter": res.first_sat_iter,
+        "first_sat_iter_full_run": None if first_iter_full == INT32_MAX else first_iter_full,
+        "satisfied_after_full_run": sat_end,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "traffic": None,
+            "kernel": "ct::particle_kernel<4,S,MODE_STEP>",
+            "kernel_us": kernel_s * 1e6,
+            "flop_per_particle_iter": wk.flops,
+            "algorithmic_bytes_per_launch": wk.bytes * n,
+            "hbm_gbs_algorithmic": wk.bytes * n / kernel_s / 1e9,
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle ...", q)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,254 @@
+/*
+ * cutamp.h -- C ABI of the MI355X particle cost / gradient / Adam step of
+ * differentiable GPU-parallelized task and motion planning (Shen et al.,
+ * "Differentiable GPU-Parallelized Task and Motion Planning").
+ *
+ * A plan skeleton of K pick-place steps induces a continuous constraint
+ * satisfaction problem (Sec. IV-A).  A *particle* is one assignment to all of
+ * its continuous variables; per step k it holds 21 floats at offset 21k:
+ *
+ *     [ q_grasp(7) | q_place(7) | grasp gx gy gz gyaw (4) | place px py pyaw (3) ]
+ *
+ * Each constraint c has a cost J_c >= 0 and a tolerance eps_c; the particle
+ * cost is the weighted sum of Eq. (2) and a particle is satisfying when every
+ * constraint holds, Eq. (3).  A batch of N particles is optimized on the mean
+ * cost of Eq. (4) with Adam (Sec. IV-B).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Particle buffers are FP32, dimension-major (structure of arrays):
+ *    element (d, i) of particle i lives at X[d * ld + i], 0 <= i < n.
+ *    Requirements: ld >= n, ld % 64 == 0, base pointer 256-byte aligned.
+ *    The same layout and ld apply to M, V (Adam moments) and G (gradient).
+ *  - All buffer arguments named X, M, V, G, cost, terms, mask, frozen and
+ *    first_sat are DEVICE pointers owned by the caller.  The library never
+ *    frees or keeps them, and step calls never allocate.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream); every call
+ *    only enqueues work on it and returns without synchronizing.
+ *  - n == 0 is a valid empty batch: the call validates and returns CT_OK
+ *    without launching anything.
+ *  - Return values: CT_OK, or an error code (see ct_status_string).  Argument
+ *    errors are detected synchronously before any work is enqueued.  Launch
+ *    failures report CT_ERR_DEVICE; faults inside a kernel surface at the
+ *    caller's next synchronization.  No C++ exception crosses this boundary.
+ *  - A particle with a non-finite coordinate gets a non-finite cost, mask 0,
+ *    and is left untouched by Adam; this is not an error.
+ *  - A problem handle is immutable after creation except for its tuning
+ *    choice and graph cache; calls on one handle must not overlap in time
+ *    from several host threads.  Separate handles are independent.
+ */
+#ifndef CUTAMP_H
+#define CUTAMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CT_OK = 0,
+    CT_ERR_INVALID_ARG = 1,   /* null / out-of-range / misaligned argument   */
+    CT_ERR_UNSUPPORTED = 2,   /* valid request beyond this build's limits    */
+    CT_ERR_ALLOC = 3,         /* device allocation failed (create only)      */
+    CT_ERR_DEVICE = 4         /* a HIP runtime call or kernel launch failed  */
+};
+
+/* Limits of this build (CT_ERR_UNSUPPORTED beyond them). */
+#define CT_N_JOINTS 7
+#define CT_MAX_STEPS 6
+#define CT_MAX_ROBOT_SPHERES 128
+#define CT_MAX_STATIC_BOXES 32
+#define CT_MAX_OBJECTS 24
+#define CT_MAX_OBJ_SPHERES 16
+#define CT_MAX_WAYPOINTS 32
+#define CT_STEP_DIM 21
+#define CT_TERMS_PER_STEP 11
+
+/*
+ * Robot: a 7-joint revolute arm in standard Denavit-Hartenberg form.
+ * Forward kinematics FK(q) (the map named in Kin, Sec. III):
+ *   F_0 = identity (base at the world origin),
+ *   F_i = F_{i-1} Rz(q_i + theta0_i) Tz(d_i) Tx(a_i) Rx(alpha_i),  i = 1..7,
+ *   F_ee = F_7 Tz(tool_d).
+ * The robot is approximated by spheres rigid with a link frame
+ * (App. "Collision Representation").
+ */
+typedef struct ct_robot {
+    int32_t n_joints;          /* must be 7                                        */
+    const double *dh;          /* [7][4]: a, alpha, d, theta0 (metres / radians)    */
+    const double *q_lo;        /* [7] joint lower limits                            */
+    const double *q_hi;        /* [7] joint upper limits, q_hi > q_lo               */
+    double tool_d;             /* tool offset along z of frame 7                    */
+    int32_t n_spheres;         /* 1 .. CT_MAX_ROBOT_SPHERES                         */
+    const double *spheres;     /* [n_spheres][4]: x, y, z, radius in the parent frame; radius > 0 */
+    const int32_t *sphere_link;/* [n_spheres]: 1..7 = frame F_i, 8 = tool frame F_ee */
+} ct_robot;
+
+/*
+ * World: a table and obstacles as yaw-only oriented boxes, movable objects
+ * (boxes approximated by spheres when moved), and a rectangular region on the
+ * table that placements must lie in.  A box is 7 doubles:
+ *   (cx, cy, cz, yaw, hx, hy, hz): centre, rotation about world z, half extents > 0.
+ * The table's top face (cz + hz) is the support height of placements.
+ */
+typedef struct ct_scene {
+    const double *table;       /* [7]                                               */
+    int32_t n_obstacles;       /* >= 0                                               */
+    const double *obstacles;   /* [n_obstacles][7]                                   */
+    int32_t n_objects;         /* 1 .. CT_MAX_OBJECTS                                */
+    const double *objects;     /* [n_objects][7]: initial pose (cx, cy, cz, yaw) + half extents */
+    int32_t n_obj_spheres;     /* spheres per object, 1 .. CT_MAX_OBJ_SPHERES        */
+    const double *obj_spheres; /* [n_objects][n_obj_spheres][4]: x, y, z, r in the object frame */
+    double region_lo[2];       /* placement region (x, y), lo < hi                   */
+    double region_hi[2];
+} ct_scene;
+
+/*
+ * Skeleton: K pick-place steps, step k moves object object_of_step[k]
+ * (Pick then Place, Listing 1).  Objects not listed stay at their initial
+ * poses as obstacles.  goal_cost adds the soft pairwise distance of all
+ * placed objects (the MinimizeObjDist goal action, Sec. III "Goal Costs").
+ * waypoints > 0 adds, for each of the 2K transitions q0 -> q_g^1 -> q_p^1 ->
+ * q_g^2 ... , a collision term over `waypoints` interior linearly
+ * interpolated configurations and the soft TrajLength cost (MoveFree /
+ * MoveHold, Listing 1).
+ */
+typedef struct ct_skeleton {
+    int32_t n_steps;               /* K, 1 .. CT_MAX_STEPS                          */
+    const int32_t *object_of_step; /* [K] distinct indices into scene objects        */
+    const double *grasp_lo;        /* [K][3] valid grasp positions (tool origin in   */
+    const double *grasp_hi;        /* [K][3]  the object frame), lo <= hi            */
+    int32_t goal_cost;             /* 0 or 1                                         */
+    int32_t waypoints;             /* 0 .. CT_MAX_WAYPOINTS                          */
+    const double *q0;              /* [7] start configuration; used if waypoints > 0 */
+} ct_skeleton;
+
+/* Weights lambda of Eq. (2) (App. "Cost Weights"). */
+typedef struct ct_weights {
+    double kin_pos, kin_rot, grasp, place, jlim, coll, goal, traj_len, motion_coll;
+} ct_weights;
+
+/* Tolerances eps of Eq. (3) (App. "Constraint Tolerances"); all >= 0. */
+typedef struct ct_tolerances {
+    double kin_pos, kin_rot, grasp, place, jlim, coll, motion_coll;
+} ct_tolerances;
+
+/* Adam hyper-parameters (Sec. IV-B).  grad_scale multiplies dJ/dx before the
+ * moments are updated: 1/N_b gives the batch mean of Eq. (4). */
+typedef struct ct_adam {
+    float lr, beta1, beta2, eps, grad_scale;
+} ct_adam;
+
+typedef struct ct_problem ct_problem;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *ct_status_string(int status);
+
+/*
+ * Validate the descriptors, build the constraint and term tables of the
+ * skeleton's CSP (Sec. IV-A), and upload them to the current HIP device.
+ * All descriptor pointers are host pointers, read only during the call.
+ * On success *out owns the device tables (freed by ct_problem_destroy).
+ * Errors: CT_ERR_INVALID_ARG, CT_ERR_UNSUPPORTED, CT_ERR_ALLOC, CT_ERR_DEVICE.
+ */
+int ct_problem_create(const ct_robot *robot, const ct_scene *scene, const ct_skeleton *skeleton,
+                      const ct_weights *weights, const ct_tolerances *tolerances,
+                      ct_problem **out);
+
+/* Release a handle and its device tables (NULL is accepted). */
+int ct_problem_destroy(ct_problem *problem);
+
+/*
+ * Sizes of the problem: particle dimension (21 K), number of terms, and how
+ * many of them are constraints (the rest are soft costs, which never enter
+ * the mask).  Term order: per step k the 11 terms
+ *   kin_pick_pos, kin_pick_rot, kin_place_pos, kin_place_rot, grasp, place,
+ *   jlim_grasp, jlim_place, coll_grasp, coll_place_conf, coll_placed_obj,
+ * then (with waypoints) one collision term per transition, then the goal
+ * cost (if enabled), then TrajLength (if waypoints > 0).
+ * Any output pointer may be NULL.
+ */
+int ct_problem_info(const ct_problem *problem, int32_t *dim, int32_t *n_terms,
+                    int32_t *n_constraint_terms);
+
+/*
+ * Uniform initialization within bounds (the Optimization baseline of
+ * Sec. VII): joint angles in their limits, grasp positions in the grasp box,
+ * yaws in [-pi, pi), placement x, y in the region.  Dimension d of particle i
+ * uses Philox4x32-10 (Salmon et al., SC'11) with key (seed low, seed high
+ * 32 bits) and counter (i, d / 4, 0, 0), word d % 4 -> u = (w >> 8) 2^-24,
+ * x = lo_d + (hi_d - lo_d) u in FP32.  M and V, when non-NULL, are zeroed
+ * for the same particles.
+ */
+int ct_seed_uniform(const ct_problem *problem, uint64_t seed, float *X, float *M, float *V,
+                    int64_t n, int64_t ld, void *stream);
+
+/*
+ * Cost of Eq. (2) per particle: cost[i] (FP32, [n]).  Optional outputs:
+ * terms [n_terms][ld] unweighted term values, and mask[i] = 1 iff particle i
+ * satisfies every constraint (Eq. (3), J_c <= eps_c).  terms and mask may be
+ * NULL.  X is read only.
+ */
+int ct_cost(const ct_problem *problem, const float *X, int64_t n, int64_t ld, float *cost,
+            float *terms, uint8_t *mask, void *stream);
+
+/*
+ * Cost and its gradient dJ/dx per particle (not scaled by 1/N_b):
+ * G [dim][ld].  cost may be NULL.
+ */
+int ct_cost_grad(const ct_problem *problem, const float *X, int64_t n, int64_t ld, float *cost,
+                 float *G, void *stream);
+
+/*
+ * Adam update number t (t >= 1, 1-based, bias-corrected) using the
+ * gradient G: g = grad_scale * G; m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * x -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).
+ * frozen (device [dim] bytes, may be NULL) keeps dimensions fixed (the
+ * paper's fixed-grasp mode).  A particle with any non-finite G or X entry is
+ * left untouched.
+ */
+int ct_adam_apply(const ct_problem *problem, float *X, float *M, float *V, const float *G,
+                  int64_t n, int64_t ld, int64_t t, const ct_adam *adam, const uint8_t *frozen,
+                  void *stream);
+
+/*
+ * One fused optimization step: cost, gradient, mask and Adam update number t
+ * in a single kernel (X, M, V updated in place).  cost and mask report the
+ * particle *before* this update.  If some particle is satisfying,
+ * *first_sat = min(*first_sat, t - 1) (an atomic on a device int the caller
+ * initializes, e.g. to INT32_MAX); first_sat may be NULL.  cost and mask may
+ * be NULL.
+ */
+int ct_step(const ct_problem *problem, float *X, float *M, float *V, int64_t n, int64_t ld,
+            int64_t t, const ct_adam *adam, const uint8_t *frozen, float *cost, uint8_t *mask,
+            int32_t *first_sat, void *stream);
+
+/*
+ * `iters` fused steps with updates t0+1 .. t0+iters, launched as one HIP
+ * graph (captured on first use for this argument set and cached in the
+ * handle; a call with different arguments re-captures).  cost / mask hold the
+ * values of the last step; first_sat as in ct_step.  The first call for an
+ * argument set may allocate graph resources; later identical calls do not.
+ */
+int ct_optimize(ct_problem *problem, float *X, float *M, float *V, int64_t n, int64_t ld,
+                int64_t t0, int32_t iters, const ct_adam *adam, const uint8_t *frozen,
+                float *cost, uint8_t *mask, int32_t *first_sat, void *stream);
+
+/*
+ * Kernel shape: split = how many lanes share one particle configuration's
+ * sphere list (1, 2 or 4; 0 = library default).  ct_autotune times every
+ * supported split on a copy of the given particles (it allocates and frees
+ * scratch copies; X is not modified) and keeps the fastest; *chosen (host,
+ * may be NULL) receives it.
+ */
+int ct_set_split(ct_problem *problem, int32_t split);
+int ct_get_split(const ct_problem *problem, int32_t *split);
+int ct_autotune(ct_problem *problem, const float *X, int64_t n, int64_t ld, int32_t *chosen,
+                void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUTAMP_H */

@@ -1,0 +1,193 @@
+"""Thin ctypes binding of libcutamp.so (include/cutamp.h), same names as the C ABI.
+
+Argument marshalling only: device buffers are passed as integer addresses
+(``tensor.data_ptr()``), streams as integer ``hipStream_t`` handles
+(``torch.cuda.current_stream().cuda_stream``).  Every call raises
+``CtError`` on a non-zero status.  Importing this module fails loudly when
+the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import inputs as I
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcutamp.so")
+
+CT_OK, CT_ERR_INVALID_ARG, CT_ERR_UNSUPPORTED, CT_ERR_ALLOC, CT_ERR_DEVICE = range(5)
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class CtRobot(C.Structure):
+    _fields_ = [("n_joints", C.c_int32), ("dh", _dp), ("q_lo", _dp), ("q_hi", _dp), ("tool_d", C.c_double),
+                ("n_spheres", C.c_int32), ("spheres", _dp), ("sphere_link", _ip)]
+
+
+class CtScene(C.Structure):
+    _fields_ = [("table", _dp), ("n_obstacles", C.c_int32), ("obstacles", _dp), ("n_objects", C.c_int32),
+                ("objects", _dp), ("n_obj_spheres", C.c_int32), ("obj_spheres", _dp),
+                ("region_lo", C.c_double * 2), ("region_hi", C.c_double * 2)]
+
+
+class CtSkeleton(C.Structure):
+    _fields_ = [("n_steps", C.c_int32), ("object_of_step", _ip), ("grasp_lo", _dp), ("grasp_hi", _dp),
+                ("goal_cost", C.c_int32), ("waypoints", C.c_int32), ("q0", _dp)]
+
+
+class CtWeights(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("kin_pos", "kin_rot", "grasp", "place", "jlim", "coll", "goal",
+                                          "traj_len", "motion_coll")]
+
+
+class CtTolerances(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("kin_pos", "kin_rot", "grasp", "place", "jlim", "coll",
+                                          "motion_coll")]
+
+
+class CtAdam(C.Structure):
+    _fields_ = [(n, C.c_float) for n in ("lr", "beta1", "beta2", "eps", "grad_scale")]
+
+
+class CtError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {ct_status_string(status)} ({status})")
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2411_11833_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64
+    sig = {
+        "ct_status_string": (C.c_char_p, [C.c_int]),
+        "ct_problem_create": (C.c_int, [C.POINTER(CtRobot), C.POINTER(CtScene), C.POINTER(CtSkeleton),
+                                        C.POINTER(CtWeights), C.POINTER(CtTolerances), C.POINTER(vp)]),
+        "ct_problem_destroy": (C.c_int, [vp]),
+        "ct_problem_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
+        "ct_seed_uniform": (C.c_int, [vp, u64, vp, vp, vp, i64, i64, vp]),
+        "ct_cost": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp]),
+        "ct_cost_grad": (C.c_int, [vp, vp, i64, i64, vp, vp, vp]),
+        "ct_adam_apply": (C.c_int, [vp, vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp]),
+        "ct_step": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp, vp, vp, vp]),
+        "ct_optimize": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, i32, C.POINTER(CtAdam), vp, vp, vp, vp, vp]),
+        "ct_set_split": (C.c_int, [vp, i32]),
+        "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
+        "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype, f.argtypes = res, args
+    return lib
+
+
+LIB = _load()
+
+
+def _chk(status: int, what: str):
+    if status != CT_OK:
+        raise CtError(status, what)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def ct_status_string(status: int) -> str:
+    return LIB.ct_status_string(int(status)).decode()
+
+
+def ct_problem_create(prob: I.Problem) -> int:
+    """Marshal an inputs.Problem into the C descriptors and create a handle
+    (an opaque integer).  The numpy buffers only need to live for the call."""
+    r, sc, sk, w, e = prob.robot, prob.scene, prob.skeleton, prob.weights, prob.tolerances
+    keep = []
+
+    def dp(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return _dptr(a)
+
+    def ip(a):
+        a = np.ascontiguousarray(a, dtype=np.int32)
+        keep.append(a)
+        return a.ctypes.data_as(_ip)
+
+    robot = CtRobot(7, dp(r.dh), dp(r.q_lo), dp(r.q_hi), float(r.tool_d), int(r.spheres.shape[0]),
+                    dp(r.spheres), ip(r.sphere_link))
+    scene = CtScene(dp(sc.table), int(sc.obstacles.shape[0]), dp(sc.obstacles.reshape(-1, 7)),
+                    int(sc.objects.shape[0]), dp(sc.objects), int(sc.obj_spheres.shape[1]), dp(sc.obj_spheres),
+                    (C.c_double * 2)(*sc.region_lo), (C.c_double * 2)(*sc.region_hi))
+    K = sk.n_steps
+    glo = np.array([prob.grasp_bounds(k)[0] for k in range(K)])
+    ghi = np.array([prob.grasp_bounds(k)[1] for k in range(K)])
+    skel = CtSkeleton(K, ip(sk.object_of_step), dp(glo), dp(ghi), int(sk.goal_cost), int(sk.waypoints),
+                      dp(sk.q0))
+    weights = CtWeights(w.kin_pos, w.kin_rot, w.grasp, w.place, w.jlim, w.coll, w.goal, w.traj_len,
+                        w.motion_coll)
+    tols = CtTolerances(e.kin_pos, e.kin_rot, e.grasp, e.place, e.jlim, e.coll, e.motion_coll)
+    h = C.c_void_p()
+    _chk(LIB.ct_problem_create(C.byref(robot), C.byref(scene), C.byref(skel), C.byref(weights),
+                               C.byref(tols), C.byref(h)), "ct_problem_create")
+    return h.value
+
+
+def ct_problem_destroy(h: int) -> None:
+    _chk(LIB.ct_problem_destroy(h), "ct_problem_destroy")
+
+
+def ct_problem_info(h: int) -> tuple[int, int, int]:
+    d, t, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _chk(LIB.ct_problem_info(h, C.byref(d), C.byref(t), C.byref(c)), "ct_problem_info")
+    return d.value, t.value, c.value
+
+
+def ct_seed_uniform(h, seed, X, M, V, n, ld, stream=0):
+    _chk(LIB.ct_seed_uniform(h, int(seed) & (2 ** 64 - 1), X, M, V, n, ld, stream), "ct_seed_uniform")
+
+
+def ct_cost(h, X, n, ld, cost, terms=None, mask=None, stream=0):
+    _chk(LIB.ct_cost(h, X, n, ld, cost, terms, mask, stream), "ct_cost")
+
+
+def ct_cost_grad(h, X, n, ld, cost, G, stream=0):
+    _chk(LIB.ct_cost_grad(h, X, n, ld, cost, G, stream), "ct_cost_grad")
+
+
+def _adam(lr, beta1, beta2, eps, grad_scale):
+    return CtAdam(lr, beta1, beta2, eps, grad_scale)
+
+
+def ct_adam_apply(h, X, M, V, G, n, ld, t, adam: CtAdam, frozen=None, stream=0):
+    _chk(LIB.ct_adam_apply(h, X, M, V, G, n, ld, t, C.byref(adam), frozen, stream), "ct_adam_apply")
+
+
+def ct_step(h, X, M, V, n, ld, t, adam: CtAdam, frozen=None, cost=None, mask=None, first_sat=None, stream=0):
+    _chk(LIB.ct_step(h, X, M, V, n, ld, t, C.byref(adam), frozen, cost, mask, first_sat, stream), "ct_step")
+
+
+def ct_optimize(h, X, M, V, n, ld, t0, iters, adam: CtAdam, frozen=None, cost=None, mask=None,
+                first_sat=None, stream=0):
+    _chk(LIB.ct_optimize(h, X, M, V, n, ld, t0, iters, C.byref(adam), frozen, cost, mask, first_sat, stream),
+         "ct_optimize")
+
+
+def ct_set_split(h, split: int):
+    _chk(LIB.ct_set_split(h, split), "ct_set_split")
+
+
+def ct_get_split(h) -> int:
+    s = C.c_int32()
+    _chk(LIB.ct_get_split(h, C.byref(s)), "ct_get_split")
+    return s.value
+
+
+def ct_autotune(h, X, n, ld, stream=0) -> int:
+    s = C.c_int32()
+    _chk(LIB.ct_autotune(h, X, n, ld, C.byref(s), stream), "ct_autotune")
+    return s.value

@@ -1,0 +1,89 @@
+// Elementwise kernels around the fused step: the uniform initializer and the
+// stand-alone Adam update.
+#pragma once
+
+#include "ct_tables.hpp"
+
+namespace ct {
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies and xors, with the key bumped by the Weyl constants between
+// rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// One thread per particle: uniform draw inside the initialization box for
+// every dimension (stores coalesced along particles), moments zeroed.
+__global__ __launch_bounds__(256) void seed_uniform_kernel(const Tables* __restrict__ T, uint32_t k0,
+                                                           uint32_t k1, float* __restrict__ X,
+                                                           float* __restrict__ M, float* __restrict__ V,
+                                                           int64_t n, int64_t ld) {
+#pragma clang fp contract(off)
+    // lo + (hi - lo) u with one rounding per operation (no fused multiply-add),
+    // so that any IEEE single-precision implementation reproduces it bit for bit
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int D = T->D;
+    for (int b = 0; 4 * b < D; ++b) {
+        uint32_t c[4] = {(uint32_t)i, (uint32_t)b, 0u, 0u};
+        philox4x32_10(c, k0, k1);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int d = 4 * b + w;
+            if (d < D) {
+                const float u = (float)(c[w] >> 8) * 5.9604644775390625e-08f;   // 2^-24
+                const float lo = T->lo[d], hi = T->hi[d];
+                X[d * ld + i] = lo + (hi - lo) * u;
+                if (M) M[d * ld + i] = 0.f;
+                if (V) V[d * ld + i] = 0.f;
+            }
+        }
+    }
+}
+
+// Stand-alone Adam: one thread per particle, so that a particle with a
+// non-finite gradient or coordinate is skipped as a whole.
+__global__ __launch_bounds__(256) void adam_kernel(int D, float* __restrict__ X, float* __restrict__ M,
+                                                   float* __restrict__ V, const float* __restrict__ G,
+                                                   const uint8_t* __restrict__ frozen, int64_t n, int64_t ld,
+                                                   float lr, float b1, float b2, float eps, float gscale,
+                                                   int32_t t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+    bool fin = true;
+    for (int d = 0; d < D; ++d) {
+        const float s = G[d * ld + i] + X[d * ld + i];
+        fin = fin && __builtin_isfinite(s);
+    }
+    if (!fin) return;
+    for (int d = 0; d < D; ++d) {
+        if (frozen && frozen[d]) continue;
+        const int64_t a = d * ld + i;
+        const float gs = gscale * G[a];
+        const float m1 = b1 * M[a] + (1.f - b1) * gs;
+        const float v1 = b2 * V[a] + (1.f - b2) * gs * gs;
+        X[a] = X[a] - lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
+        M[a] = m1;
+        V[a] = v1;
+    }
+}
+
+// Device counter of applied Adam updates, set before a captured loop.
+__global__ void counter_set_kernel(int32_t* c, int32_t v) { *c = v; }
+
+}  // namespace ct

@@ -1,0 +1,545 @@
+// Host side of the C ABI declared in include/cutamp.h: descriptor validation,
+// construction of the device tables of one skeleton's CSP, kernel dispatch,
+// the graph-captured optimization loop and the split autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cutamp.h"
+#include "aux_kernels.hpp"
+#include "ct_tables.hpp"
+#include "pk_dispatch.hpp"
+
+namespace {
+
+struct GraphKey {
+    float *X = nullptr, *M = nullptr, *V = nullptr, *cost = nullptr;
+    uint8_t* mask = nullptr;
+    int32_t* first_sat = nullptr;
+    const uint8_t* frozen = nullptr;
+    int64_t n = -1, ld = -1;
+    int32_t iters = -1, split = -1;
+    float lr = 0, b1 = 0, b2 = 0, eps = 0, gs = 0;
+    bool operator==(const GraphKey& o) const {
+        return X == o.X && M == o.M && V == o.V && cost == o.cost && mask == o.mask &&
+               first_sat == o.first_sat && frozen == o.frozen && n == o.n && ld == o.ld &&
+               iters == o.iters && split == o.split && lr == o.lr && b1 == o.b1 && b2 == o.b2 &&
+               eps == o.eps && gs == o.gs;
+    }
+};
+
+}  // namespace
+
+struct ct_problem {
+    ct::Tables h;               // host copy of the tables
+    ct::Tables* d = nullptr;    // device copy
+    int K = 0, D = 0, n_terms = 0, nc = 0;
+    int split = 0;              // 0 = default
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t* t_dev = nullptr;   // two-slot device counter of applied updates for captured loops
+    GraphKey key;
+};
+
+namespace {
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+bool valid_box(const double* b) {
+    for (int i = 0; i < 7; ++i)
+        if (!is_fin(b[i])) return false;
+    return b[4] > 0 && b[5] > 0 && b[6] > 0;
+}
+
+ct::Box to_box(const double* b) {
+    ct::Box o;
+    o.cx = (float)b[0];
+    o.cy = (float)b[1];
+    o.cz = (float)b[2];
+    o.c = (float)std::cos(b[3]);
+    o.s = (float)std::sin(b[3]);
+    o.hx = (float)b[4];
+    o.hy = (float)b[5];
+    o.hz = (float)b[6];
+    return o;
+}
+
+int default_split(int K) { return K <= 1 ? 4 : (K <= 2 ? 2 : 1); }
+
+// n == 0 is an empty batch: only the handle and ld are checked
+bool empty_ok(const ct_problem* P, int64_t n, int64_t ld) { return P && n == 0 && ld >= 0 && ld % 64 == 0; }
+
+bool good_layout(const void* p, int64_t n, int64_t ld) {
+    if (n < 0 || ld < n || ld % 64 != 0) return false;
+    return n == 0 || ((uintptr_t)p % 256) == 0;
+}
+
+int err_of(hipError_t e) { return e == hipSuccess ? CT_OK : CT_ERR_DEVICE; }
+
+AdamArgs adam_args(const ct_adam* a) {
+    AdamArgs o;
+    o.lr = a->lr;
+    o.b1 = a->beta1;
+    o.b2 = a->beta2;
+    o.eps = a->eps;
+    o.gs = a->grad_scale;
+    return o;
+}
+
+bool valid_adam(const ct_adam* a) {
+    return a && std::isfinite(a->lr) && a->beta1 >= 0 && a->beta1 < 1 && a->beta2 >= 0 && a->beta2 < 1 &&
+           std::isfinite(a->eps) && a->eps >= 0 && std::isfinite(a->grad_scale);
+}
+
+// ---------------------------------------------------------------------------
+// particle kernel dispatch: K in 1..6 (one object file per K), split in
+// {1, 2, 4}, three modes
+
+PkFn pick_kernel(int K, int split, int mode) {
+    switch (K) {
+        case 1: return ct_pick_k1(split, mode);
+        case 2: return ct_pick_k2(split, mode);
+        case 3: return ct_pick_k3(split, mode);
+        case 4: return ct_pick_k4(split, mode);
+        case 5: return ct_pick_k5(split, mode);
+        case 6: return ct_pick_k6(split, mode);
+        default: return nullptr;
+    }
+}
+
+int effective_split(const ct_problem* P) { return P->split ? P->split : default_split(P->K); }
+
+int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0) {
+    if (a.n == 0) return CT_OK;
+    PkFn f = pick_kernel(P->K, split ? split : effective_split(P), mode);
+    if (!f) return CT_ERR_UNSUPPORTED;
+    return err_of(f(P->d, a, st));
+}
+
+void drop_graph(ct_problem* P) {
+    if (P->gexec) hipGraphExecDestroy(P->gexec);
+    if (P->graph) hipGraphDestroy(P->graph);
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    P->key = GraphKey();
+}
+
+}  // namespace
+
+// ===========================================================================
+
+extern "C" const char* ct_status_string(int status) {
+    switch (status) {
+        case CT_OK: return "ok";
+        case CT_ERR_INVALID_ARG: return "invalid argument";
+        case CT_ERR_UNSUPPORTED: return "unsupported by this build";
+        case CT_ERR_ALLOC: return "device allocation failed";
+        case CT_ERR_DEVICE: return "HIP runtime or kernel launch failure";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, const ct_skeleton* sk,
+                                 const ct_weights* w, const ct_tolerances* e, ct_problem** out) {
+    if (!out) return CT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!robot || !scene || !sk || !w || !e) return CT_ERR_INVALID_ARG;
+    // ---- robot
+    if (robot->n_joints != CT_N_JOINTS) return CT_ERR_UNSUPPORTED;
+    if (!robot->dh || !robot->q_lo || !robot->q_hi || !robot->spheres || !robot->sphere_link)
+        return CT_ERR_INVALID_ARG;
+    if (robot->n_spheres < 1) return CT_ERR_INVALID_ARG;
+    if (robot->n_spheres > CT_MAX_ROBOT_SPHERES) return CT_ERR_UNSUPPORTED;
+    for (int i = 0; i < 4 * CT_N_JOINTS; ++i)
+        if (!is_fin(robot->dh[i])) return CT_ERR_INVALID_ARG;
+    for (int i = 0; i < CT_N_JOINTS; ++i)
+        if (!is_fin(robot->q_lo[i]) || !is_fin(robot->q_hi[i]) || !(robot->q_lo[i] < robot->q_hi[i]))
+            return CT_ERR_INVALID_ARG;
+    if (!is_fin(robot->tool_d)) return CT_ERR_INVALID_ARG;
+    for (int s = 0; s < robot->n_spheres; ++s) {
+        for (int c = 0; c < 4; ++c)
+            if (!is_fin(robot->spheres[4 * s + c])) return CT_ERR_INVALID_ARG;
+        if (!(robot->spheres[4 * s + 3] > 0)) return CT_ERR_INVALID_ARG;
+        if (robot->sphere_link[s] < 1 || robot->sphere_link[s] > 8) return CT_ERR_INVALID_ARG;
+    }
+    // ---- scene
+    if (!scene->table || !valid_box(scene->table)) return CT_ERR_INVALID_ARG;
+    if (scene->n_obstacles < 0 || (scene->n_obstacles > 0 && !scene->obstacles)) return CT_ERR_INVALID_ARG;
+    for (int b = 0; b < scene->n_obstacles; ++b)
+        if (!valid_box(scene->obstacles + 7 * b)) return CT_ERR_INVALID_ARG;
+    if (scene->n_objects < 1 || !scene->objects || !scene->obj_spheres) return CT_ERR_INVALID_ARG;
+    if (scene->n_objects > CT_MAX_OBJECTS) return CT_ERR_UNSUPPORTED;
+    for (int o = 0; o < scene->n_objects; ++o)
+        if (!valid_box(scene->objects + 7 * o)) return CT_ERR_INVALID_ARG;
+    if (scene->n_obj_spheres < 1) return CT_ERR_INVALID_ARG;
+    if (scene->n_obj_spheres > CT_MAX_OBJ_SPHERES) return CT_ERR_UNSUPPORTED;
+    for (int i = 0; i < scene->n_objects * scene->n_obj_spheres; ++i) {
+        for (int c = 0; c < 4; ++c)
+            if (!is_fin(scene->obj_spheres[4 * i + c])) return CT_ERR_INVALID_ARG;
+        if (!(scene->obj_spheres[4 * i + 3] > 0)) return CT_ERR_INVALID_ARG;
+    }
+    for (int c = 0; c < 2; ++c)
+        if (!is_fin(scene->region_lo[c]) || !is_fin(scene->region_hi[c]) ||
+            !(scene->region_lo[c] < scene->region_hi[c]))
+            return CT_ERR_INVALID_ARG;
+    // ---- skeleton
+    const int K = sk->n_steps;
+    if (K < 1) return CT_ERR_INVALID_ARG;
+    if (K > CT_MAX_STEPS) return CT_ERR_UNSUPPORTED;
+    if (!sk->object_of_step || !sk->grasp_lo || !sk->grasp_hi) return CT_ERR_INVALID_ARG;
+    if (sk->goal_cost != 0 && sk->goal_cost != 1) return CT_ERR_INVALID_ARG;
+    if (sk->waypoints < 0) return CT_ERR_INVALID_ARG;
+    if (sk->waypoints > 0) return CT_ERR_UNSUPPORTED;   // the motion cost has its own entry points
+    std::vector<int> used(scene->n_objects, 0);
+    for (int k = 0; k < K; ++k) {
+        const int o = sk->object_of_step[k];
+        if (o < 0 || o >= scene->n_objects || used[o]) return CT_ERR_INVALID_ARG;
+        used[o] = 1;
+        for (int c = 0; c < 3; ++c)
+            if (!is_fin(sk->grasp_lo[3 * k + c]) || !is_fin(sk->grasp_hi[3 * k + c]) ||
+                sk->grasp_lo[3 * k + c] > sk->grasp_hi[3 * k + c])
+                return CT_ERR_INVALID_ARG;
+    }
+    const int n_unmoved = scene->n_objects - K;
+    if (1 + scene->n_obstacles + n_unmoved > CT_MAX_STATIC_BOXES) return CT_ERR_UNSUPPORTED;
+    // ---- weights and tolerances
+    const double ws[9] = {w->kin_pos, w->kin_rot, w->grasp, w->place, w->jlim, w->coll, w->goal, w->traj_len,
+                          w->motion_coll};
+    for (double v : ws)
+        if (!is_fin(v) || v < 0) return CT_ERR_INVALID_ARG;
+    const double es[7] = {e->kin_pos, e->kin_rot, e->grasp, e->place, e->jlim, e->coll, e->motion_coll};
+    for (double v : es)
+        if (!is_fin(v) || v < 0) return CT_ERR_INVALID_ARG;
+
+    ct_problem* P = new (std::nothrow) ct_problem();
+    if (!P) return CT_ERR_ALLOC;
+    ct::Tables& T = P->h;
+    std::memset(&T, 0, sizeof(T));
+    T.K = K;
+    T.D = CT_STEP_DIM * K;
+    T.W = sk->waypoints;
+    T.n_constraint = CT_TERMS_PER_STEP * K + (T.W > 0 ? 2 * K : 0);
+    T.goal = sk->goal_cost;
+    T.goal_term = T.goal ? T.n_constraint : -1;
+    T.traj_term = T.W > 0 ? T.n_constraint + T.goal : -1;
+    T.n_terms = T.n_constraint + T.goal + (T.W > 0 ? 1 : 0);
+    T.n_os = scene->n_obj_spheres;
+    for (int i = 0; i < CT_N_JOINTS; ++i) {
+        const double* r = robot->dh + 4 * i;
+        T.a[i] = (float)r[0];
+        T.ca[i] = (float)std::cos(r[1]);
+        T.sa[i] = (float)std::sin(r[1]);
+        T.d[i] = (float)r[2];
+        T.th0[i] = (float)r[3];
+        T.q_lo[i] = (float)robot->q_lo[i];
+        T.q_hi[i] = (float)robot->q_hi[i];
+        T.q0[i] = sk->q0 ? (float)sk->q0[i] : 0.f;
+    }
+    T.tool_d = (float)robot->tool_d;
+    // robot spheres grouped by link (stable within a link)
+    int cnt = 0;
+    T.link_start[0] = T.link_start[1] = 0;
+    for (int L = 1; L <= 8; ++L) {
+        T.link_start[L] = cnt;
+        for (int s = 0; s < robot->n_spheres; ++s)
+            if (robot->sphere_link[s] == L) {
+                const double* sp = robot->spheres + 4 * s;
+                T.rs[cnt++] = make_float4((float)sp[0], (float)sp[1], (float)sp[2], (float)sp[3]);
+            }
+    }
+    T.link_start[9] = cnt;
+    // boxes that never move
+    int nb = 0;
+    T.sbox[nb++] = to_box(scene->table);
+    for (int b = 0; b < scene->n_obstacles; ++b) T.sbox[nb++] = to_box(scene->obstacles + 7 * b);
+    for (int o = 0; o < scene->n_objects; ++o)
+        if (!used[o]) T.sbox[nb++] = to_box(scene->objects + 7 * o);
+    T.n_static = nb;
+    const double table_top = scene->table[2] + scene->table[6];
+    for (int k = 0; k < K; ++k) {
+        const int o = sk->object_of_step[k];
+        const double* ob = scene->objects + 7 * o;
+        T.obj0[k] = to_box(ob);
+        T.p0_yaw[k] = (float)ob[3];
+        T.place_z[k] = (float)(table_top + ob[6]);
+        for (int c = 0; c < 3; ++c) {
+            T.grasp_lo[k][c] = (float)sk->grasp_lo[3 * k + c];
+            T.grasp_hi[k][c] = (float)sk->grasp_hi[3 * k + c];
+        }
+        for (int m = 0; m < T.n_os; ++m) {
+            const double* sp = scene->obj_spheres + 4 * (o * T.n_os + m);
+            T.os[k][m] = make_float4((float)sp[0], (float)sp[1], (float)sp[2], (float)sp[3]);
+        }
+        // uniform-initialization box of step k's 21 coordinates
+        float* lo = T.lo + CT_STEP_DIM * k;
+        float* hi = T.hi + CT_STEP_DIM * k;
+        for (int j = 0; j < 7; ++j) {
+            lo[j] = lo[7 + j] = (float)robot->q_lo[j];
+            hi[j] = hi[7 + j] = (float)robot->q_hi[j];
+        }
+        for (int c = 0; c < 3; ++c) {
+            lo[14 + c] = (float)sk->grasp_lo[3 * k + c];
+            hi[14 + c] = (float)sk->grasp_hi[3 * k + c];
+        }
+        lo[17] = lo[20] = (float)-M_PI;
+        hi[17] = hi[20] = (float)M_PI;
+        lo[18] = (float)scene->region_lo[0];
+        hi[18] = (float)scene->region_hi[0];
+        lo[19] = (float)scene->region_lo[1];
+        hi[19] = (float)scene->region_hi[1];
+    }
+    for (int c = 0; c < 2; ++c) {
+        T.region_lo[c] = (float)scene->region_lo[c];
+        T.region_hi[c] = (float)scene->region_hi[c];
+    }
+    for (int i = 0; i < ct::W_N; ++i) T.w[i] = (float)ws[i];
+    for (int i = 0; i < ct::E_N; ++i) T.eps[i] = (float)es[i];
+
+    P->K = K;
+    P->D = T.D;
+    P->n_terms = T.n_terms;
+    P->nc = T.n_constraint;
+    if (hipMalloc(&P->d, sizeof(ct::Tables)) != hipSuccess) {
+        delete P;
+        return CT_ERR_ALLOC;
+    }
+    if (hipMalloc(&P->t_dev, 2 * sizeof(int32_t)) != hipSuccess) {
+        hipFree(P->d);
+        delete P;
+        return CT_ERR_ALLOC;
+    }
+    if (hipMemcpy(P->d, &T, sizeof(ct::Tables), hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(P->d);
+        hipFree(P->t_dev);
+        delete P;
+        return CT_ERR_DEVICE;
+    }
+    *out = P;
+    return CT_OK;
+}
+
+extern "C" int ct_problem_destroy(ct_problem* P) {
+    if (!P) return CT_OK;
+    drop_graph(P);
+    if (P->capture_stream) hipStreamDestroy(P->capture_stream);
+    if (P->d) hipFree(P->d);
+    if (P->t_dev) hipFree(P->t_dev);
+    delete P;
+    return CT_OK;
+}
+
+extern "C" int ct_problem_info(const ct_problem* P, int32_t* dim, int32_t* n_terms, int32_t* n_constraint) {
+    if (!P) return CT_ERR_INVALID_ARG;
+    if (dim) *dim = P->D;
+    if (n_terms) *n_terms = P->n_terms;
+    if (n_constraint) *n_constraint = P->nc;
+    return CT_OK;
+}
+
+extern "C" int ct_seed_uniform(const ct_problem* P, uint64_t seed, float* X, float* M, float* V, int64_t n,
+                               int64_t ld, void* stream) {
+    if (empty_ok(P, n, ld)) return CT_OK;
+    if (!P || !X || !good_layout(X, n, ld)) return CT_ERR_INVALID_ARG;
+    if ((M && !good_layout(M, n, ld)) || (V && !good_layout(V, n, ld))) return CT_ERR_INVALID_ARG;
+    if (n == 0) return CT_OK;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(ct::seed_uniform_kernel, grid, dim3(256), 0, (hipStream_t)stream, P->d,
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), X, M, V, n, ld);
+    return err_of(hipGetLastError());
+}
+
+extern "C" int ct_cost(const ct_problem* P, const float* X, int64_t n, int64_t ld, float* cost, float* terms,
+                       uint8_t* mask, void* stream) {
+    if (empty_ok(P, n, ld)) return CT_OK;
+    if (!P || !X || !cost || !good_layout(X, n, ld)) return CT_ERR_INVALID_ARG;
+    if (terms && !good_layout(terms, n, ld)) return CT_ERR_INVALID_ARG;
+    PkArgs a{};
+    a.X = const_cast<float*>(X);
+    a.cost = cost;
+    a.terms = terms;
+    a.mask = mask;
+    a.n = n;
+    a.ld = ld;
+    return run_pk(P, ct::MODE_COST, a, (hipStream_t)stream);
+}
+
+extern "C" int ct_cost_grad(const ct_problem* P, const float* X, int64_t n, int64_t ld, float* cost, float* G,
+                            void* stream) {
+    if (empty_ok(P, n, ld)) return CT_OK;
+    if (!P || !X || !G || !good_layout(X, n, ld) || !good_layout(G, n, ld)) return CT_ERR_INVALID_ARG;
+    PkArgs a{};
+    a.X = const_cast<float*>(X);
+    a.G = G;
+    a.cost = cost;
+    a.n = n;
+    a.ld = ld;
+    return run_pk(P, ct::MODE_GRAD, a, (hipStream_t)stream);
+}
+
+extern "C" int ct_adam_apply(const ct_problem* P, float* X, float* M, float* V, const float* G, int64_t n,
+                             int64_t ld, int64_t t, const ct_adam* adam, const uint8_t* frozen, void* stream) {
+    if (empty_ok(P, n, ld)) return CT_OK;
+    if (!P || !X || !M || !V || !G || t < 1 || !valid_adam(adam)) return CT_ERR_INVALID_ARG;
+    if (!good_layout(X, n, ld) || !good_layout(M, n, ld) || !good_layout(V, n, ld) || !good_layout(G, n, ld))
+        return CT_ERR_INVALID_ARG;
+    if (n == 0) return CT_OK;
+    const AdamArgs a = adam_args(adam);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(ct::adam_kernel, grid, dim3(256), 0, (hipStream_t)stream, P->D, X, M, V, G, frozen, n, ld,
+                       a.lr, a.b1, a.b2, a.eps, a.gs, (int32_t)t);
+    return err_of(hipGetLastError());
+}
+
+namespace {
+int step_impl(const ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld, int64_t t,
+              const ct_adam* adam, const uint8_t* frozen, float* cost, uint8_t* mask, int32_t* first_sat,
+              hipStream_t st, int split, const int32_t* t_in = nullptr, int32_t* t_out = nullptr) {
+    PkArgs a{};
+    a.X = X;
+    a.M = M;
+    a.V = V;
+    a.cost = cost;
+    a.mask = mask;
+    a.first_sat = first_sat;
+    a.frozen = frozen;
+    a.n = n;
+    a.ld = ld;
+    a.a = adam_args(adam);
+    a.t = (int32_t)t;
+    a.t_in = t_in;
+    a.t_out = t_out;
+    return run_pk(P, ct::MODE_STEP, a, st, split);
+}
+
+bool valid_step_args(const ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld,
+                     const ct_adam* adam) {
+    return P && X && M && V && valid_adam(adam) && good_layout(X, n, ld) && good_layout(M, n, ld) &&
+           good_layout(V, n, ld);
+}
+}  // namespace
+
+extern "C" int ct_step(const ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld, int64_t t,
+                       const ct_adam* adam, const uint8_t* frozen, float* cost, uint8_t* mask,
+                       int32_t* first_sat, void* stream) {
+    if (empty_ok(P, n, ld) && t >= 1) return CT_OK;
+    if (!valid_step_args(P, X, M, V, n, ld, adam) || t < 1) return CT_ERR_INVALID_ARG;
+    return step_impl(P, X, M, V, n, ld, t, adam, frozen, cost, mask, first_sat, (hipStream_t)stream, 0);
+}
+
+extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld, int64_t t0,
+                           int32_t iters, const ct_adam* adam, const uint8_t* frozen, float* cost, uint8_t* mask,
+                           int32_t* first_sat, void* stream) {
+    if (empty_ok(P, n, ld) && t0 >= 0 && iters >= 0) return CT_OK;
+    if (!valid_step_args(P, X, M, V, n, ld, adam) || t0 < 0 || iters < 0 || t0 + iters > INT32_MAX)
+        return CT_ERR_INVALID_ARG;
+    if (n == 0 || iters == 0) return CT_OK;
+    GraphKey key;
+    key.X = X; key.M = M; key.V = V; key.cost = cost; key.mask = mask; key.first_sat = first_sat;
+    key.frozen = frozen; key.n = n; key.ld = ld; key.iters = iters;
+    key.split = effective_split(P);
+    key.lr = adam->lr; key.b1 = adam->beta1; key.b2 = adam->beta2; key.eps = adam->eps;
+    key.gs = adam->grad_scale;
+    if (!(P->gexec && P->key == key)) {
+        // capture iters steps; the update number comes from the device
+        // counter (two slots used alternately), so one graph serves every t0
+        drop_graph(P);
+        if (!P->capture_stream && hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return CT_ERR_DEVICE;
+        if (hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return CT_ERR_DEVICE;
+        int rc = CT_OK;
+        for (int32_t it = 0; it < iters && rc == CT_OK; ++it) {
+            rc = step_impl(P, X, M, V, n, ld, 0, adam, frozen, cost, mask, first_sat, P->capture_stream, key.split,
+                           P->t_dev + (it & 1), P->t_dev + ((it + 1) & 1));
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(P->capture_stream, &g);
+        if (rc != CT_OK || ec != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return rc != CT_OK ? rc : CT_ERR_DEVICE;
+        }
+        hipGraphExec_t ge = nullptr;
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return CT_ERR_DEVICE;
+        }
+        P->graph = g;
+        P->gexec = ge;
+        P->key = key;
+    }
+    hipLaunchKernelGGL(ct::counter_set_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, P->t_dev, (int32_t)t0);
+    const int rc = err_of(hipGetLastError());
+    if (rc != CT_OK) return rc;
+    return err_of(hipGraphLaunch(P->gexec, (hipStream_t)stream));
+}
+
+extern "C" int ct_set_split(ct_problem* P, int32_t split) {
+    if (!P || !(split == 0 || split == 1 || split == 2 || split == 4)) return CT_ERR_INVALID_ARG;
+    if (split != P->split) drop_graph(P);
+    P->split = split;
+    return CT_OK;
+}
+
+extern "C" int ct_get_split(const ct_problem* P, int32_t* split) {
+    if (!P || !split) return CT_ERR_INVALID_ARG;
+    *split = effective_split(P);
+    return CT_OK;
+}
+
+extern "C" int ct_autotune(ct_problem* P, const float* X, int64_t n, int64_t ld, int32_t* chosen, void* stream) {
+    if (!P || !X || !good_layout(X, n, ld) || n == 0) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)P->D * (size_t)ld * sizeof(float);
+    float *Xs = nullptr, *Ms = nullptr, *Vs = nullptr;
+    if (hipMalloc(&Xs, bytes) != hipSuccess || hipMalloc(&Ms, bytes) != hipSuccess ||
+        hipMalloc(&Vs, bytes) != hipSuccess) {
+        hipFree(Xs);
+        hipFree(Ms);
+        hipFree(Vs);
+        return CT_ERR_ALLOC;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const ct_adam adam{1e-2f, 0.9f, 0.999f, 1e-8f, 1.f / (float)n};
+    const int cands[3] = {1, 2, 4};
+    float best = 1e30f;
+    int best_split = default_split(P->K);
+    int rc = CT_OK;
+    for (int c : cands) {
+        if (hipMemcpyAsync(Xs, X, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) { rc = CT_ERR_DEVICE; break; }
+        hipMemsetAsync(Ms, 0, bytes, st);
+        hipMemsetAsync(Vs, 0, bytes, st);
+        for (int w = 0; w < 2 && rc == CT_OK; ++w)
+            rc = step_impl(P, Xs, Ms, Vs, n, ld, 1 + w, &adam, nullptr, nullptr, nullptr, nullptr, st, c);
+        hipEventRecord(e0, st);
+        const int reps = 10;
+        for (int r = 0; r < reps && rc == CT_OK; ++r)
+            rc = step_impl(P, Xs, Ms, Vs, n, ld, 3 + r, &adam, nullptr, nullptr, nullptr, nullptr, st, c);
+        hipEventRecord(e1, st);
+        if (rc != CT_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = CT_ERR_DEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            best_split = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamSynchronize(st);
+    hipFree(Xs);
+    hipFree(Ms);
+    hipFree(Vs);
+    if (rc != CT_OK) return rc;
+    ct_set_split(P, best_split);
+    if (chosen) *chosen = best_split;
+    return CT_OK;
+}

@@ -1,0 +1,641 @@
+// Fused particle cost / gradient / mask / Adam kernel for gfx950.
+//
+// What it computes (per particle x of a K-step pick-place skeleton):
+//   the terms J_c of every constraint and soft cost (Sec. IV-A, App. "Cost
+//   Weights"), the weighted cost J(x) of Eq. (2), the satisfaction bit of
+//   Eq. (3), dJ/dx, and optionally Adam update number t on the batch-mean
+//   objective of Eq. (4) (Sec. IV-B).
+//
+// Work decomposition (one workgroup = 256 lanes = 4 wave64s):
+//   * a particle owns 2K "slots", one per robot configuration (q_grasp and
+//     q_place of each step); each slot is served by SPLIT adjacent lanes that
+//     share its sphere list.  A workgroup holds P = 256 / (2K SPLIT) particles.
+//   * phase 0 stages the particles' columns of the dimension-major X in LDS
+//     (coalesced rows), phase 1 runs every lane's configuration: forward
+//     kinematics, sphere transforms, sphere-vs-box penetration with its
+//     adjoint fused into the same pass, pose / bound terms; gradients leave
+//     the lane as world-frame wrenches folded onto the joint axes.
+//   * the SPLIT lanes of a slot reduce with cross-lane shuffles; slots of a
+//     particle meet in LDS; phase 2 sums each coordinate's partials in a fixed
+//     order (bit-reproducible) and writes G or applies Adam in place.
+//
+// Box and robot-sphere tables are read with wave-uniform indices (scalar
+// loads); per-lane data are the particle's own variables and the poses of
+// the objects it has already placed.
+#pragma once
+
+#include "ct_tables.hpp"
+
+namespace ct {
+
+
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// Penetration max(0, r - sdf) of a sphere into a yaw-only box.
+// (dx, dy, dz) = sphere centre minus box centre (world frame), (c, s) the
+// box yaw's cos / sin, h the half extents.  In the box frame p = R^T d,
+// u = |p| - h, sdf = ||max(u, 0)|| + min(max_i u_i, 0)  (App. "Collision
+// Representation": spheres against oriented boxes).  Returns false when the
+// sphere does not penetrate; otherwise pen = r - sdf > 0 and lam * d pen / d
+// centre (world frame) in (gx, gy, gz).
+// Tie conventions: sign(0) = +1; among equal interior depths the lowest axis.
+__device__ __forceinline__ bool pair_pen(float dx, float dy, float dz, float r, float c, float s,
+                                         float hx, float hy, float hz, float lam, float& pen,
+                                         float& gx, float& gy, float& gz) {
+    const float px = c * dx + s * dy;
+    const float py = c * dy - s * dx;
+    const float pz = dz;
+    const float ux = fabsf(px) - hx, uy = fabsf(py) - hy, uz = fabsf(pz) - hz;
+    const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
+    const float d2 = mx * mx + my * my + mz * mz;
+    if (!(d2 < r * r)) return false;
+    float sdf, ax, ay, az;  // sdf and d sdf / d p
+    if (d2 > 0.f) {
+        const float inv = fast_rsq(d2);
+        sdf = d2 * inv;
+        ax = copysignf(mx * inv, px);
+        ay = copysignf(my * inv, py);
+        az = copysignf(mz * inv, pz);
+    } else {
+        const float sx = px >= 0.f ? 1.f : -1.f;
+        const float sy = py >= 0.f ? 1.f : -1.f;
+        const float sz = pz >= 0.f ? 1.f : -1.f;
+        if (ux >= uy && ux >= uz) {
+            sdf = ux; ax = sx; ay = 0.f; az = 0.f;
+        } else if (uy >= uz) {
+            sdf = uy; ax = 0.f; ay = sy; az = 0.f;
+        } else {
+            sdf = uz; ax = 0.f; ay = 0.f; az = sz;
+        }
+    }
+    pen = r - sdf;
+    // d pen / d centre = -R d sdf / d p
+    gx = -lam * (c * ax - s * ay);
+    gy = -lam * (s * ax + c * ay);
+    gz = -lam * az;
+    return true;
+}
+
+// Poses of the moved objects as seen by one lane's step: placed by an earlier
+// step (at P(rho_j), a particle variable) or still at the initial pose.
+template <int K>
+struct Movables {
+    float x[K], y[K], c[K], s[K];
+};
+
+// One sphere against every box of step k: static boxes (uniform, scalar
+// loads) and the other moved objects (per lane).  Accumulates the unweighted
+// penetration, the weighted centre gradient, and the weighted gradient with
+// respect to the placements rho_j of boxes placed by earlier steps.
+template <int K, bool GRAD>
+__device__ __forceinline__ void sphere_vs_world(const Tables* __restrict__ T, const Movables<K>& mb,
+                                                int k, float cx, float cy, float cz, float r, float lam,
+                                                float& pen_sum, float& gcx, float& gcy, float& gcz,
+                                                float (&gr)[K][3]) {
+    const int nsb = T->n_static;
+    for (int b = 0; b < nsb; ++b) {
+        const Box B = T->sbox[b];
+        float pen, gx, gy, gz;
+        if (pair_pen(cx - B.cx, cy - B.cy, cz - B.cz, r, B.c, B.s, B.hx, B.hy, B.hz, lam, pen, gx, gy, gz)) {
+            pen_sum += pen;
+            if (GRAD) { gcx += gx; gcy += gy; gcz += gz; }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const float bz = T->obj0[j].cz, hx = T->obj0[j].hx, hy = T->obj0[j].hy, hz = T->obj0[j].hz;
+        const float dx = cx - mb.x[j], dy = cy - mb.y[j];
+        float pen, gx, gy, gz;
+        if (j != k && pair_pen(dx, dy, cz - bz, r, mb.c[j], mb.s[j], hx, hy, hz, lam, pen, gx, gy, gz)) {
+            pen_sum += pen;
+            if (GRAD) {
+                gcx += gx; gcy += gy; gcz += gz;
+                if (j < k) {
+                    // moving the box by d equals moving the sphere by -d; turning it
+                    // about its own vertical axis equals turning the sphere back.
+                    gr[j][0] -= gx;
+                    gr[j][1] -= gy;
+                    gr[j][2] -= dx * gy - dy * gx;
+                }
+            }
+        }
+    }
+}
+
+template <int SPLIT>
+__device__ __forceinline__ float split_sum(float v) {
+    if (SPLIT >= 2) v += __shfl_xor(v, 1);
+    if (SPLIT >= 4) v += __shfl_xor(v, 2);
+    return v;
+}
+
+__device__ __forceinline__ void cross3(const float a[3], const float b[3], float o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Robot spheres of link L (frame R, t), SPLIT lanes striding over them.
+template <int K, int SPLIT, bool GRAD>
+__device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L, int si, const float R[9],
+                                             const float t[3], const Movables<K>& mb, int k, float lam,
+                                             float& coll, float f[3], float tq[3], float (&gr)[K][3]) {
+    const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
+    for (int s = s0; s < s1; s += SPLIT) {
+        float4 sp = T->rs[s];
+        if (SPLIT > 1) {
+#pragma unroll
+            for (int u = 1; u < SPLIT; ++u) {
+                const float4 o = T->rs[min(s + u, s1 - 1)];
+                if (si == u) sp = o;
+            }
+        }
+        const float r = (s + si < s1) ? sp.w : 0.f;   // r = 0 never penetrates
+        const float cx = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + t[0];
+        const float cy = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + t[1];
+        const float cz = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
+        float pen = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, r, lam, pen, gx, gy, gz, gr);
+        coll += pen;
+        if (GRAD) {
+            f[0] += gx; f[1] += gy; f[2] += gz;
+            tq[0] += cy * gz - cz * gy;
+            tq[1] += cz * gx - cx * gz;
+            tq[2] += cx * gy - cy * gx;
+        }
+    }
+}
+
+// dist_from_bounds of v against [lo, hi] and its gradient (scaled by lam).
+template <int N>
+__device__ __forceinline__ float bounds_dist(const float v[N], const float* lo, const float* hi, float lam,
+                                             float g[N]) {
+    float m[N], ss = 0.f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float below = lo[j] - v[j], above = v[j] - hi[j];
+        const float e = fmaxf(fmaxf(below, above), 0.f);
+        m[j] = below > above ? -e : e;   // signed: d e / d v = -1 below, +1 above
+        ss += e * e;
+    }
+    const float dist = sqrtf(ss);
+    const float inv = dist > 0.f ? lam / dist : 0.f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) g[j] = m[j] * inv;
+    return dist;
+}
+
+struct LaneOut {
+    float cost;   // weighted sum of this slot's terms
+    int flags;    // bit 0: all of the slot's constraints hold; bit 1: finite
+};
+
+// ---------------------------------------------------------------------------
+// One slot of one particle: configuration q = q_grasp (even slot) or q_place
+// (odd slot) of step k, plus the terms owned by that slot.
+//   grasp slot: Kin at the pick, Grasp, joint limits of q_grasp, CFreeHold at
+//               q_grasp, CFreePlace of the object at its placement
+//   place slot: Kin at the place, StablePlace containment, joint limits of
+//               q_place, CFreeHold at q_place, the goal cost (slot 1 only)
+// Writes this lane's share of every gradient partial into part[0 .. NP).
+template <int K, int SPLIT, int MODE>
+__device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
+                                             int xs_stride, const float4* __restrict__ osl, int slot, int si,
+                                             float* __restrict__ part, float* __restrict__ terms,
+                                             int64_t term_ld, int64_t i_glob, bool write_terms) {
+    constexpr bool GRAD = MODE != MODE_COST;
+    constexpr int NP = 11 + 3 * K;
+    const int k = slot >> 1;
+    const bool placing = slot & 1;
+    auto X = [&](int d) { return xs[d * xs_stride]; };
+    const int b0 = CT_STEP_DIM * k;
+
+    const float gx = X(b0 + 14), gy = X(b0 + 15), gz = X(b0 + 16), gyaw = X(b0 + 17);
+    float g_s, g_c;
+    sincosf(gyaw, &g_s, &g_c);
+    const float rho_x = X(b0 + 18), rho_y = X(b0 + 19), rho_yaw = X(b0 + 20);
+    float rho_s, rho_c;
+    sincosf(rho_yaw, &rho_s, &rho_c);
+
+    Movables<K> mb;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        float sj, cj;
+        sincosf(X(CT_STEP_DIM * j + 20), &sj, &cj);
+        const bool placed = j < k;
+        mb.x[j] = placed ? X(CT_STEP_DIM * j + 18) : T->obj0[j].cx;
+        mb.y[j] = placed ? X(CT_STEP_DIM * j + 19) : T->obj0[j].cy;
+        mb.c[j] = placed ? cj : T->obj0[j].c;
+        mb.s[j] = placed ? sj : T->obj0[j].s;
+    }
+
+    float q[CT_N_JOINTS];
+#pragma unroll
+    for (int j = 0; j < CT_N_JOINTS; ++j) q[j] = X(b0 + (placing ? 7 : 0) + j);
+
+    const float lc = T->w[W_COLL];
+    float gq[CT_N_JOINTS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float gg[4] = {0.f, 0.f, 0.f, 0.f};
+    float gr[K][3];
+#pragma unroll
+    for (int j = 0; j < K; ++j) gr[j][0] = gr[j][1] = gr[j][2] = 0.f;
+    float coll = 0.f;
+
+    // ---- forward kinematics, link by link, with the spheres of each link
+    float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+    float t[3] = {0.f, 0.f, 0.f};
+    float az[CT_N_JOINTS][3], am[CT_N_JOINTS][3];
+#pragma unroll
+    for (int i = 0; i < CT_N_JOINTS; ++i) {
+        // joint i+1 turns about z of the previous frame through its origin
+        az[i][0] = R[2]; az[i][1] = R[5]; az[i][2] = R[8];
+        cross3(t, az[i], am[i]);
+        float sn, cs;
+        sincosf(q[i] + T->th0[i], &sn, &cs);
+        const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
+        const float lx = a * cs, ly = a * sn;
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr) {
+            const float r0 = R[3 * rr], r1 = R[3 * rr + 1], r2 = R[3 * rr + 2];
+            t[rr] += r0 * lx + r1 * ly + r2 * d;
+            const float w = r1 * cs - r0 * sn;
+            R[3 * rr] = r0 * cs + r1 * sn;
+            R[3 * rr + 1] = ca * w + r2 * sa;
+            R[3 * rr + 2] = r2 * ca - sa * w;
+        }
+        float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
+        link_spheres<K, SPLIT, GRAD>(T, i + 1, si, R, t, mb, k, lc, coll, f, tq, gr);
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                gq[j] += az[j][0] * tq[0] + az[j][1] * tq[1] + az[j][2] * tq[2] +
+                         am[j][0] * f[0] + am[j][1] * f[1] + am[j][2] * f[2];
+        }
+    }
+    // ---- tool frame: tool spheres, the held object, the kinematic constraint
+    const float te[3] = {t[0] + R[2] * T->tool_d, t[1] + R[5] * T->tool_d, t[2] + R[8] * T->tool_d};
+    float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
+    link_spheres<K, SPLIT, GRAD>(T, 8, si, R, te, mb, k, lc, coll, f, tq, gr);
+
+    // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
+    // rotation H = Rz(gyaw) Rx(pi) is symmetric and its own inverse.
+    const float H[9] = {g_c, g_s, 0.f, g_s, -g_c, 0.f, 0.f, 0.f, -1.f};
+    float RO[9];
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+            RO[3 * rr + cc] = R[3 * rr] * H[cc] + R[3 * rr + 1] * H[3 + cc] + R[3 * rr + 2] * H[6 + cc];
+    const float tO[3] = {te[0] - (RO[0] * gx + RO[1] * gy + RO[2] * gz),
+                         te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
+                         te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
+    {
+        float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
+        const int nos = T->n_os;
+        for (int m = si; m < nos; m += SPLIT) {
+            const float4 sp = osl[k * CT_MAX_OBJ_SPHERES + m];
+            const float cx = RO[0] * sp.x + RO[1] * sp.y + RO[2] * sp.z + tO[0];
+            const float cy = RO[3] * sp.x + RO[4] * sp.y + RO[5] * sp.z + tO[1];
+            const float cz = RO[6] * sp.x + RO[7] * sp.y + RO[8] * sp.z + tO[2];
+            float pen = 0.f, sgx = 0.f, sgy = 0.f, sgz = 0.f;
+            sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, sp.w, lc, pen, sgx, sgy, sgz, gr);
+            coll += pen;
+            if (GRAD) {
+                fo[0] += sgx; fo[1] += sgy; fo[2] += sgz;
+                to[0] += cy * sgz - cz * sgy;
+                to[1] += cz * sgx - cx * sgz;
+                to[2] += cx * sgy - cy * sgx;
+            }
+        }
+        if (GRAD) {
+            // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
+            // object turns about the tool z-axis through the tool origin.
+            gg[0] -= RO[0] * fo[0] + RO[3] * fo[1] + RO[6] * fo[2];
+            gg[1] -= RO[1] * fo[0] + RO[4] * fo[1] + RO[7] * fo[2];
+            gg[2] -= RO[2] * fo[0] + RO[5] * fo[1] + RO[8] * fo[2];
+            float txf[3];
+            cross3(te, fo, txf);
+            gg[3] += R[2] * (to[0] - txf[0]) + R[5] * (to[1] - txf[1]) + R[8] * (to[2] - txf[2]);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) { f[j] += fo[j]; tq[j] += to[j]; }
+        }
+    }
+
+    // kinematic constraint FK(q) = P G at the pick (P = initial pose) or the
+    // place (P = P(rho_k)): position and rotation error.
+    float kin_pos = 0.f, kin_rot = 0.f;
+    if (si == 0) {
+        float Px, Py, Pz, Pc, Ps;
+        if (placing) {
+            Px = rho_x; Py = rho_y; Pz = T->place_z[k]; Pc = rho_c; Ps = rho_s;
+        } else {
+            Px = T->obj0[k].cx; Py = T->obj0[k].cy; Pz = T->obj0[k].cz; Pc = T->obj0[k].c; Ps = T->obj0[k].s;
+        }
+        const float Rgx = Pc * gx - Ps * gy, Rgy = Ps * gx + Pc * gy;
+        const float ex = te[0] - (Px + Rgx), ey = te[1] - (Py + Rgy), ez = te[2] - (Pz + gz);
+        kin_pos = sqrtf(ex * ex + ey * ey + ez * ez);
+        const float cphi = Pc * g_c - Ps * g_s, sphi = Ps * g_c + Pc * g_s;
+        // R_err = R_ee^T R_t with R_t columns (cphi, sphi, 0), (sphi, -cphi, 0), (0, 0, -1)
+        const float E00 = R[0] * cphi + R[3] * sphi, E01 = R[0] * sphi - R[3] * cphi, E02 = -R[6];
+        const float E10 = R[1] * cphi + R[4] * sphi, E11 = R[1] * sphi - R[4] * cphi, E12 = -R[7];
+        const float E20 = R[2] * cphi + R[5] * sphi, E21 = R[2] * sphi - R[5] * cphi, E22 = -R[8];
+        const float w0 = 0.5f * (E21 - E12), w1 = 0.5f * (E02 - E20), w2 = 0.5f * (E10 - E01);
+        const float sw = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
+        kin_rot = atan2f(sw, 0.5f * (E00 + E11 + E22 - 1.f));
+        if (GRAD) {
+            const float lp = T->w[W_KPOS], lr = T->w[W_KROT];
+            if (kin_pos > 0.f) {
+                const float s = lp / kin_pos;
+                const float nx = ex * s, ny = ey * s, nz = ez * s;
+                f[0] += nx; f[1] += ny; f[2] += nz;
+                tq[0] += te[1] * nz - te[2] * ny;
+                tq[1] += te[2] * nx - te[0] * nz;
+                tq[2] += te[0] * ny - te[1] * nx;
+                // the target moves with the grasp offset (and the placement)
+                gg[0] -= Pc * nx + Ps * ny;
+                gg[1] -= -Ps * nx + Pc * ny;
+                gg[2] -= nz;
+                if (placing) {
+                    gr[k][0] -= nx;
+                    gr[k][1] -= ny;
+                    gr[k][2] -= -Rgy * nx + Rgx * ny;
+                }
+            }
+            if (sw > 0.f) {
+                const float inv = 1.f / sw;
+                const float u0 = w0 * inv, u1 = w1 * inv, u2 = w2 * inv;
+                const float uw0 = R[0] * u0 + R[1] * u1 + R[2] * u2;
+                const float uw1 = R[3] * u0 + R[4] * u1 + R[5] * u2;
+                const float uw2 = R[6] * u0 + R[7] * u1 + R[8] * u2;
+                // turning the tool by w lowers the angle by u_w . w; turning the
+                // target about world z raises it by u_w . z
+                tq[0] -= lr * uw0; tq[1] -= lr * uw1; tq[2] -= lr * uw2;
+                gg[3] += lr * uw2;
+                if (placing) gr[k][2] += lr * uw2;
+            }
+        }
+    }
+    if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < CT_N_JOINTS; ++j)
+            gq[j] += az[j][0] * tq[0] + az[j][1] * tq[1] + az[j][2] * tq[2] +
+                     am[j][0] * f[0] + am[j][1] * f[1] + am[j][2] * f[2];
+    }
+
+    // joint limits of this configuration
+    float jlim = 0.f;
+    if (si == 0) {
+        float gj[CT_N_JOINTS];
+        jlim = bounds_dist<CT_N_JOINTS>(q, T->q_lo, T->q_hi, T->w[W_JLIM], gj);
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] += gj[j];
+        }
+    }
+
+    float grasp = 0.f, coll_obj = 0.f, place = 0.f, goal = 0.f;
+    if (!placing) {
+        if (si == 0) {
+            const float gv[3] = {gx, gy, gz};
+            float gb[3];
+            grasp = bounds_dist<3>(gv, T->grasp_lo[k], T->grasp_hi[k], T->w[W_GRASP], gb);
+            if (GRAD) { gg[0] += gb[0]; gg[1] += gb[1]; gg[2] += gb[2]; }
+        }
+        // CFreePlace: the object's spheres at its placement P(rho_k)
+        const float pz = T->place_z[k];
+        const int nos = T->n_os;
+        for (int m = si; m < nos; m += SPLIT) {
+            const float4 sp = osl[k * CT_MAX_OBJ_SPHERES + m];
+            const float ox = rho_c * sp.x - rho_s * sp.y, oy = rho_s * sp.x + rho_c * sp.y;
+            const float cx = rho_x + ox, cy = rho_y + oy, cz = pz + sp.z;
+            float pen = 0.f, sgx = 0.f, sgy = 0.f, sgz = 0.f;
+            sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, sp.w, lc, pen, sgx, sgy, sgz, gr);
+            coll_obj += pen;
+            if (GRAD) {
+                gr[k][0] += sgx;
+                gr[k][1] += sgy;
+                gr[k][2] += ox * sgy - oy * sgx;
+            }
+        }
+    } else if (si == 0) {
+        // StablePlace containment: footprint corners inside the region
+        const float hx = T->obj0[k].hx, hy = T->obj0[k].hy, lpl = T->w[W_PLACE];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const float sx = (cc & 1) ? hx : -hx, sy = (cc & 2) ? hy : -hy;
+            const float vx = rho_c * sx - rho_s * sy, vy = rho_s * sx + rho_c * sy;
+            const float cv[2] = {rho_x + vx, rho_y + vy};
+            float gcr[2];
+            place += bounds_dist<2>(cv, T->region_lo, T->region_hi, lpl, gcr);
+            if (GRAD) {
+                gr[k][0] += gcr[0];
+                gr[k][1] += gcr[1];
+                gr[k][2] += -vy * gcr[0] + vx * gcr[1];
+            }
+        }
+        if (slot == 1 && T->goal) {
+            // MinimizeObjDist: sum of pairwise distances of the placements
+            const float lg = T->w[W_GOAL];
+#pragma unroll
+            for (int a = 0; a < K; ++a)
+#pragma unroll
+                for (int b = a + 1; b < K; ++b) {
+                    const float dx = X(CT_STEP_DIM * a + 18) - X(CT_STEP_DIM * b + 18);
+                    const float dy = X(CT_STEP_DIM * a + 19) - X(CT_STEP_DIM * b + 19);
+                    const float dz = T->place_z[a] - T->place_z[b];
+                    const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+                    goal += dist;
+                    if (GRAD && dist > 0.f) {
+                        const float s = lg / dist;
+                        gr[a][0] += dx * s; gr[a][1] += dy * s;
+                        gr[b][0] -= dx * s; gr[b][1] -= dy * s;
+                    }
+                }
+        }
+    }
+
+    // ---- combine the SPLIT lanes of this slot
+    coll = split_sum<SPLIT>(coll);
+    coll_obj = split_sum<SPLIT>(coll_obj);
+    if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = split_sum<SPLIT>(gq[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gg[j] = split_sum<SPLIT>(gg[j]);
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) gr[j][c] = split_sum<SPLIT>(gr[j][c]);
+    }
+
+    LaneOut out;
+    const float* w = T->w;
+    const float* e = T->eps;
+    float gsum = 0.f;
+    if (si == 0) {
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j < CT_N_JOINTS; ++j) { part[j] = gq[j]; gsum += gq[j]; }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { part[11 + 3 * j + c] = gr[j][c]; gsum += gr[j][c]; }
+        }
+        (void)NP;
+    }
+    const float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll;
+    bool ok = kin_pos <= e[E_KPOS] && kin_rot <= e[E_KROT] && jlim <= e[E_JLIM] && coll <= e[E_COLL];
+    if (!placing) {
+        out.cost = kw + w[W_GRASP] * grasp + w[W_COLL] * coll_obj;
+        ok = ok && grasp <= e[E_GRASP] && coll_obj <= e[E_COLL];
+    } else {
+        out.cost = kw + w[W_PLACE] * place + w[W_GOAL] * goal;
+        ok = ok && place <= e[E_PLACE];
+    }
+    const bool fin = __builtin_isfinite(out.cost + gsum);
+    out.flags = (ok ? 1 : 0) | (fin ? 2 : 0);
+
+    if (write_terms && si == 0) {
+        const int tb = CT_TERMS_PER_STEP * k;
+        auto put = [&](int idx, float v) { terms[(int64_t)idx * term_ld + i_glob] = v; };
+        if (!placing) {
+            put(tb + T_PICK_POS, kin_pos);
+            put(tb + T_PICK_ROT, kin_rot);
+            put(tb + T_GRASP, grasp);
+            put(tb + T_JLIM_G, jlim);
+            put(tb + T_COLL_G, coll);
+            put(tb + T_COLL_OBJ, coll_obj);
+        } else {
+            put(tb + T_PLACE_POS, kin_pos);
+            put(tb + T_PLACE_ROT, kin_rot);
+            put(tb + T_PLACE, place);
+            put(tb + T_JLIM_P, jlim);
+            put(tb + T_COLL_P, coll);
+            if (slot == 1 && T->goal) put(T->goal_term, goal);
+        }
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+template <int K, int SPLIT, int MODE>
+__global__ __launch_bounds__(WG) void particle_kernel(
+    const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
+    float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
+    int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
+    float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
+    int32_t* __restrict__ t_out) {
+    constexpr int SLOTS = 2 * K;
+    constexpr int LPP = SLOTS * SPLIT;
+    constexpr int P = WG / LPP;
+    constexpr int D = CT_STEP_DIM * K;
+    constexpr int NP = 11 + 3 * K;
+
+    __shared__ float xs[D * P];
+    __shared__ float part[P * SLOTS * NP];
+    __shared__ float cpart[P * SLOTS];
+    __shared__ int flg[P * SLOTS];
+    __shared__ int okp[P];
+    __shared__ float4 osl[K * CT_MAX_OBJ_SPHERES];
+    __shared__ int any_sat;
+
+    const int tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * P;
+    // update number t: explicit, or one past the device counter of applied
+    // updates; a captured loop alternates two counter slots (read t_in,
+    // write t_out), so no launch writes a slot that its own workgroups read
+    const int32_t t = t_in ? *t_in + 1 : t_arg;
+    const int32_t iter = t - 1;
+    if (t_out && blockIdx.x == 0 && threadIdx.x == 0) *t_out = t;
+
+    // phase 0: stage this workgroup's particles (coalesced along particles)
+    for (int idx = tid; idx < D * P; idx += WG) {
+        const int d = idx / P, p = idx - d * P;
+        const int64_t i = p0 + p;
+        xs[idx] = i < n ? X[d * ld + i] : 0.f;
+    }
+    for (int idx = tid; idx < K * CT_MAX_OBJ_SPHERES; idx += WG) osl[idx] = T->os[idx / CT_MAX_OBJ_SPHERES][idx % CT_MAX_OBJ_SPHERES];
+    if (tid == 0) any_sat = 0;
+    __syncthreads();
+
+    // phase 1: every lane evaluates its slot
+    {
+        const int p = tid / LPP;
+        if (p < P) {
+            const int rem = tid - p * LPP;
+            const int slot = rem / SPLIT, si = rem - slot * SPLIT;
+            const int64_t i = p0 + p;
+            const bool wt = (MODE == MODE_COST) && terms != nullptr && i < n;
+            const LaneOut o = lane_slot<K, SPLIT, MODE>(T, xs + p, P, osl, slot, si,
+                                                        part + (p * SLOTS + slot) * NP, terms, ld, i, wt);
+            if (si == 0) {
+                cpart[p * SLOTS + slot] = o.cost;
+                flg[p * SLOTS + slot] = o.flags;
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase 1.5: per-particle cost, mask, update permission
+    if (tid < P) {
+        const int64_t i = p0 + tid;
+        float J = 0.f;
+        int m = 1, ok = 1;
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            J += cpart[tid * SLOTS + s];
+            m &= flg[tid * SLOTS + s] & 1;
+            ok &= (flg[tid * SLOTS + s] >> 1) & 1;
+        }
+        ok &= __builtin_isfinite(J) ? 1 : 0;
+        m &= __builtin_isfinite(J) ? 1 : 0;
+        okp[tid] = ok;
+        if (i < n) {
+            if (cost) cost[i] = J;
+            if (mask) mask[i] = (uint8_t)m;
+            if (m) any_sat = 1;
+        }
+    }
+    __syncthreads();
+    if (first_sat && tid == 0 && any_sat) atomicMin(first_sat, iter);
+
+    if (MODE == MODE_COST) return;
+
+    // phase 2: sum each coordinate's partials (fixed order), then G or Adam
+    for (int idx = tid; idx < D * P; idx += WG) {
+        const int d = idx / P, p = idx - d * P;
+        const int64_t i = p0 + p;
+        if (i >= n) continue;
+        const int k = d / CT_STEP_DIM, r = d - CT_STEP_DIM * k;
+        const float* pp = part + p * SLOTS * NP;
+        float g;
+        if (r < 7) {
+            g = pp[(2 * k) * NP + r];
+        } else if (r < 14) {
+            g = pp[(2 * k + 1) * NP + (r - 7)];
+        } else if (r < 18) {
+            g = pp[(2 * k) * NP + 7 + (r - 14)] + pp[(2 * k + 1) * NP + 7 + (r - 14)];
+        } else {
+            g = 0.f;
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) g += pp[s * NP + 11 + 3 * k + (r - 18)];
+        }
+        const int64_t a = d * ld + i;
+        if (MODE == MODE_GRAD) {
+            G[a] = g;
+        } else if (okp[p] && !(frozen && frozen[d])) {
+            const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+            const float gs = gscale * g;
+            const float m1 = b1 * M[a] + (1.f - b1) * gs;
+            const float v1 = b2 * V[a] + (1.f - b2) * gs * gs;
+            const float mh = m1 / bc1, vh = v1 / bc2;
+            X[a] = xs[idx] - lr * mh / (sqrtf(vh) + eps);
+            M[a] = m1;
+            V[a] = v1;
+        }
+    }
+}
+
+}  // namespace ct

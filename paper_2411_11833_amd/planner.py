@@ -1,0 +1,165 @@
+"""Torch-facing wrapper over the C ABI: PyTorch supplies device memory and
+the stream; every step of the particle path runs in the HIP library.
+
+* ``GpuProblem`` owns a problem handle and allocates particle buffers in the
+  library's dimension-major layout (``[dim, ld]``, ld a multiple of 64).
+* ``plain_solve`` is the paper's Optimization baseline (Sec. VII): uniform
+  initialization within bounds, then Adam on the batch-mean cost of Eq. (4),
+  stopping at the first satisfying particle (Sec. IV-B) or at the budget.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import torch
+
+from . import binding as B
+from . import inputs as I
+
+
+def padded(n: int) -> int:
+    return max(64, ((n + 63) // 64) * 64)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+class GpuProblem:
+    """A created problem handle plus buffer helpers."""
+
+    def __init__(self, prob: I.Problem, device: str | torch.device = "cuda"):
+        self.prob = prob
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.handle = B.ct_problem_create(prob)
+        self.dim, self.n_terms, self.n_constraint = B.ct_problem_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.ct_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- buffers
+    def empty(self, n: int, rows: int | None = None) -> torch.Tensor:
+        return torch.zeros((rows or self.dim, padded(n)), dtype=torch.float32, device=self.device)
+
+    def from_rows(self, x_rows) -> torch.Tensor:
+        """[n, dim] host/device rows -> [dim, ld] device SoA buffer."""
+        x = torch.as_tensor(x_rows, dtype=torch.float32)
+        out = self.empty(x.shape[0])
+        out[:, : x.shape[0]] = x.T.to(self.device)
+        return out
+
+    @staticmethod
+    def to_rows(buf: torch.Tensor, n: int) -> torch.Tensor:
+        return buf[:, :n].T.contiguous()
+
+    # ---- calls (argument marshalling only)
+    def seed_uniform(self, seed: int, X, M=None, V=None, n: int | None = None):
+        n = X.shape[1] if n is None else n
+        B.ct_seed_uniform(self.handle, seed, X.data_ptr(), M.data_ptr() if M is not None else None,
+                          V.data_ptr() if V is not None else None, n, X.shape[1], _stream())
+
+    def cost(self, X, n: int, terms: bool = False, mask: bool = True):
+        c = torch.empty(n, dtype=torch.float32, device=self.device)
+        T = self.empty(n, rows=self.n_terms) if terms else None
+        m = torch.empty(n, dtype=torch.uint8, device=self.device) if mask else None
+        B.ct_cost(self.handle, X.data_ptr(), n, X.shape[1], c.data_ptr(), T.data_ptr() if T is not None else None,
+                  m.data_ptr() if m is not None else None, _stream())
+        return c, T, m
+
+    def cost_grad(self, X, n: int):
+        c = torch.empty(n, dtype=torch.float32, device=self.device)
+        G = self.empty(n)
+        B.ct_cost_grad(self.handle, X.data_ptr(), n, X.shape[1], c.data_ptr(), G.data_ptr(), _stream())
+        return c, G
+
+    def adam_apply(self, X, M, V, G, n: int, t: int, adam: B.CtAdam, frozen=None):
+        B.ct_adam_apply(self.handle, X.data_ptr(), M.data_ptr(), V.data_ptr(), G.data_ptr(), n, X.shape[1], t,
+                        adam, frozen.data_ptr() if frozen is not None else None, _stream())
+
+    def step(self, X, M, V, n: int, t: int, adam: B.CtAdam, frozen=None, cost=None, mask=None, first_sat=None):
+        ptr = lambda a: a.data_ptr() if a is not None else None  # noqa: E731
+        B.ct_step(self.handle, X.data_ptr(), M.data_ptr(), V.data_ptr(), n, X.shape[1], t, adam, ptr(frozen),
+                  ptr(cost), ptr(mask), ptr(first_sat), _stream())
+
+    def optimize(self, X, M, V, n: int, t0: int, iters: int, adam: B.CtAdam, frozen=None, cost=None, mask=None,
+                 first_sat=None):
+        ptr = lambda a: a.data_ptr() if a is not None else None  # noqa: E731
+        B.ct_optimize(self.handle, X.data_ptr(), M.data_ptr(), V.data_ptr(), n, X.shape[1], t0, iters, adam,
+                      ptr(frozen), ptr(cost), ptr(mask), ptr(first_sat), _stream())
+
+    def set_split(self, split: int):
+        B.ct_set_split(self.handle, split)
+
+    def get_split(self) -> int:
+        return B.ct_get_split(self.handle)
+
+    def autotune(self, X, n: int) -> int:
+        return B.ct_autotune(self.handle, X.data_ptr(), n, X.shape[1], _stream())
+
+
+def grasp_frozen(prob: I.Problem, device="cuda") -> torch.Tensor:
+    """Frozen-dimension mask that fixes every step's grasp (gx, gy, gz, gyaw)
+    after initialization: the paper samples grasps and keeps them fixed while
+    placements and configurations are optimized (Sec. VII, Experimental
+    Setup)."""
+    f = torch.zeros(prob.dim, dtype=torch.uint8)
+    for k in range(prob.skeleton.n_steps):
+        f[I.STEP_DIM * k + 14:I.STEP_DIM * k + 18] = 1
+    return f.to(device)
+
+
+def default_adam(n: int, lr: float = 1e-2) -> B.CtAdam:
+    """lr 1e-2, betas (0.9, 0.999), eps 1e-8, gradient scaled by 1/N_b (Eq. 4)."""
+    return B.CtAdam(lr, 0.9, 0.999, 1e-8, 1.0 / n)
+
+
+@dataclass
+class SolveResult:
+    iters_run: int
+    first_sat_iter: int | None      # optimizer iterations before the first satisfying particle
+    time_to_first_s: float | None   # wall clock from the start of initialization
+    wall_s: float
+    n_satisfied: int                # satisfying particles at the last evaluated iterate
+
+
+INT32_MAX = 2 ** 31 - 1
+
+
+def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, check_every: int = 10, stop_at_first: bool = True,
+                adam: B.CtAdam | None = None, X=None, fixed_grasps: bool = True) -> SolveResult:
+    """Uniform seeds + Adam, checking the device's first-satisfied flag every
+    `check_every` iterations (each chunk is one captured graph replay).
+    With fixed_grasps the grasp coordinates keep their initial draw."""
+    adam = adam or default_adam(n)
+    frozen = grasp_frozen(gp.prob, gp.device) if fixed_grasps else None
+    X = gp.empty(n) if X is None else X
+    M, V = gp.empty(n), gp.empty(n)
+    cost = torch.empty(n, dtype=torch.float32, device=gp.device)
+    mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
+    flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=gp.device)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    gp.seed_uniform(seed, X, M, V, n)
+    done, t_first, it_first = 0, None, None
+    while done < iters:
+        chunk = min(check_every, iters - done)
+        gp.optimize(X, M, V, n, done, chunk, adam, frozen=frozen, cost=cost, mask=mask, first_sat=flag)
+        done += chunk
+        f = int(flag.item())         # synchronizes the stream
+        if f != INT32_MAX and t_first is None:
+            t_first, it_first = time.perf_counter() - t_start, f
+            if stop_at_first:
+                break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    return SolveResult(done, it_first, t_first, wall, int(mask.sum().item()))

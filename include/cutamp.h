@@ -226,14 +226,20 @@ int ct_step(const ct_problem *problem, float *X, float *M, float *V, int64_t n, 
 
 /*
  * `iters` fused steps with updates t0+1 .. t0+iters, launched as one HIP
- * graph (captured on first use for this argument set and cached in the
- * handle; a call with different arguments re-captures).  cost / mask hold the
- * values of the last step; first_sat as in ct_step.  The first call for an
- * argument set may allocate graph resources; later identical calls do not.
+ * graph.  The graph is captured on first use for an argument set (t0 is not
+ * part of it: the update number comes from a device counter the call sets
+ * before launching) and cached in the handle; a call with other arguments
+ * re-captures, which may allocate graph resources.  cost / mask hold the
+ * values of the last executed step; first_sat as in ct_step.  With
+ * stop_at_first != 0 (first_sat required), a step whose predecessors already
+ * produced a satisfying particle does nothing, so a whole iteration budget
+ * can be enqueued at once and still stops at the first solution
+ * (Sec. IV-B, stopping criterion).
  */
 int ct_optimize(ct_problem *problem, float *X, float *M, float *V, int64_t n, int64_t ld,
                 int64_t t0, int32_t iters, const ct_adam *adam, const uint8_t *frozen,
-                float *cost, uint8_t *mask, int32_t *first_sat, void *stream);
+                float *cost, uint8_t *mask, int32_t *first_sat, int32_t stop_at_first,
+                void *stream);
 
 /*
  * Kernel shape: split = how many lanes share one particle configuration's

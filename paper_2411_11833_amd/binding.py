@@ -15,7 +15,7 @@ import numpy as np
 
 from . import inputs as I
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcutamp.so")
+LIB_PATH = os.environ.get("CUTAMP_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcutamp.so")
 
 CT_OK, CT_ERR_INVALID_ARG, CT_ERR_UNSUPPORTED, CT_ERR_ALLOC, CT_ERR_DEVICE = range(5)
 
@@ -75,7 +75,7 @@ def _load() -> C.CDLL:
         "ct_cost_grad": (C.c_int, [vp, vp, i64, i64, vp, vp, vp]),
         "ct_adam_apply": (C.c_int, [vp, vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp]),
         "ct_step": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp, vp, vp, vp]),
-        "ct_optimize": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, i32, C.POINTER(CtAdam), vp, vp, vp, vp, vp]),
+        "ct_optimize": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, i32, C.POINTER(CtAdam), vp, vp, vp, vp, i32, vp]),
         "ct_set_split": (C.c_int, [vp, i32]),
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
@@ -172,9 +172,9 @@ def ct_step(h, X, M, V, n, ld, t, adam: CtAdam, frozen=None, cost=None, mask=Non
 
 
 def ct_optimize(h, X, M, V, n, ld, t0, iters, adam: CtAdam, frozen=None, cost=None, mask=None,
-                first_sat=None, stream=0):
-    _chk(LIB.ct_optimize(h, X, M, V, n, ld, t0, iters, C.byref(adam), frozen, cost, mask, first_sat, stream),
-         "ct_optimize")
+                first_sat=None, stop_at_first=0, stream=0):
+    _chk(LIB.ct_optimize(h, X, M, V, n, ld, t0, iters, C.byref(adam), frozen, cost, mask, first_sat,
+                         int(stop_at_first), stream), "ct_optimize")
 
 
 def ct_set_split(h, split: int):

@@ -45,23 +45,27 @@ def _run(cmd, verbose):
     return res
 
 
-def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None) -> str:
+def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None,
+          out: str | None = None, objdir: str | None = None) -> str:
     """Compile every HIP source and link the in-tree shared library (always
-    recompiles).  Returns the library path."""
-    os.makedirs(OBJ, exist_ok=True)
+    recompiles).  `extra` adds hipcc flags (e.g. -DCT_RUN=1); `out` / `objdir`
+    redirect the library and objects.  Returns the library path."""
+    lib = out or LIB
+    obj_dir = objdir or OBJ
+    os.makedirs(obj_dir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(OBJ, "cutamp.o"), [])]
+    units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(obj_dir, "cutamp.o"), [])]
     for k in range(1, MAX_K + 1):
-        units.append((os.path.join(CSRC, "pk_instances.hip"), os.path.join(OBJ, f"pk_k{k}.o"), [f"-DCT_K={k}"]))
+        units.append((os.path.join(CSRC, "pk_instances.hip"), os.path.join(obj_dir, f"pk_k{k}.o"), [f"-DCT_K={k}"]))
     cmds = [[hipcc(), *HIPCC_FLAGS, *(extra or []), *inc, *defs, "-c", src, "-o", obj]
             for src, obj, defs in units]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda c: _run(c, verbose), cmds))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[u[1] for u in units]], verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

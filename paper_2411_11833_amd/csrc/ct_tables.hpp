@@ -24,6 +24,13 @@ struct Box {
     float cx, cy, cz, c, s, hx, hy, hz;
 };
 
+// A box that never moves, stored for the point-in-box-frame transform
+// p = R^T (x - t) = (c x + s y + u0, c y - s x + u1, z - tz) with
+// u0 = -(c tx + s ty), u1 = s tx - c ty (two FMAs per horizontal axis).
+struct SBox {
+    float c, s, u0, u1, tz, hx, hy, hz;
+};
+
 // weight slots
 enum { W_KPOS, W_KROT, W_GRASP, W_PLACE, W_JLIM, W_COLL, W_GOAL, W_TRAJ, W_MCOLL, W_N };
 // tolerance slots
@@ -55,7 +62,7 @@ struct Tables {
     float eps[E_N];
     float region_lo[2], region_hi[2];
     float4 rs[CT_MAX_ROBOT_SPHERES];           // (x, y, z, r) in the parent frame, grouped by link
-    Box sbox[CT_MAX_STATIC_BOXES];
+    SBox sbox[CT_MAX_STATIC_BOXES];
     Box obj0[CT_MAX_STEPS];                    // moved object of step k at its initial pose
     float p0_yaw[CT_MAX_STEPS];                // its initial yaw
     float place_z[CT_MAX_STEPS];               // centre height when placed on the table

@@ -23,12 +23,12 @@ struct GraphKey {
     int32_t* first_sat = nullptr;
     const uint8_t* frozen = nullptr;
     int64_t n = -1, ld = -1;
-    int32_t iters = -1, split = -1;
+    int32_t iters = -1, split = -1, stop = -1;
     float lr = 0, b1 = 0, b2 = 0, eps = 0, gs = 0;
     bool operator==(const GraphKey& o) const {
         return X == o.X && M == o.M && V == o.V && cost == o.cost && mask == o.mask &&
                first_sat == o.first_sat && frozen == o.frozen && n == o.n && ld == o.ld &&
-               iters == o.iters && split == o.split && lr == o.lr && b1 == o.b1 && b2 == o.b2 &&
+               iters == o.iters && split == o.split && stop == o.stop && lr == o.lr && b1 == o.b1 && b2 == o.b2 &&
                eps == o.eps && gs == o.gs;
     }
 };
@@ -55,6 +55,20 @@ bool valid_box(const double* b) {
     for (int i = 0; i < 7; ++i)
         if (!is_fin(b[i])) return false;
     return b[4] > 0 && b[5] > 0 && b[6] > 0;
+}
+
+ct::SBox to_sbox(const double* b) {
+    const double c = std::cos(b[3]), s = std::sin(b[3]);
+    ct::SBox o;
+    o.c = (float)c;
+    o.s = (float)s;
+    o.u0 = (float)(-(c * b[0] + s * b[1]));
+    o.u1 = (float)(s * b[0] - c * b[1]);
+    o.tz = (float)b[2];
+    o.hx = (float)b[4];
+    o.hy = (float)b[5];
+    o.hz = (float)b[6];
+    return o;
 }
 
 ct::Box to_box(const double* b) {
@@ -256,10 +270,10 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
     T.link_start[9] = cnt;
     // boxes that never move
     int nb = 0;
-    T.sbox[nb++] = to_box(scene->table);
-    for (int b = 0; b < scene->n_obstacles; ++b) T.sbox[nb++] = to_box(scene->obstacles + 7 * b);
+    T.sbox[nb++] = to_sbox(scene->table);
+    for (int b = 0; b < scene->n_obstacles; ++b) T.sbox[nb++] = to_sbox(scene->obstacles + 7 * b);
     for (int o = 0; o < scene->n_objects; ++o)
-        if (!used[o]) T.sbox[nb++] = to_box(scene->objects + 7 * o);
+        if (!used[o]) T.sbox[nb++] = to_sbox(scene->objects + 7 * o);
     T.n_static = nb;
     const double table_top = scene->table[2] + scene->table[6];
     for (int k = 0; k < K; ++k) {
@@ -399,7 +413,8 @@ extern "C" int ct_adam_apply(const ct_problem* P, float* X, float* M, float* V, 
 namespace {
 int step_impl(const ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld, int64_t t,
               const ct_adam* adam, const uint8_t* frozen, float* cost, uint8_t* mask, int32_t* first_sat,
-              hipStream_t st, int split, const int32_t* t_in = nullptr, int32_t* t_out = nullptr) {
+              hipStream_t st, int split, const int32_t* t_in = nullptr, int32_t* t_out = nullptr,
+              int32_t stop_at_first = 0) {
     PkArgs a{};
     a.X = X;
     a.M = M;
@@ -414,6 +429,7 @@ int step_impl(const ct_problem* P, float* X, float* M, float* V, int64_t n, int6
     a.t = (int32_t)t;
     a.t_in = t_in;
     a.t_out = t_out;
+    a.stop_at_first = stop_at_first;
     return run_pk(P, ct::MODE_STEP, a, st, split);
 }
 
@@ -434,15 +450,17 @@ extern "C" int ct_step(const ct_problem* P, float* X, float* M, float* V, int64_
 
 extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t n, int64_t ld, int64_t t0,
                            int32_t iters, const ct_adam* adam, const uint8_t* frozen, float* cost, uint8_t* mask,
-                           int32_t* first_sat, void* stream) {
+                           int32_t* first_sat, int32_t stop_at_first, void* stream) {
     if (empty_ok(P, n, ld) && t0 >= 0 && iters >= 0) return CT_OK;
     if (!valid_step_args(P, X, M, V, n, ld, adam) || t0 < 0 || iters < 0 || t0 + iters > INT32_MAX)
         return CT_ERR_INVALID_ARG;
+    if (stop_at_first && !first_sat) return CT_ERR_INVALID_ARG;
     if (n == 0 || iters == 0) return CT_OK;
     GraphKey key;
     key.X = X; key.M = M; key.V = V; key.cost = cost; key.mask = mask; key.first_sat = first_sat;
     key.frozen = frozen; key.n = n; key.ld = ld; key.iters = iters;
     key.split = effective_split(P);
+    key.stop = stop_at_first ? 1 : 0;
     key.lr = adam->lr; key.b1 = adam->beta1; key.b2 = adam->beta2; key.eps = adam->eps;
     key.gs = adam->grad_scale;
     if (!(P->gexec && P->key == key)) {
@@ -456,7 +474,7 @@ extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t 
         int rc = CT_OK;
         for (int32_t it = 0; it < iters && rc == CT_OK; ++it) {
             rc = step_impl(P, X, M, V, n, ld, 0, adam, frozen, cost, mask, first_sat, P->capture_stream, key.split,
-                           P->t_dev + (it & 1), P->t_dev + ((it + 1) & 1));
+                           P->t_dev + (it & 1), P->t_dev + ((it + 1) & 1), key.stop);
         }
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->capture_stream, &g);

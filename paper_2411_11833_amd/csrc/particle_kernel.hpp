@@ -31,24 +31,27 @@ namespace ct {
 
 __device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// Penetration max(0, r - sdf) of a sphere into a yaw-only box.
-// (dx, dy, dz) = sphere centre minus box centre (world frame), (c, s) the
-// box yaw's cos / sin, h the half extents.  In the box frame p = R^T d,
-// u = |p| - h, sdf = ||max(u, 0)|| + min(max_i u_i, 0)  (App. "Collision
-// Representation": spheres against oriented boxes).  Returns false when the
-// sphere does not penetrate; otherwise pen = r - sdf > 0 and lam * d pen / d
-// centre (world frame) in (gx, gy, gz).
+// Squared distance from a point to a box, given the point in the box frame
+// (p) and the half extents: ||max(|p| - h, 0)||^2, zero inside the box.
+__device__ __forceinline__ float box_d2(float px, float py, float pz, float hx, float hy, float hz) {
+    const float mx = fmaxf(fabsf(px) - hx, 0.f);
+    const float my = fmaxf(fabsf(py) - hy, 0.f);
+    const float mz = fmaxf(fabsf(pz) - hz, 0.f);
+    return mx * mx + my * my + mz * mz;
+}
+
+// Penetration of a sphere that touches the box (its squared outside distance
+// is below r^2), from the centre p in the box frame: pen = r - sdf with
+// sdf = ||max(u, 0)|| + min(max_i u_i, 0), u = |p| - h (App. "Collision
+// Representation": spheres against oriented boxes), and lam * d pen / d
+// centre in world coordinates (box yaw cos c, sin s).
 // Tie conventions: sign(0) = +1; among equal interior depths the lowest axis.
-__device__ __forceinline__ bool pair_pen(float dx, float dy, float dz, float r, float c, float s,
-                                         float hx, float hy, float hz, float lam, float& pen,
-                                         float& gx, float& gy, float& gz) {
-    const float px = c * dx + s * dy;
-    const float py = c * dy - s * dx;
-    const float pz = dz;
+__device__ __forceinline__ void pair_hit(float px, float py, float pz, float r, float c, float s, float hx,
+                                         float hy, float hz, float lam, float& pen, float& gx, float& gy,
+                                         float& gz) {
     const float ux = fabsf(px) - hx, uy = fabsf(py) - hy, uz = fabsf(pz) - hz;
     const float mx = fmaxf(ux, 0.f), my = fmaxf(uy, 0.f), mz = fmaxf(uz, 0.f);
     const float d2 = mx * mx + my * my + mz * mz;
-    if (!(d2 < r * r)) return false;
     float sdf, ax, ay, az;  // sdf and d sdf / d p
     if (d2 > 0.f) {
         const float inv = fast_rsq(d2);
@@ -73,7 +76,6 @@ __device__ __forceinline__ bool pair_pen(float dx, float dy, float dz, float r, 
     gx = -lam * (c * ax - s * ay);
     gy = -lam * (s * ax + c * ay);
     gz = -lam * az;
-    return true;
 }
 
 // Poses of the moved objects as seen by one lane's step: placed by an earlier
@@ -83,44 +85,100 @@ struct Movables {
     float x[K], y[K], c[K], s[K];
 };
 
-// One sphere against every box of step k: static boxes (uniform, scalar
-// loads) and the other moved objects (per lane).  Accumulates the unweighted
-// penetration, the weighted centre gradient, and the weighted gradient with
-// respect to the placements rho_j of boxes placed by earlier steps.
-template <int K, bool GRAD>
-__device__ __forceinline__ void sphere_vs_world(const Tables* __restrict__ T, const Movables<K>& mb,
-                                                int k, float cx, float cy, float cz, float r, float lam,
-                                                float& pen_sum, float& gcx, float& gcy, float& gcz,
-                                                float (&gr)[K][3]) {
+// A run of NB spheres of one lane against every box of step k: static boxes
+// (uniform, one scalar load per box for the whole run) and the other moved
+// objects (per lane).  The NB distance tests are independent dependency
+// chains; the penetration branch runs only when some lane's sphere touches
+// the box.  Accumulates the unweighted penetration, each sphere's weighted
+// centre gradient, and the weighted gradient with respect to the placements
+// rho_j of boxes placed by earlier steps.
+template <int K, int NB, bool GRAD>
+__device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const Movables<K>& mb, int k,
+                                             const float (&cx)[NB], const float (&cy)[NB], const float (&cz)[NB],
+                                             const float (&r)[NB], float lam, float& pen_sum, float (&gx)[NB],
+                                             float (&gy)[NB], float (&gz)[NB], float (&gr)[K][3]) {
+    float r2[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) r2[m] = r[m] * r[m];
     const int nsb = T->n_static;
     for (int b = 0; b < nsb; ++b) {
-        const Box B = T->sbox[b];
-        float pen, gx, gy, gz;
-        if (pair_pen(cx - B.cx, cy - B.cy, cz - B.cz, r, B.c, B.s, B.hx, B.hy, B.hz, lam, pen, gx, gy, gz)) {
-            pen_sum += pen;
-            if (GRAD) { gcx += gx; gcy += gy; gcz += gz; }
+        const SBox B = T->sbox[b];
+        bool act[NB];
+        bool any = false;
+        float px[NB], py[NB], pz[NB];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            px[m] = fmaf(B.c, cx[m], fmaf(B.s, cy[m], B.u0));
+            py[m] = fmaf(B.c, cy[m], fmaf(-B.s, cx[m], B.u1));
+            pz[m] = cz[m] - B.tz;
+            act[m] = box_d2(px[m], py[m], pz[m], B.hx, B.hy, B.hz) < r2[m];
+            any |= act[m];
+        }
+        if (any) {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                if (act[m]) {
+                    float pen, ax, ay, az;
+                    pair_hit(px[m], py[m], pz[m], r[m], B.c, B.s, B.hx, B.hy, B.hz, lam, pen, ax, ay, az);
+                    pen_sum += pen;
+                    if (GRAD) { gx[m] += ax; gy[m] += ay; gz[m] += az; }
+                }
+            }
         }
     }
 #pragma unroll
     for (int j = 0; j < K; ++j) {
         const float bz = T->obj0[j].cz, hx = T->obj0[j].hx, hy = T->obj0[j].hy, hz = T->obj0[j].hz;
-        const float dx = cx - mb.x[j], dy = cy - mb.y[j];
-        float pen, gx, gy, gz;
-        if (j != k && pair_pen(dx, dy, cz - bz, r, mb.c[j], mb.s[j], hx, hy, hz, lam, pen, gx, gy, gz)) {
-            pen_sum += pen;
-            if (GRAD) {
-                gcx += gx; gcy += gy; gcz += gz;
-                if (j < k) {
-                    // moving the box by d equals moving the sphere by -d; turning it
-                    // about its own vertical axis equals turning the sphere back.
-                    gr[j][0] -= gx;
-                    gr[j][1] -= gy;
-                    gr[j][2] -= dx * gy - dy * gx;
+        const bool on = j != k;   // the step's own object is held, not an obstacle
+        bool act[NB];
+        bool any = false;
+        float dx[NB], dy[NB], px[NB], py[NB], pz[NB];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            dx[m] = cx[m] - mb.x[j];
+            dy[m] = cy[m] - mb.y[j];
+            px[m] = mb.c[j] * dx[m] + mb.s[j] * dy[m];
+            py[m] = mb.c[j] * dy[m] - mb.s[j] * dx[m];
+            pz[m] = cz[m] - bz;
+            act[m] = on && box_d2(px[m], py[m], pz[m], hx, hy, hz) < r2[m];
+            any |= act[m];
+        }
+        if (any) {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                if (act[m]) {
+                    float pen, ax, ay, az;
+                    pair_hit(px[m], py[m], pz[m], r[m], mb.c[j], mb.s[j], hx, hy, hz, lam, pen, ax, ay, az);
+                    pen_sum += pen;
+                    if (GRAD) {
+                        gx[m] += ax; gy[m] += ay; gz[m] += az;
+                        if (j < k) {
+                            // moving the box by d equals moving the sphere by -d; turning it
+                            // about its own vertical axis equals turning the sphere back
+                            gr[j][0] -= ax;
+                            gr[j][1] -= ay;
+                            gr[j][2] -= dx[m] * ay - dy[m] * ax;
+                        }
+                    }
                 }
             }
         }
     }
 }
+
+// Bijection from the launch index to a tile index that keeps each XCD's
+// workgroups (b = x, x + 8, x + 16, ...) on a contiguous tile range.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
+    constexpr int NX = 8;
+    const int64_t x = b % NX, q = G / NX, rem = G % NX;
+    return x * q + (x < rem ? x : rem) + b / NX;
+}
+
+// spheres tested together against each box (independent dependency chains)
+#ifndef CT_RUN
+#define CT_RUN 2
+#endif
+constexpr int RUN = CT_RUN;
 
 template <int SPLIT>
 __device__ __forceinline__ float split_sum(float v) {
@@ -135,35 +193,101 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-// Robot spheres of link L (frame R, t), SPLIT lanes striding over them.
+// NB consecutive robot spheres of one lane on a link with frame (R, t):
+// lane si of a slot takes table entries s0 + si + SPLIT j, j = j0 .. j0+NB-1
+// (entries past the link's end get radius 0, which never penetrates).
+// Accumulates the link's wrench (force f, moment tq about the world origin).
+template <int K, int SPLIT, int NB, bool GRAD>
+__device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, int s1, int j0, int si,
+                                          const float R[9], const float t[3], const Movables<K>& mb, int k,
+                                          float lam, float& coll, float f[3], float tq[3], float (&gr)[K][3]) {
+    float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const int base = s0 + SPLIT * (j0 + m);   // uniform
+        float4 sp = T->rs[min(base, s1 - 1)];
+        if (SPLIT > 1) {
+#pragma unroll
+            for (int u = 1; u < SPLIT; ++u) {
+                const float4 o = T->rs[min(base + u, s1 - 1)];
+                if (si == u) sp = o;
+            }
+        }
+        rr[m] = (base + si < s1) ? sp.w : 0.f;
+        cx[m] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + t[0];
+        cy[m] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + t[1];
+        cz[m] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
+        gx[m] = gy[m] = gz[m] = 0.f;
+    }
+    float pen = 0.f;
+    run_vs_world<K, NB, GRAD>(T, mb, k, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    coll += pen;
+    if (GRAD) {
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            f[0] += gx[m]; f[1] += gy[m]; f[2] += gz[m];
+            tq[0] += cy[m] * gz[m] - cz[m] * gy[m];
+            tq[1] += cz[m] * gx[m] - cx[m] * gz[m];
+            tq[2] += cx[m] * gy[m] - cy[m] * gx[m];
+        }
+    }
+}
+
+// All robot spheres of link L: runs of 2, then 1, over the (wave-uniform)
+// number of entries each lane of the slot handles.
 template <int K, int SPLIT, bool GRAD>
 __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L, int si, const float R[9],
                                              const float t[3], const Movables<K>& mb, int k, float lam,
                                              float& coll, float f[3], float tq[3], float (&gr)[K][3]) {
     const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
-    for (int s = s0; s < s1; s += SPLIT) {
-        float4 sp = T->rs[s];
-        if (SPLIT > 1) {
+    const int per_lane = (s1 - s0 + SPLIT - 1) / SPLIT;
+    int j = 0;
+    for (; j + RUN <= per_lane; j += RUN) robot_run<K, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mb, k, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j) robot_run<K, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mb, k, lam, coll, f, tq, gr);
+}
+
+// Runs of object spheres (table osl, object frame) transformed by (R, t):
+// lane si takes entries si + SPLIT j.  Returns the penetration sum; with GRAD
+// accumulates the force and the moment about the world origin.
+template <int K, int SPLIT, int NB, bool GRAD>
+__device__ __forceinline__ void object_run(const Tables* __restrict__ T, const float4* __restrict__ osl, int nos,
+                                           int j0, int si, const float R[9], const float t[3],
+                                           const Movables<K>& mb, int k, float lam, float& coll, float f[3],
+                                           float tq[3], float (&gr)[K][3]) {
+    float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
-            for (int u = 1; u < SPLIT; ++u) {
-                const float4 o = T->rs[min(s + u, s1 - 1)];
-                if (si == u) sp = o;
-            }
-        }
-        const float r = (s + si < s1) ? sp.w : 0.f;   // r = 0 never penetrates
-        const float cx = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + t[0];
-        const float cy = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + t[1];
-        const float cz = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
-        float pen = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
-        sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, r, lam, pen, gx, gy, gz, gr);
-        coll += pen;
-        if (GRAD) {
-            f[0] += gx; f[1] += gy; f[2] += gz;
-            tq[0] += cy * gz - cz * gy;
-            tq[1] += cz * gx - cx * gz;
-            tq[2] += cx * gy - cy * gx;
+    for (int m = 0; m < NB; ++m) {
+        const int e = si + SPLIT * (j0 + m);
+        const float4 sp = osl[min(e, nos - 1)];
+        rr[m] = e < nos ? sp.w : 0.f;
+        cx[m] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + t[0];
+        cy[m] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + t[1];
+        cz[m] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
+        gx[m] = gy[m] = gz[m] = 0.f;
+    }
+    float pen = 0.f;
+    run_vs_world<K, NB, GRAD>(T, mb, k, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    coll += pen;
+    if (GRAD) {
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            f[0] += gx[m]; f[1] += gy[m]; f[2] += gz[m];
+            tq[0] += cy[m] * gz[m] - cz[m] * gy[m];
+            tq[1] += cz[m] * gx[m] - cx[m] * gz[m];
+            tq[2] += cx[m] * gy[m] - cy[m] * gx[m];
         }
     }
+}
+
+template <int K, int SPLIT, bool GRAD>
+__device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const float4* __restrict__ osl,
+                                               int nos, int si, const float R[9], const float t[3],
+                                               const Movables<K>& mb, int k, float lam, float& coll, float f[3],
+                                               float tq[3], float (&gr)[K][3]) {
+    const int per_lane = (nos + SPLIT - 1) / SPLIT;
+    int j = 0;
+    for (; j + RUN <= per_lane; j += RUN) object_run<K, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mb, k, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j) object_run<K, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mb, k, lam, coll, f, tq, gr);
 }
 
 // dist_from_bounds of v against [lo, hi] and its gradient (scaled by lam).
@@ -291,22 +415,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
                          te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
     {
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        const int nos = T->n_os;
-        for (int m = si; m < nos; m += SPLIT) {
-            const float4 sp = osl[k * CT_MAX_OBJ_SPHERES + m];
-            const float cx = RO[0] * sp.x + RO[1] * sp.y + RO[2] * sp.z + tO[0];
-            const float cy = RO[3] * sp.x + RO[4] * sp.y + RO[5] * sp.z + tO[1];
-            const float cz = RO[6] * sp.x + RO[7] * sp.y + RO[8] * sp.z + tO[2];
-            float pen = 0.f, sgx = 0.f, sgy = 0.f, sgz = 0.f;
-            sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, sp.w, lc, pen, sgx, sgy, sgz, gr);
-            coll += pen;
-            if (GRAD) {
-                fo[0] += sgx; fo[1] += sgy; fo[2] += sgz;
-                to[0] += cy * sgz - cz * sgy;
-                to[1] += cz * sgx - cx * sgz;
-                to[2] += cx * sgy - cy * sgx;
-            }
-        }
+        object_spheres<K, SPLIT, GRAD>(T, osl + k * CT_MAX_OBJ_SPHERES, T->n_os, si, RO, tO, mb, k, lc, coll, fo,
+                                       to, gr);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
             // object turns about the tool z-axis through the tool origin.
@@ -401,21 +511,19 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             grasp = bounds_dist<3>(gv, T->grasp_lo[k], T->grasp_hi[k], T->w[W_GRASP], gb);
             if (GRAD) { gg[0] += gb[0]; gg[1] += gb[1]; gg[2] += gb[2]; }
         }
-        // CFreePlace: the object's spheres at its placement P(rho_k)
-        const float pz = T->place_z[k];
-        const int nos = T->n_os;
-        for (int m = si; m < nos; m += SPLIT) {
-            const float4 sp = osl[k * CT_MAX_OBJ_SPHERES + m];
-            const float ox = rho_c * sp.x - rho_s * sp.y, oy = rho_s * sp.x + rho_c * sp.y;
-            const float cx = rho_x + ox, cy = rho_y + oy, cz = pz + sp.z;
-            float pen = 0.f, sgx = 0.f, sgy = 0.f, sgz = 0.f;
-            sphere_vs_world<K, GRAD>(T, mb, k, cx, cy, cz, sp.w, lc, pen, sgx, sgy, sgz, gr);
-            coll_obj += pen;
-            if (GRAD) {
-                gr[k][0] += sgx;
-                gr[k][1] += sgy;
-                gr[k][2] += ox * sgy - oy * sgx;
-            }
+        // CFreePlace: the object's spheres at its placement P(rho_k); the
+        // object frame's force and moment give the placement gradient
+        const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
+        const float tp[3] = {rho_x, rho_y, T->place_z[k]};
+        float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
+        object_spheres<K, SPLIT, GRAD>(T, osl + k * CT_MAX_OBJ_SPHERES, T->n_os, si, Rp, tp, mb, k, lc, coll_obj,
+                                       fp, mp, gr);
+        if (GRAD) {
+            // translation: the force; turning about the vertical through the
+            // placement origin: z of the moment about that point
+            gr[k][0] += fp[0];
+            gr[k][1] += fp[1];
+            gr[k][2] += mp[2] - (tp[0] * fp[1] - tp[1] * fp[0]);
         }
     } else if (si == 0) {
         // StablePlace containment: footprint corners inside the region
@@ -526,7 +634,7 @@ __global__ __launch_bounds__(WG) void particle_kernel(
     float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
     int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
     float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
-    int32_t* __restrict__ t_out) {
+    int32_t* __restrict__ t_out, int32_t stop_at_first) {
     constexpr int SLOTS = 2 * K;
     constexpr int LPP = SLOTS * SPLIT;
     constexpr int P = WG / LPP;
@@ -542,13 +650,21 @@ __global__ __launch_bounds__(WG) void particle_kernel(
     __shared__ int any_sat;
 
     const int tid = threadIdx.x;
-    const int64_t p0 = (int64_t)blockIdx.x * P;
+    // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
+    // 8 XCDs, so give each XCD a contiguous range of particle tiles; tiles
+    // that share cache lines of X, M and V then share one L2
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t p0 = tile * P;
     // update number t: explicit, or one past the device counter of applied
     // updates; a captured loop alternates two counter slots (read t_in,
     // write t_out), so no launch writes a slot that its own workgroups read
     const int32_t t = t_in ? *t_in + 1 : t_arg;
     const int32_t iter = t - 1;
     if (t_out && blockIdx.x == 0 && threadIdx.x == 0) *t_out = t;
+    // stop-at-first: once an earlier iteration produced a satisfying
+    // particle, the remaining steps of a captured loop do nothing (every
+    // workgroup reads the same value: this launch only writes iter itself)
+    if (stop_at_first && first_sat && *first_sat < iter) return;
 
     // phase 0: stage this workgroup's particles (coalesced along particles)
     for (int idx = tid; idx < D * P; idx += WG) {

@@ -20,6 +20,7 @@ struct PkArgs {
     int32_t t;               // update number, used when t_in is null
     const int32_t* t_in;     // device counter of applied updates (t = *t_in + 1), or null
     int32_t* t_out;          // receives t (the other counter slot), or null
+    int32_t stop_at_first;   // skip the step if an earlier iteration satisfied
 };
 
 using PkFn = hipError_t (*)(const ct::Tables*, const PkArgs&, hipStream_t);

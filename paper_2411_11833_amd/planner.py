@@ -92,10 +92,10 @@ class GpuProblem:
                   ptr(cost), ptr(mask), ptr(first_sat), _stream())
 
     def optimize(self, X, M, V, n: int, t0: int, iters: int, adam: B.CtAdam, frozen=None, cost=None, mask=None,
-                 first_sat=None):
+                 first_sat=None, stop_at_first: bool = False):
         ptr = lambda a: a.data_ptr() if a is not None else None  # noqa: E731
         B.ct_optimize(self.handle, X.data_ptr(), M.data_ptr(), V.data_ptr(), n, X.shape[1], t0, iters, adam,
-                      ptr(frozen), ptr(cost), ptr(mask), ptr(first_sat), _stream())
+                      ptr(frozen), ptr(cost), ptr(mask), ptr(first_sat), int(stop_at_first), _stream())
 
     def set_split(self, split: int):
         B.ct_set_split(self.handle, split)
@@ -125,21 +125,25 @@ def default_adam(n: int, lr: float = 1e-2) -> B.CtAdam:
 
 @dataclass
 class SolveResult:
-    iters_run: int
+    iters_budget: int
     first_sat_iter: int | None      # optimizer iterations before the first satisfying particle
-    time_to_first_s: float | None   # wall clock from the start of initialization
-    wall_s: float
-    n_satisfied: int                # satisfying particles at the last evaluated iterate
+    time_to_first_s: float | None   # GPU time from the start of initialization to the end of the
+                                    # chunk of iterations that produced the first satisfying particle
+    wall_s: float                   # host wall clock of the whole call
+    n_satisfied: int                # satisfying particles at the last executed iterate
 
 
 INT32_MAX = 2 ** 31 - 1
 
 
-def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, check_every: int = 10, stop_at_first: bool = True,
+def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, stop_at_first: bool = True,
                 adam: B.CtAdam | None = None, X=None, fixed_grasps: bool = True) -> SolveResult:
-    """Uniform seeds + Adam, checking the device's first-satisfied flag every
-    `check_every` iterations (each chunk is one captured graph replay).
-    With fixed_grasps the grasp coordinates keep their initial draw."""
+    """The plain method: uniform seeds, then Adam until the first satisfying
+    particle or the iteration budget.  The whole budget is enqueued at once as
+    replays of one captured `chunk`-step graph with a GPU event after each;
+    with stop_at_first the device skips every step after the first satisfying
+    iteration, so no host polling is needed.  Time to first = GPU time to the
+    end of the chunk holding that iteration."""
     adam = adam or default_adam(n)
     frozen = grasp_frozen(gp.prob, gp.device) if fixed_grasps else None
     X = gp.empty(n) if X is None else X
@@ -147,19 +151,26 @@ def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, check_every: int 
     cost = torch.empty(n, dtype=torch.float32, device=gp.device)
     mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
     flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=gp.device)
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    t_start = time.perf_counter()
+    t_wall = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
     gp.seed_uniform(seed, X, M, V, n)
-    done, t_first, it_first = 0, None, None
+    events = []
+    done = 0
     while done < iters:
-        chunk = min(check_every, iters - done)
-        gp.optimize(X, M, V, n, done, chunk, adam, frozen=frozen, cost=cost, mask=mask, first_sat=flag)
-        done += chunk
-        f = int(flag.item())         # synchronizes the stream
-        if f != INT32_MAX and t_first is None:
-            t_first, it_first = time.perf_counter() - t_start, f
-            if stop_at_first:
-                break
+        c = min(chunk, iters - done)
+        gp.optimize(X, M, V, n, done, c, adam, frozen=frozen, cost=cost, mask=mask, first_sat=flag,
+                    stop_at_first=stop_at_first)
+        done += c
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        events.append(e)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    return SolveResult(done, it_first, t_first, wall, int(mask.sum().item()))
+    wall = time.perf_counter() - t_wall
+    f = int(flag.item())
+    if f == INT32_MAX:
+        return SolveResult(iters, None, None, wall, int(mask.sum().item()))
+    ttf = start.elapsed_time(events[min(f // chunk, len(events) - 1)]) / 1e3
+    return SolveResult(iters, f, ttf, wall, int(mask.sum().item()))

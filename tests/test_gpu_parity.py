@@ -311,3 +311,27 @@ def test_first_satisfying_iteration_matches_masks():
     torch.cuda.synchronize()
     f = int(flag.item())
     assert f == (first if first is not None else 2 ** 31 - 1)
+
+
+def test_stop_at_first_freezes_the_batch():
+    """With stop_at_first the steps after the first satisfying iteration do
+    nothing: the state equals an eager run stopped right after that step."""
+    from paper_2411_11833_amd.planner import grasp_frozen
+    prob = CASES["single"]()
+    gp = _gp(prob)
+    n = 256
+    fz = grasp_frozen(prob)
+    X0, M0, V0 = gp.empty(n), gp.empty(n), gp.empty(n)
+    gp.seed_uniform(1000, X0, M0, V0, n)
+    flag = torch.full((1,), 2 ** 31 - 1, dtype=torch.int32, device="cuda")
+    X, M, V = X0.clone(), M0.clone(), V0.clone()
+    for c in range(300):
+        gp.optimize(X, M, V, n, 10 * c, 10, _adam(n), frozen=fz, first_sat=flag, stop_at_first=True)
+    torch.cuda.synchronize()
+    f = int(flag.item())
+    assert f < 3000, "no satisfying particle within the budget"
+    Xe, Me, Ve = X0.clone(), M0.clone(), V0.clone()
+    for t in range(1, f + 2):
+        gp.step(Xe, Me, Ve, n, t, _adam(n), frozen=fz)
+    torch.cuda.synchronize()
+    assert torch.equal(X, Xe) and torch.equal(M, Me) and torch.equal(V, Ve)

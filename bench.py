@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--robot-seed", type=int, default=0)
     ap.add_argument("--split", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-motion", action="store_true", help="skip the waypoint motion-cost measurement")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
@@ -180,6 +181,51 @@ def main():
         log(f"[bench] single pick-place (256 particles) time-to-first seed {seed}: {r.time_to_first_s} s "
             f"at iteration {r.first_sat_iter}", q)
 
+    # ---- motion cost: 16 interpolated waypoints per transition, 16384 particles
+    motion = None
+    if not args.no_motion:
+        mprob = I.packing(robot_seed=args.robot_seed, scene_seed=args.scene_seed, waypoints=16)
+        mg = GpuProblem(mprob, dev)
+        nm = 16384
+        Xm, Mm, Vm = mg.empty(nm), mg.empty(nm), mg.empty(nm)
+        mg.seed_uniform(31, Xm, Mm, Vm, nm)
+        msplit = mg.autotune(Xm, nm)
+        from paper_2411_11833_amd.planner import particle_cost
+        Xg = Xm.clone().requires_grad_(True)
+        for _ in range(2):
+            particle_cost(mg, Xg, nm).sum().backward()
+        torch.cuda.synchronize()
+        reps_m = 10
+        e0.record(stream)
+        for _ in range(reps_m):
+            Xg.grad = None
+            particle_cost(mg, Xg, nm).sum().backward()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fb_s = e0.elapsed_time(e1) / 1e3 / reps_m
+        mfz = grasp_frozen(mprob, dev)
+        madam = default_adam(nm)
+        e0.record(stream)
+        for t in range(1, reps_m + 1):
+            mg.step(Xm, Mm, Vm, nm, t, madam, frozen=mfz)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st_s = e0.elapsed_time(e1) / 1e3 / reps_m
+        mwk = workmodel.per_particle_iteration(mprob)
+        motion = {
+            "workload": "4-object packing + motion cost: 16 interior waypoints per transition (136 "
+                        "configurations per particle), 16384 particles",
+            "split": msplit,
+            "fwd_bwd_particle_iters_per_s": nm / fb_s,
+            "fwd_bwd_ms": fb_s * 1e3,
+            "step_particle_iters_per_s": nm / st_s,
+            "step_kernel_ms": st_s * 1e3,
+            "flop_per_particle_iter": mwk.flops,
+            "step_tflops_model": mwk.flops * nm / st_s / 1e12,
+        }
+        log(f"[bench] motion: fwd+bwd {nm / fb_s:.4g} particle-iters/s, fused step {st_s * 1e3:.2f} ms "
+            f"({mwk.flops * nm / st_s / 1e12:.1f} TFLOP/s model)", q)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -208,6 +254,7 @@ def main():
         },
         "first_sat_iter_full_run": None if first_iter_full == INT32_MAX else first_iter_full,
         "satisfied_after_full_run": sat_end,
+        "motion": motion,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

@@ -195,10 +195,15 @@ int ct_cost(const ct_problem *problem, const float *X, int64_t n, int64_t ld, fl
 
 /*
  * Cost and its gradient dJ/dx per particle (not scaled by 1/N_b):
- * G [dim][ld].  cost may be NULL.
+ * G [dim][ld].  With weights (device [n], may be NULL) column i of G is
+ * weights[i] * dJ/dx_i -- the vector-Jacobian product a reverse-mode caller
+ * needs (weights = the incoming gradient of the per-particle costs).  The
+ * gradient pass recomputes every configuration it needs, including the
+ * motion cost's interpolated waypoints; nothing is saved between calls.
+ * cost may be NULL.
  */
 int ct_cost_grad(const ct_problem *problem, const float *X, int64_t n, int64_t ld, float *cost,
-                 float *G, void *stream);
+                 float *G, const float *weights, void *stream);
 
 /*
  * Adam update number t (t >= 1, 1-based, bias-corrected) using the

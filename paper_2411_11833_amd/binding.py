@@ -72,7 +72,7 @@ def _load() -> C.CDLL:
         "ct_problem_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "ct_seed_uniform": (C.c_int, [vp, u64, vp, vp, vp, i64, i64, vp]),
         "ct_cost": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp]),
-        "ct_cost_grad": (C.c_int, [vp, vp, i64, i64, vp, vp, vp]),
+        "ct_cost_grad": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp]),
         "ct_adam_apply": (C.c_int, [vp, vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp]),
         "ct_step": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp, vp, vp, vp]),
         "ct_optimize": (C.c_int, [vp, vp, vp, vp, i64, i64, i64, i32, C.POINTER(CtAdam), vp, vp, vp, vp, i32, vp]),
@@ -155,8 +155,8 @@ def ct_cost(h, X, n, ld, cost, terms=None, mask=None, stream=0):
     _chk(LIB.ct_cost(h, X, n, ld, cost, terms, mask, stream), "ct_cost")
 
 
-def ct_cost_grad(h, X, n, ld, cost, G, stream=0):
-    _chk(LIB.ct_cost_grad(h, X, n, ld, cost, G, stream), "ct_cost_grad")
+def ct_cost_grad(h, X, n, ld, cost, G, weights=None, stream=0):
+    _chk(LIB.ct_cost_grad(h, X, n, ld, cost, G, weights, stream), "ct_cost_grad")
 
 
 def _adam(lr, beta1, beta2, eps, grad_scale):

@@ -209,7 +209,12 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
     if (!sk->object_of_step || !sk->grasp_lo || !sk->grasp_hi) return CT_ERR_INVALID_ARG;
     if (sk->goal_cost != 0 && sk->goal_cost != 1) return CT_ERR_INVALID_ARG;
     if (sk->waypoints < 0) return CT_ERR_INVALID_ARG;
-    if (sk->waypoints > 0) return CT_ERR_UNSUPPORTED;   // the motion cost has its own entry points
+    if (sk->waypoints > CT_MAX_WAYPOINTS) return CT_ERR_UNSUPPORTED;
+    if (sk->waypoints > 0) {
+        if (!sk->q0) return CT_ERR_INVALID_ARG;
+        for (int j = 0; j < CT_N_JOINTS; ++j)
+            if (!is_fin(sk->q0[j])) return CT_ERR_INVALID_ARG;
+    }
     std::vector<int> used(scene->n_objects, 0);
     for (int k = 0; k < K; ++k) {
         const int o = sk->object_of_step[k];
@@ -384,13 +389,14 @@ extern "C" int ct_cost(const ct_problem* P, const float* X, int64_t n, int64_t l
 }
 
 extern "C" int ct_cost_grad(const ct_problem* P, const float* X, int64_t n, int64_t ld, float* cost, float* G,
-                            void* stream) {
+                            const float* weights, void* stream) {
     if (empty_ok(P, n, ld)) return CT_OK;
     if (!P || !X || !G || !good_layout(X, n, ld) || !good_layout(G, n, ld)) return CT_ERR_INVALID_ARG;
     PkArgs a{};
     a.X = const_cast<float*>(X);
     a.G = G;
     a.cost = cost;
+    a.gw = weights;
     a.n = n;
     a.ld = ld;
     return run_pk(P, ct::MODE_GRAD, a, (hipStream_t)stream);

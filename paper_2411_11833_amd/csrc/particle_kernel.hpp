@@ -311,71 +311,47 @@ __device__ __forceinline__ float bounds_dist(const float v[N], const float* lo, 
 
 struct LaneOut {
     float cost;   // weighted sum of this slot's terms
+    float traj;   // this slot's transition length (TrajLength share), 0 without motion
     int flags;    // bit 0: all of the slot's constraints hold; bit 1: finite
 };
 
-// ---------------------------------------------------------------------------
-// One slot of one particle: configuration q = q_grasp (even slot) or q_place
-// (odd slot) of step k, plus the terms owned by that slot.
-//   grasp slot: Kin at the pick, Grasp, joint limits of q_grasp, CFreeHold at
-//               q_grasp, CFreePlace of the object at its placement
-//   place slot: Kin at the place, StablePlace containment, joint limits of
-//               q_place, CFreeHold at q_place, the goal cost (slot 1 only)
-// Writes this lane's share of every gradient partial into part[0 .. NP).
-template <int K, int SPLIT, int MODE>
-__device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
-                                             int xs_stride, const float4* __restrict__ osl, int slot, int si,
-                                             float* __restrict__ part, float* __restrict__ terms,
-                                             int64_t term_ld, int64_t i_glob, bool write_terms) {
-    constexpr bool GRAD = MODE != MODE_COST;
-    constexpr int NP = 11 + 3 * K;
-    const int k = slot >> 1;
-    const bool placing = slot & 1;
-    auto X = [&](int d) { return xs[d * xs_stride]; };
-    const int b0 = CT_STEP_DIM * k;
-
-    const float gx = X(b0 + 14), gy = X(b0 + 15), gz = X(b0 + 16), gyaw = X(b0 + 17);
-    float g_s, g_c;
-    sincosf(gyaw, &g_s, &g_c);
-    const float rho_x = X(b0 + 18), rho_y = X(b0 + 19), rho_yaw = X(b0 + 20);
-    float rho_s, rho_c;
-    sincosf(rho_yaw, &rho_s, &rho_c);
-
-    Movables<K> mb;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        float sj, cj;
-        sincosf(X(CT_STEP_DIM * j + 20), &sj, &cj);
-        const bool placed = j < k;
-        mb.x[j] = placed ? X(CT_STEP_DIM * j + 18) : T->obj0[j].cx;
-        mb.y[j] = placed ? X(CT_STEP_DIM * j + 19) : T->obj0[j].cy;
-        mb.c[j] = placed ? cj : T->obj0[j].c;
-        mb.s[j] = placed ? sj : T->obj0[j].s;
-    }
-
-    float q[CT_N_JOINTS];
-#pragma unroll
-    for (int j = 0; j < CT_N_JOINTS; ++j) q[j] = X(b0 + (placing ? 7 : 0) + j);
-
-    const float lc = T->w[W_COLL];
-    float gq[CT_N_JOINTS] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    float gg[4] = {0.f, 0.f, 0.f, 0.f};
-    float gr[K][3];
-#pragma unroll
-    for (int j = 0; j < K; ++j) gr[j][0] = gr[j][1] = gr[j][2] = 0.f;
-    float coll = 0.f;
-
-    // ---- forward kinematics, link by link, with the spheres of each link
+// The per-configuration part of a slot's work: forward kinematics link by
+// link with each link's robot spheres, the held object (optional) and the
+// kinematic constraint (optional).  Accumulates the penetration sum `coll`,
+// dJ/dq of this configuration into gq (folded onto the joint axes from
+// world-frame wrenches: dJ/dq_j = z_j . tau + (o_j x z_j) . f for the wrench
+// of everything beyond joint j), and the grasp / placement partials gg, gr.
+template <int K, int SPLIT, bool GRAD>
+__device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const float4* __restrict__ osl_k, int k,
+                                            int si, const float q[CT_N_JOINTS], bool held, bool kin, bool placing,
+                                            float lam, const Movables<K>& mb, float gx, float gy, float gz,
+                                            float g_c, float g_s, float rho_x, float rho_y, float rho_c,
+                                            float rho_s, float& coll, float gq[CT_N_JOINTS], float gg[4],
+                                            float (&gr)[K][3], float& kin_pos, float& kin_rot) {
+    // Joint axis S_j = (z_j, o_j x z_j) of joint j+1 (z of frame j through its
+    // origin).  dJ/dq_j = <S_j, wrench of links j+1..8>
+    //                   = <S_j, total wrench> - <S_j, wrench of links 1..j>;
+    // the second product (c_j) is taken on the way out, when S_j is formed
+    // and links 1..j are done; the first after the tip, by a second sweep
+    // over the chain that re-forms the axes from the stored joint sines and
+    // cosines.  (Cancellation is bounded: an element that matters is >= 1%
+    // of the largest, and the subtracted products are of that size.)
     float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
     float t[3] = {0.f, 0.f, 0.f};
-    float az[CT_N_JOINTS][3], am[CT_N_JOINTS][3];
-#pragma unroll
+    float jsn[CT_N_JOINTS], jcs[CT_N_JOINTS], cj[CT_N_JOINTS];
+    float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};   // wrench of the links done so far
+#pragma unroll 1
     for (int i = 0; i < CT_N_JOINTS; ++i) {
-        // joint i+1 turns about z of the previous frame through its origin
-        az[i][0] = R[2]; az[i][1] = R[5]; az[i][2] = R[8];
-        cross3(t, az[i], am[i]);
+        if (GRAD) {
+            const float z[3] = {R[2], R[5], R[8]};
+            float m[3];
+            cross3(t, z, m);
+            cj[i] = z[0] * tq[0] + z[1] * tq[1] + z[2] * tq[2] + m[0] * f[0] + m[1] * f[1] + m[2] * f[2];
+        }
         float sn, cs;
         sincosf(q[i] + T->th0[i], &sn, &cs);
+        jsn[i] = sn;
+        jcs[i] = cs;
         const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
         const float lx = a * cs, ly = a * sn;
 #pragma unroll
@@ -387,39 +363,30 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             R[3 * rr + 1] = ca * w + r2 * sa;
             R[3 * rr + 2] = r2 * ca - sa * w;
         }
-        float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
-        link_spheres<K, SPLIT, GRAD>(T, i + 1, si, R, t, mb, k, lc, coll, f, tq, gr);
-        if (GRAD) {
-#pragma unroll
-            for (int j = 0; j <= i; ++j)
-                gq[j] += az[j][0] * tq[0] + az[j][1] * tq[1] + az[j][2] * tq[2] +
-                         am[j][0] * f[0] + am[j][1] * f[1] + am[j][2] * f[2];
-        }
+        link_spheres<K, SPLIT, GRAD>(T, i + 1, si, R, t, mb, k, lam, coll, f, tq, gr);
     }
     // ---- tool frame: tool spheres, the held object, the kinematic constraint
     const float te[3] = {t[0] + R[2] * T->tool_d, t[1] + R[5] * T->tool_d, t[2] + R[8] * T->tool_d};
-    float f[3] = {0.f, 0.f, 0.f}, tq[3] = {0.f, 0.f, 0.f};
-    link_spheres<K, SPLIT, GRAD>(T, 8, si, R, te, mb, k, lc, coll, f, tq, gr);
+    link_spheres<K, SPLIT, GRAD>(T, 8, si, R, te, mb, k, lam, coll, f, tq, gr);
 
-    // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
-    // rotation H = Rz(gyaw) Rx(pi) is symmetric and its own inverse.
-    const float H[9] = {g_c, g_s, 0.f, g_s, -g_c, 0.f, 0.f, 0.f, -1.f};
-    float RO[9];
+    if (held) {
+        // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
+        // rotation H = Rz(gyaw) Rx(pi) is symmetric and its own inverse
+        const float H[9] = {g_c, g_s, 0.f, g_s, -g_c, 0.f, 0.f, 0.f, -1.f};
+        float RO[9];
 #pragma unroll
-    for (int rr = 0; rr < 3; ++rr)
+        for (int rr = 0; rr < 3; ++rr)
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc)
-            RO[3 * rr + cc] = R[3 * rr] * H[cc] + R[3 * rr + 1] * H[3 + cc] + R[3 * rr + 2] * H[6 + cc];
-    const float tO[3] = {te[0] - (RO[0] * gx + RO[1] * gy + RO[2] * gz),
-                         te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
-                         te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
-    {
+            for (int cc = 0; cc < 3; ++cc)
+                RO[3 * rr + cc] = R[3 * rr] * H[cc] + R[3 * rr + 1] * H[3 + cc] + R[3 * rr + 2] * H[6 + cc];
+        const float tO[3] = {te[0] - (RO[0] * gx + RO[1] * gy + RO[2] * gz),
+                             te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
+                             te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        object_spheres<K, SPLIT, GRAD>(T, osl + k * CT_MAX_OBJ_SPHERES, T->n_os, si, RO, tO, mb, k, lc, coll, fo,
-                                       to, gr);
+        object_spheres<K, SPLIT, GRAD>(T, osl_k, T->n_os, si, RO, tO, mb, k, lam, coll, fo, to, gr);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
-            // object turns about the tool z-axis through the tool origin.
+            // object turns about the tool z-axis through the tool origin
             gg[0] -= RO[0] * fo[0] + RO[3] * fo[1] + RO[6] * fo[2];
             gg[1] -= RO[1] * fo[0] + RO[4] * fo[1] + RO[7] * fo[2];
             gg[2] -= RO[2] * fo[0] + RO[5] * fo[1] + RO[8] * fo[2];
@@ -432,9 +399,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     }
 
     // kinematic constraint FK(q) = P G at the pick (P = initial pose) or the
-    // place (P = P(rho_k)): position and rotation error.
-    float kin_pos = 0.f, kin_rot = 0.f;
-    if (si == 0) {
+    // place (P = P(rho_k)): position and rotation error
+    if (kin && si == 0) {
         float Px, Py, Pz, Pc, Ps;
         if (placing) {
             Px = rho_x; Py = rho_y; Pz = T->place_z[k]; Pc = rho_c; Ps = rho_s;
@@ -455,8 +421,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         if (GRAD) {
             const float lp = T->w[W_KPOS], lr = T->w[W_KROT];
             if (kin_pos > 0.f) {
-                const float s = lp / kin_pos;
-                const float nx = ex * s, ny = ey * s, nz = ez * s;
+                const float sc = lp / kin_pos;
+                const float nx = ex * sc, ny = ey * sc, nz = ez * sc;
                 f[0] += nx; f[1] += ny; f[2] += nz;
                 tq[0] += te[1] * nz - te[2] * ny;
                 tq[1] += te[2] * nx - te[0] * nz;
@@ -486,24 +452,159 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         }
     }
     if (GRAD) {
+        // second sweep: re-form each axis and take it against the total wrench
+        float Q[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        float o[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < CT_N_JOINTS; ++j)
-            gq[j] += az[j][0] * tq[0] + az[j][1] * tq[1] + az[j][2] * tq[2] +
-                     am[j][0] * f[0] + am[j][1] * f[1] + am[j][2] * f[2];
+        for (int i = 0; i < CT_N_JOINTS; ++i) {
+            const float z[3] = {Q[2], Q[5], Q[8]};
+            float m[3];
+            cross3(o, z, m);
+            gq[i] += z[0] * tq[0] + z[1] * tq[1] + z[2] * tq[2] + m[0] * f[0] + m[1] * f[1] + m[2] * f[2] - cj[i];
+            if (i + 1 < CT_N_JOINTS) {
+                const float sn = jsn[i], cs = jcs[i];
+                const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
+                const float lx = a * cs, ly = a * sn;
+#pragma unroll
+                for (int rr = 0; rr < 3; ++rr) {
+                    const float r0 = Q[3 * rr], r1 = Q[3 * rr + 1], r2 = Q[3 * rr + 2];
+                    o[rr] += r0 * lx + r1 * ly + r2 * d;
+                    const float w = r1 * cs - r0 * sn;
+                    Q[3 * rr] = r0 * cs + r1 * sn;
+                    Q[3 * rr + 1] = ca * w + r2 * sa;
+                    Q[3 * rr + 2] = r2 * ca - sa * w;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One slot of one particle.  Slot 2k owns q_grasp of step k and the free
+// transition into it (from q_place of step k-1, or q0); slot 2k+1 owns
+// q_place of step k and the holding transition q_grasp -> q_place.  Terms:
+//   grasp slot: Kin at the pick, Grasp, joint limits of q_grasp, CFreeHold at
+//               q_grasp, CFreePlace of the object at its placement
+//   place slot: Kin at the place, StablePlace containment, joint limits of
+//               q_place, CFreeHold at q_place, the goal cost (slot 1 only)
+//   with waypoints: the transition's collision term over its interior
+//               waypoints a + s (b - a), s = w / (W + 1), and its length.
+// A waypoint's gradient goes to the transition's end (share s, this slot's
+// own configuration) and start (share 1 - s, the previous slot's
+// configuration, returned as the "foreign" partial).
+// Writes this lane's share of every gradient partial into part[0 .. NP):
+// [0,7) own q, [7,11) grasp, [11, 11+3K) placements, [11+3K, 18+3K) foreign q.
+template <int K, int SPLIT, int MODE>
+__device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
+                                             int xs_stride, const float4* __restrict__ osl, int slot, int si,
+                                             float* __restrict__ part, float* __restrict__ terms,
+                                             int64_t term_ld, int64_t i_glob, bool write_terms) {
+    constexpr bool GRAD = MODE != MODE_COST;
+    const int k = slot >> 1;
+    const bool placing = slot & 1;
+    auto X = [&](int d) { return xs[d * xs_stride]; };
+    const int b0 = CT_STEP_DIM * k;
+
+    const float gx = X(b0 + 14), gy = X(b0 + 15), gz = X(b0 + 16), gyaw = X(b0 + 17);
+    float g_s, g_c;
+    sincosf(gyaw, &g_s, &g_c);
+    const float rho_x = X(b0 + 18), rho_y = X(b0 + 19), rho_yaw = X(b0 + 20);
+    float rho_s, rho_c;
+    sincosf(rho_yaw, &rho_s, &rho_c);
+
+    Movables<K> mb;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        float sj, cj;
+        sincosf(X(CT_STEP_DIM * j + 20), &sj, &cj);
+        const bool placed = j < k;
+        mb.x[j] = placed ? X(CT_STEP_DIM * j + 18) : T->obj0[j].cx;
+        mb.y[j] = placed ? X(CT_STEP_DIM * j + 19) : T->obj0[j].cy;
+        mb.c[j] = placed ? cj : T->obj0[j].c;
+        mb.s[j] = placed ? sj : T->obj0[j].s;
     }
 
-    // joint limits of this configuration
-    float jlim = 0.f;
+    // this slot's configuration (the transition's end b, row qb_row of the
+    // staged particle) and the transition's start a (row qa_row, or q0)
+    const int W = T->W;
+    const int qb_row = b0 + (placing ? 7 : 0);
+    const bool start_is_var = placing || k > 0;
+    const int qa_row = placing ? b0 : b0 - CT_STEP_DIM + 7;
+    auto qb = [&](int j) { return X(qb_row + j); };
+    auto qa = [&](int j) { return start_is_var ? X(qa_row + j) : T->q0[j]; };
+
+    float gq[CT_N_JOINTS], gqa[CT_N_JOINTS];
+#pragma unroll
+    for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = gqa[j] = 0.f;
+    float gg[4] = {0.f, 0.f, 0.f, 0.f};
+    float gr[K][3];
+#pragma unroll
+    for (int j = 0; j < K; ++j) gr[j][0] = gr[j][1] = gr[j][2] = 0.f;
+    float coll = 0.f, coll_m = 0.f, kin_pos = 0.f, kin_rot = 0.f;
+    const float* osl_k = reinterpret_cast<const float*>(osl) + 4 * k * CT_MAX_OBJ_SPHERES;
+
+    // waypoints w = 1..W of the transition, then the configuration itself
+    for (int w = 1; w <= W + 1; ++w) {
+        const bool key = w == W + 1;   // wave-uniform
+        const float s = key ? 1.f : (float)w / (float)(W + 1);
+        float q[CT_N_JOINTS], gw[CT_N_JOINTS];
+#pragma unroll
+        for (int j = 0; j < CT_N_JOINTS; ++j) {
+            const float b = qb(j);
+            q[j] = key ? b : qa(j) + s * (b - qa(j));
+            gw[j] = 0.f;
+        }
+        float cw = 0.f;
+        // the object is in the hand at both configurations of its step and
+        // along the holding transition
+        const bool held = key || placing;
+        const float lam = key ? T->w[W_COLL] : T->w[W_MCOLL];
+        config_pass<K, SPLIT, GRAD>(T, reinterpret_cast<const float4*>(osl_k), k, si, q, held, key, placing, lam,
+                                    mb, gx, gy, gz, g_c, g_s, rho_x, rho_y, rho_c, rho_s, cw, gw, gg, gr, kin_pos,
+                                    kin_rot);
+        if (key) coll += cw; else coll_m += cw;
+        if (GRAD) {
+#pragma unroll
+            for (int j = 0; j < CT_N_JOINTS; ++j) {
+                gq[j] += s * gw[j];
+                gqa[j] += (1.f - s) * gw[j];
+            }
+        }
+    }
+    if (!start_is_var) {
+#pragma unroll
+        for (int j = 0; j < CT_N_JOINTS; ++j) gqa[j] = 0.f;
+    }
+
+    // joint limits of this configuration; the transition's length
+    float jlim = 0.f, traj = 0.f;
     if (si == 0) {
-        float gj[CT_N_JOINTS];
-        jlim = bounds_dist<CT_N_JOINTS>(q, T->q_lo, T->q_hi, T->w[W_JLIM], gj);
+        float gj[CT_N_JOINTS], qk[CT_N_JOINTS];
+#pragma unroll
+        for (int j = 0; j < CT_N_JOINTS; ++j) qk[j] = qb(j);
+        jlim = bounds_dist<CT_N_JOINTS>(qk, T->q_lo, T->q_hi, T->w[W_JLIM], gj);
         if (GRAD) {
 #pragma unroll
             for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] += gj[j];
         }
+        if (W > 0) {
+            float ss = 0.f;
+#pragma unroll
+            for (int j = 0; j < CT_N_JOINTS; ++j) ss += (qb(j) - qa(j)) * (qb(j) - qa(j));
+            traj = sqrtf(ss);
+            if (GRAD && traj > 0.f) {
+                const float sc = T->w[W_TRAJ] / traj;
+#pragma unroll
+                for (int j = 0; j < CT_N_JOINTS; ++j) {
+                    gq[j] += sc * (qb(j) - qa(j));
+                    if (start_is_var) gqa[j] -= sc * (qb(j) - qa(j));
+                }
+            }
+        }
     }
 
     float grasp = 0.f, coll_obj = 0.f, place = 0.f, goal = 0.f;
+    const float lc = T->w[W_COLL];
     if (!placing) {
         if (si == 0) {
             const float gv[3] = {gx, gy, gz};
@@ -516,8 +617,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
         const float tp[3] = {rho_x, rho_y, T->place_z[k]};
         float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
-        object_spheres<K, SPLIT, GRAD>(T, osl + k * CT_MAX_OBJ_SPHERES, T->n_os, si, Rp, tp, mb, k, lc, coll_obj,
-                                       fp, mp, gr);
+        object_spheres<K, SPLIT, GRAD>(T, reinterpret_cast<const float4*>(osl_k), T->n_os, si, Rp, tp, mb, k, lc,
+                                       coll_obj, fp, mp, gr);
         if (GRAD) {
             // translation: the force; turning about the vertical through the
             // placement origin: z of the moment about that point
@@ -554,9 +655,9 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
                     const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
                     goal += dist;
                     if (GRAD && dist > 0.f) {
-                        const float s = lg / dist;
-                        gr[a][0] += dx * s; gr[a][1] += dy * s;
-                        gr[b][0] -= dx * s; gr[b][1] -= dy * s;
+                        const float sc = lg / dist;
+                        gr[a][0] += dx * sc; gr[a][1] += dy * sc;
+                        gr[b][0] -= dx * sc; gr[b][1] -= dy * sc;
                     }
                 }
         }
@@ -564,10 +665,14 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
 
     // ---- combine the SPLIT lanes of this slot
     coll = split_sum<SPLIT>(coll);
+    coll_m = split_sum<SPLIT>(coll_m);
     coll_obj = split_sum<SPLIT>(coll_obj);
     if (GRAD) {
 #pragma unroll
-        for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = split_sum<SPLIT>(gq[j]);
+        for (int j = 0; j < CT_N_JOINTS; ++j) {
+            gq[j] = split_sum<SPLIT>(gq[j]);
+            gqa[j] = split_sum<SPLIT>(gqa[j]);
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) gg[j] = split_sum<SPLIT>(gg[j]);
 #pragma unroll
@@ -580,21 +685,24 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     const float* w = T->w;
     const float* e = T->eps;
     float gsum = 0.f;
-    if (si == 0) {
-        if (GRAD) {
+    if (si == 0 && GRAD) {
 #pragma unroll
-            for (int j = 0; j < CT_N_JOINTS; ++j) { part[j] = gq[j]; gsum += gq[j]; }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) { part[11 + 3 * j + c] = gr[j][c]; gsum += gr[j][c]; }
+        for (int j = 0; j < CT_N_JOINTS; ++j) {
+            part[j] = gq[j];
+            part[11 + 3 * K + j] = gqa[j];
+            gsum += gq[j] + gqa[j];
         }
-        (void)NP;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { part[11 + 3 * j + c] = gr[j][c]; gsum += gr[j][c]; }
     }
-    const float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll;
-    bool ok = kin_pos <= e[E_KPOS] && kin_rot <= e[E_KROT] && jlim <= e[E_JLIM] && coll <= e[E_COLL];
+    const float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll +
+                     w[W_MCOLL] * coll_m + w[W_TRAJ] * traj;
+    bool ok = kin_pos <= e[E_KPOS] && kin_rot <= e[E_KROT] && jlim <= e[E_JLIM] && coll <= e[E_COLL] &&
+              coll_m <= e[E_MCOLL];
     if (!placing) {
         out.cost = kw + w[W_GRASP] * grasp + w[W_COLL] * coll_obj;
         ok = ok && grasp <= e[E_GRASP] && coll_obj <= e[E_COLL];
@@ -602,6 +710,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         out.cost = kw + w[W_PLACE] * place + w[W_GOAL] * goal;
         ok = ok && place <= e[E_PLACE];
     }
+    out.traj = traj;
     const bool fin = __builtin_isfinite(out.cost + gsum);
     out.flags = (ok ? 1 : 0) | (fin ? 2 : 0);
 
@@ -623,6 +732,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             put(tb + T_COLL_P, coll);
             if (slot == 1 && T->goal) put(T->goal_term, goal);
         }
+        if (W > 0) put(CT_TERMS_PER_STEP * K + slot, coll_m);
     }
     return out;
 }
@@ -634,16 +744,17 @@ __global__ __launch_bounds__(WG) void particle_kernel(
     float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
     int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
     float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
-    int32_t* __restrict__ t_out, int32_t stop_at_first) {
+    int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw) {
     constexpr int SLOTS = 2 * K;
     constexpr int LPP = SLOTS * SPLIT;
     constexpr int P = WG / LPP;
     constexpr int D = CT_STEP_DIM * K;
-    constexpr int NP = 11 + 3 * K;
+    constexpr int NP = 18 + 3 * K;
 
     __shared__ float xs[D * P];
     __shared__ float part[P * SLOTS * NP];
     __shared__ float cpart[P * SLOTS];
+    __shared__ float tpart[P * SLOTS];
     __shared__ int flg[P * SLOTS];
     __shared__ int okp[P];
     __shared__ float4 osl[K * CT_MAX_OBJ_SPHERES];
@@ -688,6 +799,7 @@ __global__ __launch_bounds__(WG) void particle_kernel(
                                                         part + (p * SLOTS + slot) * NP, terms, ld, i, wt);
             if (si == 0) {
                 cpart[p * SLOTS + slot] = o.cost;
+                tpart[p * SLOTS + slot] = o.traj;
                 flg[p * SLOTS + slot] = o.flags;
             }
         }
@@ -709,6 +821,12 @@ __global__ __launch_bounds__(WG) void particle_kernel(
         m &= __builtin_isfinite(J) ? 1 : 0;
         okp[tid] = ok;
         if (i < n) {
+            if (MODE == MODE_COST && terms && T->traj_term >= 0) {
+                float tl = 0.f;
+#pragma unroll
+                for (int s = 0; s < SLOTS; ++s) tl += tpart[tid * SLOTS + s];
+                terms[(int64_t)T->traj_term * ld + i] = tl;
+            }
             if (cost) cost[i] = J;
             if (mask) mask[i] = (uint8_t)m;
             if (m) any_sat = 1;
@@ -727,10 +845,14 @@ __global__ __launch_bounds__(WG) void particle_kernel(
         const int k = d / CT_STEP_DIM, r = d - CT_STEP_DIM * k;
         const float* pp = part + p * SLOTS * NP;
         float g;
+        constexpr int FQ = 11 + 3 * K;   // foreign-configuration partials
         if (r < 7) {
-            g = pp[(2 * k) * NP + r];
+            // q_grasp of step k: its slot, plus the start of the holding transition
+            g = pp[(2 * k) * NP + r] + pp[(2 * k + 1) * NP + FQ + r];
         } else if (r < 14) {
+            // q_place of step k: its slot, plus the start of the next free transition
             g = pp[(2 * k + 1) * NP + (r - 7)];
+            if (k + 1 < K) g += pp[(2 * k + 2) * NP + FQ + (r - 7)];
         } else if (r < 18) {
             g = pp[(2 * k) * NP + 7 + (r - 14)] + pp[(2 * k + 1) * NP + 7 + (r - 14)];
         } else {
@@ -740,7 +862,7 @@ __global__ __launch_bounds__(WG) void particle_kernel(
         }
         const int64_t a = d * ld + i;
         if (MODE == MODE_GRAD) {
-            G[a] = g;
+            G[a] = gw ? gw[i] * g : g;
         } else if (okp[p] && !(frozen && frozen[d])) {
             const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
             const float gs = gscale * g;

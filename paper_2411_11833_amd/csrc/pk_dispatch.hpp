@@ -21,6 +21,7 @@ struct PkArgs {
     const int32_t* t_in;     // device counter of applied updates (t = *t_in + 1), or null
     int32_t* t_out;          // receives t (the other counter slot), or null
     int32_t stop_at_first;   // skip the step if an earlier iteration satisfied
+    const float* gw;         // per-particle gradient weights (gradient mode), or null
 };
 
 using PkFn = hipError_t (*)(const ct::Tables*, const PkArgs&, hipStream_t);

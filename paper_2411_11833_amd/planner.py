@@ -76,10 +76,11 @@ class GpuProblem:
                   m.data_ptr() if m is not None else None, _stream())
         return c, T, m
 
-    def cost_grad(self, X, n: int):
+    def cost_grad(self, X, n: int, weights=None):
         c = torch.empty(n, dtype=torch.float32, device=self.device)
         G = self.empty(n)
-        B.ct_cost_grad(self.handle, X.data_ptr(), n, X.shape[1], c.data_ptr(), G.data_ptr(), _stream())
+        B.ct_cost_grad(self.handle, X.data_ptr(), n, X.shape[1], c.data_ptr(), G.data_ptr(),
+                       weights.data_ptr() if weights is not None else None, _stream())
         return c, G
 
     def adam_apply(self, X, M, V, G, n: int, t: int, adam: B.CtAdam, frozen=None):
@@ -105,6 +106,39 @@ class GpuProblem:
 
     def autotune(self, X, n: int) -> int:
         return B.ct_autotune(self.handle, X.data_ptr(), n, X.shape[1], _stream())
+
+
+class ParticleCost(torch.autograd.Function):
+    """Per-particle cost J(x_i) of Eq. (2) as a differentiable torch op on a
+    dimension-major particle buffer X [dim, ld].
+
+    forward: ct_cost (nothing but X is saved);
+    backward: ct_cost_grad with the incoming per-particle gradients as
+    weights -- one kernel that recomputes forward kinematics of every
+    configuration and motion waypoint and applies the hand-written adjoint.
+    """
+
+    @staticmethod
+    def forward(ctx, X, gp: "GpuProblem", n: int):
+        X = X.contiguous()
+        c = torch.empty(n, dtype=torch.float32, device=X.device)
+        B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], c.data_ptr(), None, None, _stream())
+        ctx.save_for_backward(X)
+        ctx.gp, ctx.n = gp, n
+        return c
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        (X,) = ctx.saved_tensors
+        gp, n = ctx.gp, ctx.n
+        w = grad_c.to(torch.float32).contiguous()
+        G = torch.zeros_like(X)
+        B.ct_cost_grad(gp.handle, X.data_ptr(), n, X.shape[1], None, G.data_ptr(), w.data_ptr(), _stream())
+        return G, None, None
+
+
+def particle_cost(gp: "GpuProblem", X: torch.Tensor, n: int) -> torch.Tensor:
+    return ParticleCost.apply(X, gp, n)
 
 
 def grasp_frozen(prob: I.Problem, device="cuda") -> torch.Tensor:

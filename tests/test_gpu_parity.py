@@ -335,3 +335,69 @@ def test_stop_at_first_freezes_the_batch():
         gp.step(Xe, Me, Ve, n, t, _adam(n), frozen=fz)
     torch.cuda.synchronize()
     assert torch.equal(X, Xe) and torch.equal(M, Me) and torch.equal(V, Ve)
+
+
+# ----------------------------------------------------------------------------- motion cost
+
+
+def _motion(n_objects=2, W=16, seed=4):
+    return I.packing(robot_seed=2, scene_seed=seed, n_objects=n_objects, n_obstacles=3, waypoints=W)
+
+
+@pytest.mark.parametrize("n_objects,n", [(1, 48), (2, 40), (3, 24)])
+def test_motion_terms_and_gradient(n_objects, n):
+    prob = _motion(n_objects)
+    gp = _gp(prob)
+    X = I.uniform_particles(prob, n, seed=21)
+    # shrink transitions so that waypoints sweep near the scene, not through all of it
+    _check_cost_terms_mask(prob, gp, X)
+    _check_grad(prob, gp, X)
+
+
+def test_motion_gradient_matches_central_differences():
+    """GPU gradient of the waypoint motion cost against FP64 central
+    differences (h = 1e-6) of the oracle's cost, particle by particle."""
+    import torch as th
+    prob = _motion(2, W=16, seed=6)
+    gp = _gp(prob)
+    n = 16
+    X = I.uniform_particles(prob, n, seed=22)
+    Xd = gp.from_rows(X)
+    _, G = gp.cost_grad(Xd, n)
+    torch.cuda.synchronize()
+    G = gp.to_rows(G, n).cpu().numpy().astype(np.float64)
+    X64 = X.astype(np.float64)
+    _, kink = O.margins(prob, X64)
+    h = 1e-6
+    D = prob.dim
+    pert = np.repeat(X64[:, None, :], 2 * D, axis=1)
+    for d in range(D):
+        pert[:, 2 * d, d] += h
+        pert[:, 2 * d + 1, d] -= h
+    Jp = O.cost(prob, pert.reshape(-1, D)).reshape(n, D, 2)
+    fd = (Jp[:, :, 0] - Jp[:, :, 1]) / (2 * h)
+    ok = kink >= 1e-5          # at least 10 h from every kink
+    assert ok.sum() >= n // 2, ok.sum()
+    err = np.linalg.norm(G - fd, axis=1)
+    assert np.all(err[ok] <= 1e-3 * np.linalg.norm(fd, axis=1)[ok] + 1e-4), err[ok].max()
+
+
+def test_particle_cost_autograd_function():
+    """ParticleCost: forward = ct_cost, backward = one ct_cost_grad launch
+    weighted by the incoming gradient."""
+    from paper_2411_11833_amd.planner import particle_cost
+    prob = _motion(2, W=16)
+    gp = _gp(prob)
+    n = 64
+    Xd = gp.empty(n)
+    gp.seed_uniform(9, Xd, None, None, n)
+    Xg = Xd.clone().requires_grad_(True)
+    c = particle_cost(gp, Xg, n)
+    w = torch.linspace(-1.0, 2.0, n, device="cuda")
+    (c * w).sum().backward()
+    c0, G0 = gp.cost_grad(Xd, n)
+    torch.cuda.synchronize()
+    assert torch.equal(c.detach(), c0)
+    want = G0 * torch.cat([w, torch.zeros(Xd.shape[1] - n, device="cuda")])[None, :]
+    assert torch.allclose(Xg.grad, want, rtol=1e-6, atol=1e-7)
+    assert torch.all(Xg.grad[:, n:] == 0)

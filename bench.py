@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--split", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-motion", action="store_true", help="skip the waypoint motion-cost measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
+    ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
@@ -226,6 +228,42 @@ def main():
         log(f"[bench] motion: fwd+bwd {nm / fb_s:.4g} particle-iters/s, fused step {st_s * 1e3:.2f} ms "
             f"({mwk.flops * nm / st_s / 1e12:.1f} TFLOP/s model)", q)
 
+    # ---- many skeletons: one persistent launch per iteration vs one per skeleton
+    batch = None
+    if not args.no_batch:
+        from paper_2411_11833_amd.planner import GpuBatch
+        wl = I.batch_workload(0, 64)
+        gb = GpuBatch([p for p, _ in wl], [nn for _, nn in wl], dev)
+        gb.seed(1)
+        bsplit, bwg = gb.autotune()
+        bi = args.batch_iters
+        badam = default_adam(1)
+        res_b = {}
+        for mode in ("persistent", "per_skeleton"):
+            gb.set_tuning(bsplit, bwg, mode == "persistent")
+            gb.seed(2)
+            gb.optimize(0, bi, badam)          # capture + warm-up
+            torch.cuda.synchronize()
+            gb.seed(3)
+            e0.record(stream)
+            gb.optimize(0, bi, badam)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res_b[mode] = e0.elapsed_time(e1) / 1e3
+        batch = {
+            "workload": "64 skeletons, 1-6 pick-place steps (uniform), 512-8192 particles each (log-uniform, "
+                        f"{gb.particles} in total), 2-12 obstacle boxes, {bi} Adam iterations, one captured graph",
+            "split": bsplit, "workgroups": bwg,
+            "persistent_s": res_b["persistent"],
+            "per_skeleton_launches_s": res_b["per_skeleton"],
+            "persistent_particle_iters_per_s": gb.particles * bi / res_b["persistent"],
+            "per_skeleton_particle_iters_per_s": gb.particles * bi / res_b["per_skeleton"],
+            "speedup": res_b["per_skeleton"] / res_b["persistent"],
+        }
+        log(f"[bench] batch: persistent {res_b['persistent'] * 1e3:.1f} ms vs per-skeleton "
+            f"{res_b['per_skeleton'] * 1e3:.1f} ms for {bi} iterations (split {bsplit}, {bwg} workgroups)", q)
+        gb.close()
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -255,6 +293,7 @@ def main():
         "first_sat_iter_full_run": None if first_iter_full == INT32_MAX else first_iter_full,
         "satisfied_after_full_run": sat_end,
         "motion": motion,
+        "batch": batch,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

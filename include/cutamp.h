@@ -258,6 +258,53 @@ int ct_get_split(const ct_problem *problem, int32_t *split);
 int ct_autotune(ct_problem *problem, const float *X, int64_t n, int64_t ld, int32_t *chosen,
                 void *stream);
 
+/* ------------------------------------------------------------------------
+ * Many skeletons at once (the backtracking search of Alg. 1 keeps several
+ * skeletons' particle batches alive; each is optimized on its own batch mean,
+ * Eq. (4)).  A batch binds problems of any lengths (K = 1..6) to their
+ * caller-owned particle buffers; one optimizer iteration of every skeleton is
+ * then ONE persistent kernel launch in which a fixed set of workgroups pull
+ * (skeleton, particle tile) items from a device queue, largest first.
+ * ------------------------------------------------------------------------ */
+typedef struct ct_batch ct_batch;
+
+/*
+ * count skeletons; arrays of length count (host arrays of device pointers):
+ * problems[s] (handles stay owned by the caller and must outlive the batch),
+ * X/M/V[s] with layout (n[s], ld[s]) as for ct_step, cost[s] / mask[s] /
+ * first_sat[s] / frozen[s] optional (the arrays themselves may be NULL).
+ * Skeleton s uses grad_scale 1/n[s].  Allocates the device work tables.
+ */
+int ct_batch_create(int32_t count, ct_problem *const *problems, float *const *X, float *const *M,
+                    float *const *V, const int64_t *n, const int64_t *ld, float *const *cost,
+                    uint8_t *const *mask, int32_t *const *first_sat, const uint8_t *const *frozen,
+                    ct_batch **out);
+int ct_batch_destroy(ct_batch *batch);
+
+/*
+ * Launch shape: split = lanes per configuration (1, 2 or 4; 0 = default),
+ * workgroups = persistent workgroups (0 = two per compute unit), persistent
+ * = 0 launches one ordinary kernel per skeleton instead (the reference
+ * point a persistent launch is compared with).  Rebuilds the work list.
+ */
+int ct_batch_set_tuning(ct_batch *batch, int32_t split, int32_t workgroups, int32_t persistent);
+
+/* Adam update number t (>= 1) of every skeleton; lr, betas, eps from adam
+ * (adam->grad_scale is ignored: each skeleton uses 1/n[s]). */
+int ct_batch_step(ct_batch *batch, int64_t t, const ct_adam *adam, void *stream);
+
+/* iters batch steps t0+1 .. t0+iters as one captured graph (cached like
+ * ct_optimize's). */
+int ct_batch_optimize(ct_batch *batch, int64_t t0, int32_t iters, const ct_adam *adam, void *stream);
+
+/*
+ * Times every split x {1, 2, 3, 4} workgroups per compute unit of the
+ * persistent launch on the bound buffers with lr = 0 (X is not changed; M
+ * and V are zeroed afterwards) and keeps the fastest.  chosen (host int[2],
+ * may be NULL) receives (split, workgroups).
+ */
+int ct_batch_autotune(ct_batch *batch, int32_t *chosen, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

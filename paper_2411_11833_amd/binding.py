@@ -79,6 +79,14 @@ def _load() -> C.CDLL:
         "ct_set_split": (C.c_int, [vp, i32]),
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
+        "ct_batch_create": (C.c_int, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(i64), C.POINTER(i64), C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
+        "ct_batch_destroy": (C.c_int, [vp]),
+        "ct_batch_set_tuning": (C.c_int, [vp, i32, i32, i32]),
+        "ct_batch_step": (C.c_int, [vp, i64, C.POINTER(CtAdam), vp]),
+        "ct_batch_optimize": (C.c_int, [vp, i64, i32, C.POINTER(CtAdam), vp]),
+        "ct_batch_autotune": (C.c_int, [vp, C.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -191,3 +199,42 @@ def ct_autotune(h, X, n, ld, stream=0) -> int:
     s = C.c_int32()
     _chk(LIB.ct_autotune(h, X, n, ld, C.byref(s), stream), "ct_autotune")
     return s.value
+
+
+def _ptrs(vals):
+    arr = (C.c_void_p * len(vals))(*[v if v else None for v in vals])
+    return arr
+
+
+def ct_batch_create(problems, X, M, V, n, ld, cost=None, mask=None, first_sat=None, frozen=None) -> int:
+    """All list arguments have one entry per skeleton (device addresses as ints)."""
+    cnt = len(problems)
+    nn = (C.c_int64 * cnt)(*n)
+    ll = (C.c_int64 * cnt)(*ld)
+    opt = lambda a: _ptrs(a) if a is not None else None  # noqa: E731
+    h = C.c_void_p()
+    _chk(LIB.ct_batch_create(cnt, _ptrs(problems), _ptrs(X), _ptrs(M), _ptrs(V), nn, ll, opt(cost), opt(mask),
+                             opt(first_sat), opt(frozen), C.byref(h)), "ct_batch_create")
+    return h.value
+
+
+def ct_batch_destroy(h):
+    _chk(LIB.ct_batch_destroy(h), "ct_batch_destroy")
+
+
+def ct_batch_set_tuning(h, split=0, workgroups=0, persistent=1):
+    _chk(LIB.ct_batch_set_tuning(h, split, workgroups, persistent), "ct_batch_set_tuning")
+
+
+def ct_batch_step(h, t, adam: CtAdam, stream=0):
+    _chk(LIB.ct_batch_step(h, t, C.byref(adam), stream), "ct_batch_step")
+
+
+def ct_batch_optimize(h, t0, iters, adam: CtAdam, stream=0):
+    _chk(LIB.ct_batch_optimize(h, t0, iters, C.byref(adam), stream), "ct_batch_optimize")
+
+
+def ct_batch_autotune(h, stream=0) -> tuple[int, int]:
+    out = (C.c_int32 * 2)()
+    _chk(LIB.ct_batch_autotune(h, out, stream), "ct_batch_autotune")
+    return out[0], out[1]

@@ -1,7 +1,7 @@
 """Build libcutamp.so (the C ABI of include/cutamp.h) for gfx950 with hipcc.
 
-The fused particle kernel is instantiated per skeleton length K in its own
-object (pk_instances.hip with -DCT_K=K) so the objects compile in parallel;
+The fused particle kernels are instantiated per lane split in their own
+object (pk_instances.hip with -DCT_SPLIT=s) so the objects compile in parallel;
 the host side (cutamp.hip) holds the C ABI and the small elementwise kernels.
 
 Usage: python -m paper_2411_11833_amd.build
@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcutamp.so")
-MAX_K = 6
+SPLITS = (1, 2, 4)
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -55,8 +55,9 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     os.makedirs(obj_dir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(obj_dir, "cutamp.o"), [])]
-    for k in range(1, MAX_K + 1):
-        units.append((os.path.join(CSRC, "pk_instances.hip"), os.path.join(obj_dir, f"pk_k{k}.o"), [f"-DCT_K={k}"]))
+    for split in SPLITS:
+        units.append((os.path.join(CSRC, "pk_instances.hip"), os.path.join(obj_dir, f"pk_s{split}.o"),
+                      [f"-DCT_SPLIT={split}"]))
     cmds = [[hipcc(), *HIPCC_FLAGS, *(extra or []), *inc, *defs, "-c", src, "-o", obj]
             for src, obj, defs in units]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))

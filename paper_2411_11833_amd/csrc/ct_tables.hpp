@@ -72,4 +72,19 @@ struct Tables {
     float hi[CT_MAX_STEPS * CT_STEP_DIM];
 };
 
+// particles per workgroup tile for a K-step skeleton and SPLIT lanes per slot
+__host__ __device__ constexpr int tile_particles(int K, int SPLIT) { return WG / (2 * K * SPLIT); }
+
+// One skeleton of a batch, as the persistent kernel sees it.
+struct BatchSkel {
+    const Tables* T;
+    float *X, *M, *V, *cost;
+    uint8_t* mask;
+    int32_t* first_sat;
+    const uint8_t* frozen;
+    int64_t n, ld;
+    float gscale;
+    int pad;
+};
+
 }  // namespace ct

@@ -112,17 +112,24 @@ bool valid_adam(const ct_adam* a) {
 }
 
 // ---------------------------------------------------------------------------
-// particle kernel dispatch: K in 1..6 (one object file per K), split in
-// {1, 2, 4}, three modes
+// particle kernel dispatch: split in {1, 2, 4} (one object file per split),
+// skeleton length K = 1..6, three modes; the many-skeleton kernel reads K
+// from each skeleton's tables at run time
 
-PkFn pick_kernel(int K, int split, int mode) {
-    switch (K) {
-        case 1: return ct_pick_k1(split, mode);
-        case 2: return ct_pick_k2(split, mode);
-        case 3: return ct_pick_k3(split, mode);
-        case 4: return ct_pick_k4(split, mode);
-        case 5: return ct_pick_k5(split, mode);
-        case 6: return ct_pick_k6(split, mode);
+PkFn pick_kernel(int split, int K, int mode) {
+    switch (split) {
+        case 1: return ct_pick_s1(K, mode);
+        case 2: return ct_pick_s2(K, mode);
+        case 4: return ct_pick_s4(K, mode);
+        default: return nullptr;
+    }
+}
+
+BatchFn pick_batch(int split) {
+    switch (split) {
+        case 1: return ct_batch_s1();
+        case 2: return ct_batch_s2();
+        case 4: return ct_batch_s4();
         default: return nullptr;
     }
 }
@@ -131,7 +138,7 @@ int effective_split(const ct_problem* P) { return P->split ? P->split : default_
 
 int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0) {
     if (a.n == 0) return CT_OK;
-    PkFn f = pick_kernel(P->K, split ? split : effective_split(P), mode);
+    PkFn f = pick_kernel(split ? split : effective_split(P), P->K, mode);
     if (!f) return CT_ERR_UNSUPPORTED;
     return err_of(f(P->d, a, st));
 }
@@ -566,4 +573,254 @@ extern "C" int ct_autotune(ct_problem* P, const float* X, int64_t n, int64_t ld,
     ct_set_split(P, best_split);
     if (chosen) *chosen = best_split;
     return CT_OK;
+}
+
+// ===========================================================================
+// many skeletons
+
+struct ct_batch {
+    std::vector<ct_problem*> probs;
+    std::vector<ct::BatchSkel> skels;   // host copy
+    ct::BatchSkel* d_skels = nullptr;
+    int2* d_items = nullptr;
+    int32_t n_items = 0;
+    int32_t* d_queue = nullptr;   // [0] next item, [1] workgroups done
+    int32_t* t_dev = nullptr;     // two-slot step counter
+    int split = 0, workgroups = 0, persistent = 1;
+    int n_cu = 256;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int32_t g_iters = -1, g_split = -1, g_wg = -1, g_pers = -1;
+    float g_lr = 0, g_b1 = 0, g_b2 = 0, g_eps = 0;
+};
+
+namespace {
+
+void batch_drop_graph(ct_batch* B) {
+    if (B->gexec) hipGraphExecDestroy(B->gexec);
+    if (B->graph) hipGraphDestroy(B->graph);
+    B->gexec = nullptr;
+    B->graph = nullptr;
+    B->g_iters = -1;
+}
+
+int batch_split(const ct_batch* B) { return B->split ? B->split : 1; }
+int batch_workgroups(const ct_batch* B) { return B->workgroups ? B->workgroups : 2 * B->n_cu; }
+
+// (skeleton, tile) items for the current split, largest tiles first: a tile's
+// work grows with the boxes each of its configurations is tested against
+int batch_build_items(ct_batch* B) {
+    const int split = batch_split(B);
+    std::vector<std::pair<int, int2>> items;
+    for (size_t s = 0; s < B->probs.size(); ++s) {
+        const ct_problem* P = B->probs[s];
+        const int per = ct::tile_particles(P->K, split);
+        const int64_t tiles = (B->skels[s].n + per - 1) / per;
+        const int w = P->h.n_static + P->K - 1 + 2 * P->h.W * 1;
+        for (int64_t t = 0; t < tiles; ++t) items.push_back({w, make_int2((int)s, (int)t)});
+    }
+    std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    std::vector<int2> flat(items.size());
+    for (size_t i = 0; i < items.size(); ++i) flat[i] = items[i].second;
+    if (B->d_items) hipFree(B->d_items);
+    B->d_items = nullptr;
+    B->n_items = (int32_t)flat.size();
+    if (flat.empty()) return CT_OK;
+    if (hipMalloc(&B->d_items, flat.size() * sizeof(int2)) != hipSuccess) return CT_ERR_ALLOC;
+    if (hipMemcpy(B->d_items, flat.data(), flat.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return CT_ERR_DEVICE;
+    return CT_OK;
+}
+
+int batch_launch(ct_batch* B, const ct_adam* adam, int32_t t, const int32_t* t_in, int32_t* t_out, hipStream_t st) {
+    AdamArgs a = adam_args(adam);
+    if (B->persistent) {
+        if (B->n_items == 0) return CT_OK;
+        BatchFn f = pick_batch(batch_split(B));
+        if (!f) return CT_ERR_UNSUPPORTED;
+        BatchArgs g{};
+        g.skels = B->d_skels;
+        g.items = B->d_items;
+        g.n_items = B->n_items;
+        g.queue = B->d_queue;
+        g.n_workgroups = batch_workgroups(B);
+        g.a = a;
+        g.t = t;
+        g.t_in = t_in;
+        g.t_out = t_out;
+        return err_of(f(g, st));
+    }
+    // reference point: one ordinary launch per skeleton; every launch reads
+    // the same counter slot and only the last writes the next one
+    for (size_t s = 0; s < B->probs.size(); ++s) {
+        const ct::BatchSkel& k = B->skels[s];
+        if (k.n == 0) continue;
+        PkArgs p{};
+        p.X = k.X; p.M = k.M; p.V = k.V; p.cost = k.cost; p.mask = k.mask; p.first_sat = k.first_sat;
+        p.frozen = k.frozen; p.n = k.n; p.ld = k.ld; p.a = a; p.a.gs = k.gscale; p.t = t; p.t_in = t_in;
+        p.t_out = (s + 1 == B->probs.size()) ? t_out : nullptr;
+        const int rc = run_pk(B->probs[s], ct::MODE_STEP, p, st, batch_split(B));
+        if (rc != CT_OK) return rc;
+    }
+    return CT_OK;
+}
+
+}  // namespace
+
+extern "C" int ct_batch_create(int32_t count, ct_problem* const* problems, float* const* X, float* const* M,
+                               float* const* V, const int64_t* n, const int64_t* ld, float* const* cost,
+                               uint8_t* const* mask, int32_t* const* first_sat, const uint8_t* const* frozen,
+                               ct_batch** out) {
+    if (!out) return CT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (count < 1 || !problems || !X || !M || !V || !n || !ld) return CT_ERR_INVALID_ARG;
+    for (int s = 0; s < count; ++s) {
+        if (!problems[s] || !X[s] || !M[s] || !V[s]) return CT_ERR_INVALID_ARG;
+        if (!good_layout(X[s], n[s], ld[s]) || !good_layout(M[s], n[s], ld[s]) || !good_layout(V[s], n[s], ld[s]))
+            return CT_ERR_INVALID_ARG;
+        if (n[s] > INT32_MAX) return CT_ERR_UNSUPPORTED;
+    }
+    ct_batch* B = new (std::nothrow) ct_batch();
+    if (!B) return CT_ERR_ALLOC;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        B->n_cu = prop.multiProcessorCount;
+    for (int s = 0; s < count; ++s) {
+        ct::BatchSkel k{};
+        k.T = problems[s]->d;
+        k.X = X[s]; k.M = M[s]; k.V = V[s];
+        k.cost = cost ? cost[s] : nullptr;
+        k.mask = mask ? mask[s] : nullptr;
+        k.first_sat = first_sat ? first_sat[s] : nullptr;
+        k.frozen = frozen ? frozen[s] : nullptr;
+        k.n = n[s];
+        k.ld = ld[s];
+        k.gscale = n[s] > 0 ? 1.f / (float)n[s] : 0.f;
+        B->probs.push_back(problems[s]);
+        B->skels.push_back(k);
+    }
+    int rc = CT_OK;
+    if (hipMalloc(&B->d_skels, count * sizeof(ct::BatchSkel)) != hipSuccess ||
+        hipMalloc(&B->d_queue, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&B->t_dev, 2 * sizeof(int32_t)) != hipSuccess)
+        rc = CT_ERR_ALLOC;
+    if (rc == CT_OK && hipMemcpy(B->d_skels, B->skels.data(), count * sizeof(ct::BatchSkel),
+                                 hipMemcpyHostToDevice) != hipSuccess)
+        rc = CT_ERR_DEVICE;
+    if (rc == CT_OK && hipMemset(B->d_queue, 0, 2 * sizeof(int32_t)) != hipSuccess) rc = CT_ERR_DEVICE;
+    if (rc == CT_OK) rc = batch_build_items(B);
+    if (rc != CT_OK) {
+        ct_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return CT_OK;
+}
+
+extern "C" int ct_batch_destroy(ct_batch* B) {
+    if (!B) return CT_OK;
+    batch_drop_graph(B);
+    if (B->capture_stream) hipStreamDestroy(B->capture_stream);
+    if (B->d_skels) hipFree(B->d_skels);
+    if (B->d_items) hipFree(B->d_items);
+    if (B->d_queue) hipFree(B->d_queue);
+    if (B->t_dev) hipFree(B->t_dev);
+    delete B;
+    return CT_OK;
+}
+
+extern "C" int ct_batch_set_tuning(ct_batch* B, int32_t split, int32_t workgroups, int32_t persistent) {
+    if (!B || !(split == 0 || split == 1 || split == 2 || split == 4) || workgroups < 0) return CT_ERR_INVALID_ARG;
+    const bool rebuild = batch_split(B) != (split ? split : 1);
+    B->split = split;
+    B->workgroups = workgroups;
+    B->persistent = persistent ? 1 : 0;
+    batch_drop_graph(B);
+    return rebuild ? batch_build_items(B) : CT_OK;
+}
+
+extern "C" int ct_batch_step(ct_batch* B, int64_t t, const ct_adam* adam, void* stream) {
+    if (!B || t < 1 || t > INT32_MAX || !valid_adam(adam)) return CT_ERR_INVALID_ARG;
+    return batch_launch(B, adam, (int32_t)t, nullptr, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int ct_batch_optimize(ct_batch* B, int64_t t0, int32_t iters, const ct_adam* adam, void* stream) {
+    if (!B || t0 < 0 || iters < 0 || t0 + iters > INT32_MAX || !valid_adam(adam)) return CT_ERR_INVALID_ARG;
+    if (iters == 0) return CT_OK;
+    const bool same = B->gexec && B->g_iters == iters && B->g_split == batch_split(B) &&
+                      B->g_wg == batch_workgroups(B) && B->g_pers == B->persistent && B->g_lr == adam->lr &&
+                      B->g_b1 == adam->beta1 && B->g_b2 == adam->beta2 && B->g_eps == adam->eps;
+    if (!same) {
+        batch_drop_graph(B);
+        if (!B->capture_stream && hipStreamCreateWithFlags(&B->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return CT_ERR_DEVICE;
+        if (hipStreamBeginCapture(B->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return CT_ERR_DEVICE;
+        int rc = CT_OK;
+        for (int32_t it = 0; it < iters && rc == CT_OK; ++it)
+            rc = batch_launch(B, adam, 0, B->t_dev + (it & 1), B->t_dev + ((it + 1) & 1), B->capture_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(B->capture_stream, &g);
+        if (rc != CT_OK || ec != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            return rc != CT_OK ? rc : CT_ERR_DEVICE;
+        }
+        hipGraphExec_t ge = nullptr;
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return CT_ERR_DEVICE;
+        }
+        B->graph = g;
+        B->gexec = ge;
+        B->g_iters = iters;
+        B->g_split = batch_split(B);
+        B->g_wg = batch_workgroups(B);
+        B->g_pers = B->persistent;
+        B->g_lr = adam->lr; B->g_b1 = adam->beta1; B->g_b2 = adam->beta2; B->g_eps = adam->eps;
+    }
+    hipLaunchKernelGGL(ct::counter_set_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, B->t_dev, (int32_t)t0);
+    const int rc = err_of(hipGetLastError());
+    if (rc != CT_OK) return rc;
+    return err_of(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+}
+
+extern "C" int ct_batch_autotune(ct_batch* B, int32_t* chosen, void* stream) {
+    if (!B) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const ct_adam adam{0.f, 0.9f, 0.999f, 1e-8f, 1.f};   // lr 0: X stays as it is
+    const int keep_pers = B->persistent;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CT_ERR_DEVICE;
+    float best = 1e30f;
+    int best_split = 1, best_wg = 2 * B->n_cu, rc = CT_OK;
+    for (int split : {1, 2}) {
+        for (int per_cu : {1, 2, 3, 4}) {
+            rc = ct_batch_set_tuning(B, split, per_cu * B->n_cu, 1);
+            if (rc != CT_OK) break;
+            for (int w = 0; w < 2 && rc == CT_OK; ++w) rc = batch_launch(B, &adam, 1, nullptr, nullptr, st);
+            hipEventRecord(e0, st);
+            for (int r = 0; r < 5 && rc == CT_OK; ++r) rc = batch_launch(B, &adam, 2 + r, nullptr, nullptr, st);
+            hipEventRecord(e1, st);
+            if (rc != CT_OK) break;
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = CT_ERR_DEVICE; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; best_split = split; best_wg = per_cu * B->n_cu; }
+        }
+        if (rc != CT_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (const auto& k : B->skels) {
+        if (k.n == 0) continue;
+        const size_t bytes = (size_t)k.ld * (size_t)B->probs[&k - B->skels.data()]->D * sizeof(float);
+        hipMemsetAsync(k.M, 0, bytes, st);
+        hipMemsetAsync(k.V, 0, bytes, st);
+    }
+    if (rc != CT_OK) return rc;
+    rc = ct_batch_set_tuning(B, best_split, best_wg, keep_pers);
+    if (chosen) { chosen[0] = best_split; chosen[1] = best_wg; }
+    return rc;
 }

@@ -80,9 +80,37 @@ __device__ __forceinline__ void pair_hit(float px, float py, float pz, float r, 
 
 // Poses of the moved objects as seen by one lane's step: placed by an earlier
 // step (at P(rho_j), a particle variable) or still at the initial pose.
-template <int K>
-struct Movables {
-    float x[K], y[K], c[K], s[K];
+// The moved objects as seen by one lane's step k: object j (j < K) was
+// placed by an earlier step (at P(rho_j), a particle variable) or is still
+// at its initial pose (tables).  With the skeleton length known at compile
+// time (KT > 0) the lane keeps the K poses in registers and the loops over
+// them unroll; KT = 0 reads K at run time and the poses from the particle's
+// staged placements in LDS (the many-skeleton kernel).
+template <int KT>
+struct MoveCtx {
+    float x[KT], y[KT], c[KT], s[KT];
+    int k;
+    __device__ __forceinline__ int count() const { return KT; }
+    __device__ __forceinline__ void pose(const Tables* __restrict__, int j, float& bx, float& by, float& bc,
+                                         float& bs) const {
+        bx = x[j]; by = y[j]; bc = c[j]; bs = s[j];
+    }
+};
+
+template <>
+struct MoveCtx<0> {
+    const float4* plc;   // plc[j * pstride] = (x, y, cos yaw, sin yaw) of rho_j
+    int pstride;
+    int K, k;
+    __device__ __forceinline__ int count() const { return K; }
+    __device__ __forceinline__ void pose(const Tables* __restrict__ T, int j, float& bx, float& by, float& bc,
+                                         float& bs) const {
+        const bool placed = j < k;
+        const float4 pl = plc[j * pstride];
+        const Box& O = T->obj0[j];
+        bx = placed ? pl.x : O.cx; by = placed ? pl.y : O.cy;
+        bc = placed ? pl.z : O.c; bs = placed ? pl.w : O.s;
+    }
 };
 
 // A run of NB spheres of one lane against every box of step k: static boxes
@@ -92,11 +120,11 @@ struct Movables {
 // the box.  Accumulates the unweighted penetration, each sphere's weighted
 // centre gradient, and the weighted gradient with respect to the placements
 // rho_j of boxes placed by earlier steps.
-template <int K, int NB, bool GRAD>
-__device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const Movables<K>& mb, int k,
+template <int KT, int NB, bool GRAD>
+__device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const MoveCtx<KT>& mc,
                                              const float (&cx)[NB], const float (&cy)[NB], const float (&cz)[NB],
                                              const float (&r)[NB], float lam, float& pen_sum, float (&gx)[NB],
-                                             float (&gy)[NB], float (&gz)[NB], float (&gr)[K][3]) {
+                                             float (&gy)[NB], float (&gz)[NB], float* __restrict__ gr) {
     float r2[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) r2[m] = r[m] * r[m];
@@ -127,20 +155,23 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
         }
     }
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const float bz = T->obj0[j].cz, hx = T->obj0[j].hx, hy = T->obj0[j].hy, hz = T->obj0[j].hz;
-        const bool on = j != k;   // the step's own object is held, not an obstacle
+    for (int j = 0; j < mc.count(); ++j) {   // wave-uniform trip count
+        const Box O = T->obj0[j];
+        const bool placed = j < mc.k;
+        float bx, by, bc, bs;
+        mc.pose(T, j, bx, by, bc, bs);
+        const bool on = j != mc.k;   // the step's own object is held, not an obstacle
         bool act[NB];
         bool any = false;
         float dx[NB], dy[NB], px[NB], py[NB], pz[NB];
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
-            dx[m] = cx[m] - mb.x[j];
-            dy[m] = cy[m] - mb.y[j];
-            px[m] = mb.c[j] * dx[m] + mb.s[j] * dy[m];
-            py[m] = mb.c[j] * dy[m] - mb.s[j] * dx[m];
-            pz[m] = cz[m] - bz;
-            act[m] = on && box_d2(px[m], py[m], pz[m], hx, hy, hz) < r2[m];
+            dx[m] = cx[m] - bx;
+            dy[m] = cy[m] - by;
+            px[m] = bc * dx[m] + bs * dy[m];
+            py[m] = bc * dy[m] - bs * dx[m];
+            pz[m] = cz[m] - O.cz;
+            act[m] = on && box_d2(px[m], py[m], pz[m], O.hx, O.hy, O.hz) < r2[m];
             any |= act[m];
         }
         if (any) {
@@ -148,16 +179,16 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
             for (int m = 0; m < NB; ++m) {
                 if (act[m]) {
                     float pen, ax, ay, az;
-                    pair_hit(px[m], py[m], pz[m], r[m], mb.c[j], mb.s[j], hx, hy, hz, lam, pen, ax, ay, az);
+                    pair_hit(px[m], py[m], pz[m], r[m], bc, bs, O.hx, O.hy, O.hz, lam, pen, ax, ay, az);
                     pen_sum += pen;
                     if (GRAD) {
                         gx[m] += ax; gy[m] += ay; gz[m] += az;
-                        if (j < k) {
+                        if (placed) {
                             // moving the box by d equals moving the sphere by -d; turning it
                             // about its own vertical axis equals turning the sphere back
-                            gr[j][0] -= ax;
-                            gr[j][1] -= ay;
-                            gr[j][2] -= dx[m] * ay - dy[m] * ax;
+                            gr[3 * j] -= ax;
+                            gr[3 * j + 1] -= ay;
+                            gr[3 * j + 2] -= dx[m] * ay - dy[m] * ax;
                         }
                     }
                 }
@@ -197,10 +228,10 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
 // lane si of a slot takes table entries s0 + si + SPLIT j, j = j0 .. j0+NB-1
 // (entries past the link's end get radius 0, which never penetrates).
 // Accumulates the link's wrench (force f, moment tq about the world origin).
-template <int K, int SPLIT, int NB, bool GRAD>
+template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, int s1, int j0, int si,
-                                          const float R[9], const float t[3], const Movables<K>& mb, int k,
-                                          float lam, float& coll, float f[3], float tq[3], float (&gr)[K][3]) {
+                                          const float R[9], const float t[3], const MoveCtx<KT>& mc, float lam,
+                                          float& coll, float f[3], float tq[3], float* __restrict__ gr) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -220,7 +251,7 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
         gx[m] = gy[m] = gz[m] = 0.f;
     }
     float pen = 0.f;
-    run_vs_world<K, NB, GRAD>(T, mb, k, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
     coll += pen;
     if (GRAD) {
 #pragma unroll
@@ -235,25 +266,25 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
 
 // All robot spheres of link L: runs of 2, then 1, over the (wave-uniform)
 // number of entries each lane of the slot handles.
-template <int K, int SPLIT, bool GRAD>
+template <int KT, int SPLIT, bool GRAD>
 __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L, int si, const float R[9],
-                                             const float t[3], const Movables<K>& mb, int k, float lam,
-                                             float& coll, float f[3], float tq[3], float (&gr)[K][3]) {
+                                             const float t[3], const MoveCtx<KT>& mc, float lam, float& coll,
+                                             float f[3], float tq[3], float* __restrict__ gr) {
     const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
     const int per_lane = (s1 - s0 + SPLIT - 1) / SPLIT;
     int j = 0;
-    for (; j + RUN <= per_lane; j += RUN) robot_run<K, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mb, k, lam, coll, f, tq, gr);
-    for (; j < per_lane; ++j) robot_run<K, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mb, k, lam, coll, f, tq, gr);
+    for (; j + RUN <= per_lane; j += RUN) robot_run<KT, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mc, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j) robot_run<KT, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mc, lam, coll, f, tq, gr);
 }
 
 // Runs of object spheres (table osl, object frame) transformed by (R, t):
 // lane si takes entries si + SPLIT j.  Returns the penetration sum; with GRAD
 // accumulates the force and the moment about the world origin.
-template <int K, int SPLIT, int NB, bool GRAD>
+template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const float4* __restrict__ osl, int nos,
-                                           int j0, int si, const float R[9], const float t[3],
-                                           const Movables<K>& mb, int k, float lam, float& coll, float f[3],
-                                           float tq[3], float (&gr)[K][3]) {
+                                           int j0, int si, const float R[9], const float t[3], const MoveCtx<KT>& mc,
+                                           float lam, float& coll, float f[3], float tq[3],
+                                           float* __restrict__ gr) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -266,7 +297,7 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
         gx[m] = gy[m] = gz[m] = 0.f;
     }
     float pen = 0.f;
-    run_vs_world<K, NB, GRAD>(T, mb, k, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
     coll += pen;
     if (GRAD) {
 #pragma unroll
@@ -279,15 +310,15 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
     }
 }
 
-template <int K, int SPLIT, bool GRAD>
+template <int KT, int SPLIT, bool GRAD>
 __device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const float4* __restrict__ osl,
                                                int nos, int si, const float R[9], const float t[3],
-                                               const Movables<K>& mb, int k, float lam, float& coll, float f[3],
-                                               float tq[3], float (&gr)[K][3]) {
+                                               const MoveCtx<KT>& mc, float lam, float& coll, float f[3],
+                                               float tq[3], float* __restrict__ gr) {
     const int per_lane = (nos + SPLIT - 1) / SPLIT;
     int j = 0;
-    for (; j + RUN <= per_lane; j += RUN) object_run<K, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mb, k, lam, coll, f, tq, gr);
-    for (; j < per_lane; ++j) object_run<K, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mb, k, lam, coll, f, tq, gr);
+    for (; j + RUN <= per_lane; j += RUN) object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j) object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, lam, coll, f, tq, gr);
 }
 
 // dist_from_bounds of v against [lo, hi] and its gradient (scaled by lam).
@@ -321,13 +352,14 @@ struct LaneOut {
 // dJ/dq of this configuration into gq (folded onto the joint axes from
 // world-frame wrenches: dJ/dq_j = z_j . tau + (o_j x z_j) . f for the wrench
 // of everything beyond joint j), and the grasp / placement partials gg, gr.
-template <int K, int SPLIT, bool GRAD>
-__device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const float4* __restrict__ osl_k, int k,
-                                            int si, const float q[CT_N_JOINTS], bool held, bool kin, bool placing,
-                                            float lam, const Movables<K>& mb, float gx, float gy, float gz,
+template <int KT, int SPLIT, bool GRAD>
+__device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const float4* __restrict__ osl_k, int si,
+                                            const float q[CT_N_JOINTS], bool held, bool kin, bool placing,
+                                            float lam, const MoveCtx<KT>& mc, float gx, float gy, float gz,
                                             float g_c, float g_s, float rho_x, float rho_y, float rho_c,
                                             float rho_s, float& coll, float gq[CT_N_JOINTS], float gg[4],
-                                            float (&gr)[K][3], float& kin_pos, float& kin_rot) {
+                                            float* __restrict__ gr, float& kin_pos, float& kin_rot) {
+    const int k = mc.k;
     // Joint axis S_j = (z_j, o_j x z_j) of joint j+1 (z of frame j through its
     // origin).  dJ/dq_j = <S_j, wrench of links j+1..8>
     //                   = <S_j, total wrench> - <S_j, wrench of links 1..j>;
@@ -363,11 +395,11 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
             R[3 * rr + 1] = ca * w + r2 * sa;
             R[3 * rr + 2] = r2 * ca - sa * w;
         }
-        link_spheres<K, SPLIT, GRAD>(T, i + 1, si, R, t, mb, k, lam, coll, f, tq, gr);
+        link_spheres<KT, SPLIT, GRAD>(T, i + 1, si, R, t, mc, lam, coll, f, tq, gr);
     }
     // ---- tool frame: tool spheres, the held object, the kinematic constraint
     const float te[3] = {t[0] + R[2] * T->tool_d, t[1] + R[5] * T->tool_d, t[2] + R[8] * T->tool_d};
-    link_spheres<K, SPLIT, GRAD>(T, 8, si, R, te, mb, k, lam, coll, f, tq, gr);
+    link_spheres<KT, SPLIT, GRAD>(T, 8, si, R, te, mc, lam, coll, f, tq, gr);
 
     if (held) {
         // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
@@ -383,7 +415,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                              te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
                              te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        object_spheres<K, SPLIT, GRAD>(T, osl_k, T->n_os, si, RO, tO, mb, k, lam, coll, fo, to, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, si, RO, tO, mc, lam, coll, fo, to, gr);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
             // object turns about the tool z-axis through the tool origin
@@ -432,9 +464,9 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                 gg[1] -= -Ps * nx + Pc * ny;
                 gg[2] -= nz;
                 if (placing) {
-                    gr[k][0] -= nx;
-                    gr[k][1] -= ny;
-                    gr[k][2] -= -Rgy * nx + Rgx * ny;
+                    gr[3 * k] -= nx;
+                    gr[3 * k + 1] -= ny;
+                    gr[3 * k + 2] -= -Rgy * nx + Rgx * ny;
                 }
             }
             if (sw > 0.f) {
@@ -447,7 +479,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                 // target about world z raises it by u_w . z
                 tq[0] -= lr * uw0; tq[1] -= lr * uw1; tq[2] -= lr * uw2;
                 gg[3] += lr * uw2;
-                if (placing) gr[k][2] += lr * uw2;
+                if (placing) gr[3 * k + 2] += lr * uw2;
             }
         }
     }
@@ -492,36 +524,45 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
 // A waypoint's gradient goes to the transition's end (share s, this slot's
 // own configuration) and start (share 1 - s, the previous slot's
 // configuration, returned as the "foreign" partial).
-// Writes this lane's share of every gradient partial into part[0 .. NP):
-// [0,7) own q, [7,11) grasp, [11, 11+3K) placements, [11+3K, 18+3K) foreign q.
-template <int K, int SPLIT, int MODE>
+// Every lane writes its own gradient partials (no cross-lane reduction) to
+// part[0 .. 18+3K): [0,7) own q, [7,11) grasp, [11, 11+3K) placements
+// (accumulated in place), [11+3K, 18+3K) foreign q.
+template <int KT, int SPLIT, int MODE>
 __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
-                                             int xs_stride, const float4* __restrict__ osl, int slot, int si,
+                                             int xs_stride, const float4* __restrict__ plc,
+                                             const float4* __restrict__ osl, int K_rt, int slot, int si,
                                              float* __restrict__ part, float* __restrict__ terms,
                                              int64_t term_ld, int64_t i_glob, bool write_terms) {
     constexpr bool GRAD = MODE != MODE_COST;
+    const int K = KT ? KT : K_rt;
     const int k = slot >> 1;
     const bool placing = slot & 1;
     auto X = [&](int d) { return xs[d * xs_stride]; };
     const int b0 = CT_STEP_DIM * k;
+    float* gr = part + 11;   // placement partials, this lane's own
 
     const float gx = X(b0 + 14), gy = X(b0 + 15), gz = X(b0 + 16), gyaw = X(b0 + 17);
     float g_s, g_c;
     sincosf(gyaw, &g_s, &g_c);
-    const float rho_x = X(b0 + 18), rho_y = X(b0 + 19), rho_yaw = X(b0 + 20);
-    float rho_s, rho_c;
-    sincosf(rho_yaw, &rho_s, &rho_c);
-
-    Movables<K> mb;
+    const float4 own = plc[k * xs_stride];
+    const float rho_x = own.x, rho_y = own.y, rho_c = own.z, rho_s = own.w;
+    MoveCtx<KT> mc;
+    if constexpr (KT > 0) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        float sj, cj;
-        sincosf(X(CT_STEP_DIM * j + 20), &sj, &cj);
-        const bool placed = j < k;
-        mb.x[j] = placed ? X(CT_STEP_DIM * j + 18) : T->obj0[j].cx;
-        mb.y[j] = placed ? X(CT_STEP_DIM * j + 19) : T->obj0[j].cy;
-        mb.c[j] = placed ? cj : T->obj0[j].c;
-        mb.s[j] = placed ? sj : T->obj0[j].s;
+        for (int j = 0; j < KT; ++j) {
+            const bool placed = j < k;
+            const float4 pl = plc[j * xs_stride];
+            mc.x[j] = placed ? pl.x : T->obj0[j].cx;
+            mc.y[j] = placed ? pl.y : T->obj0[j].cy;
+            mc.c[j] = placed ? pl.z : T->obj0[j].c;
+            mc.s[j] = placed ? pl.w : T->obj0[j].s;
+        }
+        mc.k = k;
+    } else {
+        mc = MoveCtx<0>{plc, xs_stride, K, k};
+    }
+    if (GRAD) {
+        for (int j = 0; j < 3 * K; ++j) gr[j] = 0.f;
     }
 
     // this slot's configuration (the transition's end b, row qb_row of the
@@ -537,11 +578,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
 #pragma unroll
     for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = gqa[j] = 0.f;
     float gg[4] = {0.f, 0.f, 0.f, 0.f};
-    float gr[K][3];
-#pragma unroll
-    for (int j = 0; j < K; ++j) gr[j][0] = gr[j][1] = gr[j][2] = 0.f;
     float coll = 0.f, coll_m = 0.f, kin_pos = 0.f, kin_rot = 0.f;
-    const float* osl_k = reinterpret_cast<const float*>(osl) + 4 * k * CT_MAX_OBJ_SPHERES;
+    const float4* osl_k = osl + k * CT_MAX_OBJ_SPHERES;
 
     // waypoints w = 1..W of the transition, then the configuration itself
     for (int w = 1; w <= W + 1; ++w) {
@@ -559,9 +597,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         // along the holding transition
         const bool held = key || placing;
         const float lam = key ? T->w[W_COLL] : T->w[W_MCOLL];
-        config_pass<K, SPLIT, GRAD>(T, reinterpret_cast<const float4*>(osl_k), k, si, q, held, key, placing, lam,
-                                    mb, gx, gy, gz, g_c, g_s, rho_x, rho_y, rho_c, rho_s, cw, gw, gg, gr, kin_pos,
-                                    kin_rot);
+        config_pass<KT, SPLIT, GRAD>(T, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
+                                 rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot);
         if (key) coll += cw; else coll_m += cw;
         if (GRAD) {
 #pragma unroll
@@ -617,14 +654,13 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
         const float tp[3] = {rho_x, rho_y, T->place_z[k]};
         float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
-        object_spheres<K, SPLIT, GRAD>(T, reinterpret_cast<const float4*>(osl_k), T->n_os, si, Rp, tp, mb, k, lc,
-                                       coll_obj, fp, mp, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
         if (GRAD) {
             // translation: the force; turning about the vertical through the
             // placement origin: z of the moment about that point
-            gr[k][0] += fp[0];
-            gr[k][1] += fp[1];
-            gr[k][2] += mp[2] - (tp[0] * fp[1] - tp[1] * fp[0]);
+            gr[3 * k] += fp[0];
+            gr[3 * k + 1] += fp[1];
+            gr[3 * k + 2] += mp[2] - (tp[0] * fp[1] - tp[1] * fp[0]);
         }
     } else if (si == 0) {
         // StablePlace containment: footprint corners inside the region
@@ -637,55 +673,40 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             float gcr[2];
             place += bounds_dist<2>(cv, T->region_lo, T->region_hi, lpl, gcr);
             if (GRAD) {
-                gr[k][0] += gcr[0];
-                gr[k][1] += gcr[1];
-                gr[k][2] += -vy * gcr[0] + vx * gcr[1];
+                gr[3 * k] += gcr[0];
+                gr[3 * k + 1] += gcr[1];
+                gr[3 * k + 2] += -vy * gcr[0] + vx * gcr[1];
             }
         }
         if (slot == 1 && T->goal) {
             // MinimizeObjDist: sum of pairwise distances of the placements
             const float lg = T->w[W_GOAL];
-#pragma unroll
             for (int a = 0; a < K; ++a)
-#pragma unroll
                 for (int b = a + 1; b < K; ++b) {
-                    const float dx = X(CT_STEP_DIM * a + 18) - X(CT_STEP_DIM * b + 18);
-                    const float dy = X(CT_STEP_DIM * a + 19) - X(CT_STEP_DIM * b + 19);
+                    const float dx = plc[a * xs_stride].x - plc[b * xs_stride].x;
+                    const float dy = plc[a * xs_stride].y - plc[b * xs_stride].y;
                     const float dz = T->place_z[a] - T->place_z[b];
                     const float dist = sqrtf(dx * dx + dy * dy + dz * dz);
                     goal += dist;
                     if (GRAD && dist > 0.f) {
                         const float sc = lg / dist;
-                        gr[a][0] += dx * sc; gr[a][1] += dy * sc;
-                        gr[b][0] -= dx * sc; gr[b][1] -= dy * sc;
+                        gr[3 * a] += dx * sc; gr[3 * a + 1] += dy * sc;
+                        gr[3 * b] -= dx * sc; gr[3 * b + 1] -= dy * sc;
                     }
                 }
         }
     }
 
-    // ---- combine the SPLIT lanes of this slot
+    // ---- penetration sums of the slot (all SPLIT lanes contribute)
     coll = split_sum<SPLIT>(coll);
     coll_m = split_sum<SPLIT>(coll_m);
     coll_obj = split_sum<SPLIT>(coll_obj);
-    if (GRAD) {
-#pragma unroll
-        for (int j = 0; j < CT_N_JOINTS; ++j) {
-            gq[j] = split_sum<SPLIT>(gq[j]);
-            gqa[j] = split_sum<SPLIT>(gqa[j]);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) gg[j] = split_sum<SPLIT>(gg[j]);
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) gr[j][c] = split_sum<SPLIT>(gr[j][c]);
-    }
 
     LaneOut out;
     const float* w = T->w;
     const float* e = T->eps;
     float gsum = 0.f;
-    if (si == 0 && GRAD) {
+    if (GRAD) {
 #pragma unroll
         for (int j = 0; j < CT_N_JOINTS; ++j) {
             part[j] = gq[j];
@@ -694,10 +715,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) { part[11 + 3 * j + c] = gr[j][c]; gsum += gr[j][c]; }
+        for (int j = 0; j < 3 * K; ++j) gsum += gr[j];
     }
     const float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll +
                      w[W_MCOLL] * coll_m + w[W_TRAJ] * traj;
@@ -711,7 +729,9 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         ok = ok && place <= e[E_PLACE];
     }
     out.traj = traj;
-    const bool fin = __builtin_isfinite(out.cost + gsum);
+    // a slot is finite when its own cost and every lane's partials are
+    const float gtot = split_sum<SPLIT>(gsum);
+    const bool fin = __builtin_isfinite(out.cost) && __builtin_isfinite(gtot);
     out.flags = (ok ? 1 : 0) | (fin ? 2 : 0);
 
     if (write_terms && si == 0) {
@@ -738,53 +758,71 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
 }
 
 // ---------------------------------------------------------------------------
-template <int K, int SPLIT, int MODE>
-__global__ __launch_bounds__(WG) void particle_kernel(
-    const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
-    float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
-    int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
-    float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
-    int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw) {
-    constexpr int SLOTS = 2 * K;
-    constexpr int LPP = SLOTS * SPLIT;
-    constexpr int P = WG / LPP;
-    constexpr int D = CT_STEP_DIM * K;
-    constexpr int NP = 18 + 3 * K;
+// Workgroup-level tile: P particles x 2K slots x SPLIT lanes, K at run time.
 
-    __shared__ float xs[D * P];
-    __shared__ float part[P * SLOTS * NP];
-    __shared__ float cpart[P * SLOTS];
-    __shared__ float tpart[P * SLOTS];
-    __shared__ int flg[P * SLOTS];
-    __shared__ int okp[P];
-    __shared__ float4 osl[K * CT_MAX_OBJ_SPHERES];
-    __shared__ int any_sat;
+// Largest LDS footprint over K = 1..CT_MAX_STEPS for a given SPLIT:
+//   staged particles  D P = 21 K floor(128 / (K SPLIT))  <= 2688 / SPLIT floats
+//   placements        K P                                <= 128 / SPLIT float4
+//   lane partials     P 2K SPLIT (18 + 3K)                <= 256 (18 + 3 * 6) floats
+//   slot records      P 2K                                <= 256 / SPLIT
+template <int SPLIT>
+struct TileSmem {
+    float xs[2688 / SPLIT];
+    float4 plc[128 / SPLIT];
+    float part[WG * (18 + 3 * CT_MAX_STEPS)];
+    float cpart[WG / SPLIT];
+    float tpart[WG / SPLIT];
+    int flg[WG / SPLIT];
+    int okp[128 / SPLIT];
+    float4 osl[CT_MAX_STEPS * CT_MAX_OBJ_SPHERES];
+    int any_sat;
+};
 
+// What one tile reads and writes (one skeleton's buffers).
+struct TileIO {
+    const Tables* T;
+    float *X, *M, *V, *G, *cost, *terms;
+    uint8_t* mask;
+    int32_t* first_sat;
+    const uint8_t* frozen;
+    const float* gw;
+    int64_t n, ld;
+    float gscale;
+};
+
+
+template <int KT, int SPLIT, int MODE>
+__device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<SPLIT>& sm, float lr, float b1,
+                                         float b2, float eps, int32_t t) {
+    const Tables* __restrict__ T = io.T;
+    const int K = KT ? KT : T->K;
+    const int SLOTS = 2 * K;
+    const int LPP = SLOTS * SPLIT;
+    const int P = WG / LPP;
+    const int D = CT_STEP_DIM * K;
+    const int NP = 18 + 3 * K;
+    const int64_t n = io.n, ld = io.ld;
     const int tid = threadIdx.x;
-    // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
-    // 8 XCDs, so give each XCD a contiguous range of particle tiles; tiles
-    // that share cache lines of X, M and V then share one L2
-    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t p0 = tile * P;
-    // update number t: explicit, or one past the device counter of applied
-    // updates; a captured loop alternates two counter slots (read t_in,
-    // write t_out), so no launch writes a slot that its own workgroups read
-    const int32_t t = t_in ? *t_in + 1 : t_arg;
     const int32_t iter = t - 1;
-    if (t_out && blockIdx.x == 0 && threadIdx.x == 0) *t_out = t;
-    // stop-at-first: once an earlier iteration produced a satisfying
-    // particle, the remaining steps of a captured loop do nothing (every
-    // workgroup reads the same value: this launch only writes iter itself)
-    if (stop_at_first && first_sat && *first_sat < iter) return;
 
-    // phase 0: stage this workgroup's particles (coalesced along particles)
+    // phase 0: stage this tile's particles (coalesced along particles), the
+    // placements' poses, and the object sphere tables
     for (int idx = tid; idx < D * P; idx += WG) {
         const int d = idx / P, p = idx - d * P;
         const int64_t i = p0 + p;
-        xs[idx] = i < n ? X[d * ld + i] : 0.f;
+        sm.xs[idx] = i < n ? io.X[d * ld + i] : 0.f;
     }
-    for (int idx = tid; idx < K * CT_MAX_OBJ_SPHERES; idx += WG) osl[idx] = T->os[idx / CT_MAX_OBJ_SPHERES][idx % CT_MAX_OBJ_SPHERES];
-    if (tid == 0) any_sat = 0;
+    for (int idx = tid; idx < K * CT_MAX_OBJ_SPHERES; idx += WG)
+        sm.osl[idx] = T->os[idx / CT_MAX_OBJ_SPHERES][idx % CT_MAX_OBJ_SPHERES];
+    if (tid == 0) sm.any_sat = 0;
+    __syncthreads();
+    for (int idx = tid; idx < K * P; idx += WG) {
+        const int j = idx / P, p = idx - j * P;
+        const float* col = sm.xs + p;
+        float sj, cj;
+        sincosf(col[(CT_STEP_DIM * j + 20) * P], &sj, &cj);
+        sm.plc[idx] = make_float4(col[(CT_STEP_DIM * j + 18) * P], col[(CT_STEP_DIM * j + 19) * P], cj, sj);
+    }
     __syncthreads();
 
     // phase 1: every lane evaluates its slot
@@ -794,13 +832,14 @@ __global__ __launch_bounds__(WG) void particle_kernel(
             const int rem = tid - p * LPP;
             const int slot = rem / SPLIT, si = rem - slot * SPLIT;
             const int64_t i = p0 + p;
-            const bool wt = (MODE == MODE_COST) && terms != nullptr && i < n;
-            const LaneOut o = lane_slot<K, SPLIT, MODE>(T, xs + p, P, osl, slot, si,
-                                                        part + (p * SLOTS + slot) * NP, terms, ld, i, wt);
+            const bool wt = (MODE == MODE_COST) && io.terms != nullptr && i < n;
+            const LaneOut o = lane_slot<KT, SPLIT, MODE>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
+                                                     sm.part + (size_t)((p * SLOTS + slot) * SPLIT + si) * NP,
+                                                     io.terms, ld, i, wt);
             if (si == 0) {
-                cpart[p * SLOTS + slot] = o.cost;
-                tpart[p * SLOTS + slot] = o.traj;
-                flg[p * SLOTS + slot] = o.flags;
+                sm.cpart[p * SLOTS + slot] = o.cost;
+                sm.tpart[p * SLOTS + slot] = o.traj;
+                sm.flg[p * SLOTS + slot] = o.flags;
             }
         }
     }
@@ -811,67 +850,134 @@ __global__ __launch_bounds__(WG) void particle_kernel(
         const int64_t i = p0 + tid;
         float J = 0.f;
         int m = 1, ok = 1;
-#pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            J += cpart[tid * SLOTS + s];
-            m &= flg[tid * SLOTS + s] & 1;
-            ok &= (flg[tid * SLOTS + s] >> 1) & 1;
+            J += sm.cpart[tid * SLOTS + s];
+            m &= sm.flg[tid * SLOTS + s] & 1;
+            ok &= (sm.flg[tid * SLOTS + s] >> 1) & 1;
         }
         ok &= __builtin_isfinite(J) ? 1 : 0;
         m &= __builtin_isfinite(J) ? 1 : 0;
-        okp[tid] = ok;
+        sm.okp[tid] = ok;
         if (i < n) {
-            if (MODE == MODE_COST && terms && T->traj_term >= 0) {
+            if (MODE == MODE_COST && io.terms && T->traj_term >= 0) {
                 float tl = 0.f;
-#pragma unroll
-                for (int s = 0; s < SLOTS; ++s) tl += tpart[tid * SLOTS + s];
-                terms[(int64_t)T->traj_term * ld + i] = tl;
+                for (int s = 0; s < SLOTS; ++s) tl += sm.tpart[tid * SLOTS + s];
+                io.terms[(int64_t)T->traj_term * ld + i] = tl;
             }
-            if (cost) cost[i] = J;
-            if (mask) mask[i] = (uint8_t)m;
-            if (m) any_sat = 1;
+            if (io.cost) io.cost[i] = J;
+            if (io.mask) io.mask[i] = (uint8_t)m;
+            if (m) sm.any_sat = 1;
         }
     }
     __syncthreads();
-    if (first_sat && tid == 0 && any_sat) atomicMin(first_sat, iter);
+    if (io.first_sat && tid == 0 && sm.any_sat) atomicMin(io.first_sat, iter);
 
-    if (MODE == MODE_COST) return;
-
-    // phase 2: sum each coordinate's partials (fixed order), then G or Adam
-    for (int idx = tid; idx < D * P; idx += WG) {
-        const int d = idx / P, p = idx - d * P;
-        const int64_t i = p0 + p;
-        if (i >= n) continue;
-        const int k = d / CT_STEP_DIM, r = d - CT_STEP_DIM * k;
-        const float* pp = part + p * SLOTS * NP;
-        float g;
-        constexpr int FQ = 11 + 3 * K;   // foreign-configuration partials
-        if (r < 7) {
-            // q_grasp of step k: its slot, plus the start of the holding transition
-            g = pp[(2 * k) * NP + r] + pp[(2 * k + 1) * NP + FQ + r];
-        } else if (r < 14) {
-            // q_place of step k: its slot, plus the start of the next free transition
-            g = pp[(2 * k + 1) * NP + (r - 7)];
-            if (k + 1 < K) g += pp[(2 * k + 2) * NP + FQ + (r - 7)];
-        } else if (r < 18) {
-            g = pp[(2 * k) * NP + 7 + (r - 14)] + pp[(2 * k + 1) * NP + 7 + (r - 14)];
-        } else {
-            g = 0.f;
+    if (MODE != MODE_COST) {
+        // phase 2: sum each coordinate's partials over slots and split lanes
+        // in a fixed order, then write G or apply Adam in place
+        const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
+        const int FQ = 11 + 3 * K;   // foreign-configuration partials
+        for (int idx = tid; idx < D * P; idx += WG) {
+            const int d = idx / P, p = idx - d * P;
+            const int64_t i = p0 + p;
+            if (i >= n) continue;
+            const int k = d / CT_STEP_DIM, r = d - CT_STEP_DIM * k;
+            const float* pp = sm.part + (size_t)p * SLOTS * SPLIT * NP;
+            auto lane = [&](int slot, int si) { return pp + (size_t)(slot * SPLIT + si) * NP; };
+            float g = 0.f;
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) g += pp[s * NP + 11 + 3 * k + (r - 18)];
+            for (int si = 0; si < SPLIT; ++si) {
+                if (r < 7) {
+                    // q_grasp of step k: its slot, plus the start of the holding transition
+                    g += lane(2 * k, si)[r] + lane(2 * k + 1, si)[FQ + r];
+                } else if (r < 14) {
+                    // q_place of step k: its slot, plus the start of the next free transition
+                    g += lane(2 * k + 1, si)[r - 7];
+                    if (k + 1 < K) g += lane(2 * k + 2, si)[FQ + (r - 7)];
+                } else if (r < 18) {
+                    g += lane(2 * k, si)[7 + (r - 14)] + lane(2 * k + 1, si)[7 + (r - 14)];
+                } else {
+                    for (int s = 0; s < SLOTS; ++s) g += lane(s, si)[11 + 3 * k + (r - 18)];
+                }
+            }
+            const int64_t a = d * ld + i;
+            if (MODE == MODE_GRAD) {
+                io.G[a] = io.gw ? io.gw[i] * g : g;
+            } else if (sm.okp[p] && !(io.frozen && io.frozen[d])) {
+                const float gs = io.gscale * g;
+                const float m1 = b1 * io.M[a] + (1.f - b1) * gs;
+                const float v1 = b2 * io.V[a] + (1.f - b2) * gs * gs;
+                const float mh = m1 / bc1, vh = v1 / bc2;
+                io.X[a] = sm.xs[idx] - lr * mh / (sqrtf(vh) + eps);
+                io.M[a] = m1;
+                io.V[a] = v1;
+            }
         }
-        const int64_t a = d * ld + i;
-        if (MODE == MODE_GRAD) {
-            G[a] = gw ? gw[i] * g : g;
-        } else if (okp[p] && !(frozen && frozen[d])) {
-            const float bc1 = 1.f - powf(b1, (float)t), bc2 = 1.f - powf(b2, (float)t);
-            const float gs = gscale * g;
-            const float m1 = b1 * M[a] + (1.f - b1) * gs;
-            const float v1 = b2 * V[a] + (1.f - b2) * gs * gs;
-            const float mh = m1 / bc1, vh = v1 / bc2;
-            X[a] = xs[idx] - lr * mh / (sqrtf(vh) + eps);
-            M[a] = m1;
-            V[a] = v1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One skeleton of KT steps: one workgroup per tile (XCD-aware tile order).
+template <int SPLIT, int MODE, int KT>
+__global__ __launch_bounds__(WG) void particle_kernel(
+    const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
+    float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
+    int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
+    float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
+    int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw) {
+    __shared__ TileSmem<SPLIT> sm;
+    // update number t: explicit, or one past the device counter of applied
+    // updates; a captured loop alternates two counter slots (read t_in,
+    // write t_out), so no launch writes a slot that its own workgroups read
+    const int32_t t = t_in ? *t_in + 1 : t_arg;
+    if (t_out && blockIdx.x == 0 && threadIdx.x == 0) *t_out = t;
+    // stop-at-first: once an earlier iteration produced a satisfying
+    // particle, the remaining steps of a captured loop do nothing (every
+    // workgroup reads the same value: this launch only writes iter itself)
+    if (stop_at_first && first_sat && *first_sat < t - 1) return;
+    // XCD-aware tile order: consecutive workgroups are dealt round-robin to the
+    // 8 XCDs, so give each XCD a contiguous range of particle tiles; tiles
+    // that share cache lines of X, M and V then share one L2
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale};
+    run_tile<KT, SPLIT, MODE>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
+}
+
+
+// Many skeletons of different lengths and sizes, one launch per iteration:
+// a fixed number of workgroups pull (skeleton, tile) items from a device
+// queue (items ordered by cost, largest first) until it is empty; the last
+// workgroup to leave resets the queue for the next launch.
+template <int SPLIT>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(const BatchSkel* __restrict__ skels,
+                                                   const int2* __restrict__ items, int32_t n_items,
+                                                   int32_t* __restrict__ queue, float lr, float b1, float b2,
+                                                   float eps, int32_t t_arg, const int32_t* __restrict__ t_in,
+                                                   int32_t* __restrict__ t_out) {
+    __shared__ TileSmem<SPLIT> sm;
+    __shared__ int item_s;
+    const int32_t t = t_in ? *t_in + 1 : t_arg;
+    if (t_out && blockIdx.x == 0 && threadIdx.x == 0) *t_out = t;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = atomicAdd(&queue[0], 1);
+        __syncthreads();
+        // the item is the same for the whole workgroup: make it wave-uniform
+        // so the skeleton's tables are read through the scalar cache
+        const int it = __builtin_amdgcn_readfirstlane(item_s);
+        __syncthreads();
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const BatchSkel& b = skels[w.x];
+        const TileIO io{b.T, b.X, b.M, b.V, nullptr, b.cost, nullptr, b.mask, b.first_sat, b.frozen, nullptr,
+                        b.n, b.ld, b.gscale};
+        run_tile<0, SPLIT, MODE_STEP>(io, (int64_t)w.y * tile_particles(b.T->K, SPLIT), sm, lr, b1, b2, eps, t);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&queue[0], 0);
+            atomicExch(&queue[1], 0);
         }
     }
 }

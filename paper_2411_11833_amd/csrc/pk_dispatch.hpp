@@ -1,4 +1,4 @@
-// Launch interface shared by the host library and the per-K kernel objects.
+// Launch interface shared by the host library and the kernel objects.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,13 +24,27 @@ struct PkArgs {
     const float* gw;         // per-particle gradient weights (gradient mode), or null
 };
 
+// one skeleton of a given length (each length has its own kernels)
 using PkFn = hipError_t (*)(const ct::Tables*, const PkArgs&, hipStream_t);
 
-// kernel launcher for `split` lanes per configuration and mode (ct::Mode);
-// defined in pk_instances.hip compiled once per K
-PkFn ct_pick_k1(int split, int mode);
-PkFn ct_pick_k2(int split, int mode);
-PkFn ct_pick_k3(int split, int mode);
-PkFn ct_pick_k4(int split, int mode);
-PkFn ct_pick_k5(int split, int mode);
-PkFn ct_pick_k6(int split, int mode);
+// persistent many-skeleton step
+struct BatchArgs {
+    const void* skels;       // device ct::BatchSkel[count]
+    const int2* items;       // device (skeleton, tile) list
+    int32_t n_items;
+    int32_t* queue;          // device int[2], zero between launches
+    int32_t n_workgroups;
+    AdamArgs a;
+    int32_t t;
+    const int32_t* t_in;
+    int32_t* t_out;
+};
+using BatchFn = hipError_t (*)(const BatchArgs&, hipStream_t);
+
+// defined in pk_instances.hip, compiled once per split (-DCT_SPLIT=1, 2, 4)
+PkFn ct_pick_s1(int K, int mode);
+PkFn ct_pick_s2(int K, int mode);
+PkFn ct_pick_s4(int K, int mode);
+BatchFn ct_batch_s1();
+BatchFn ct_batch_s2();
+BatchFn ct_batch_s4();

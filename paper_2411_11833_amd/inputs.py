@@ -326,6 +326,20 @@ def random_skeleton_problem(seed: int, robot: Robot, k_range=(1, 6), obs_range=(
     return Problem(robot, scene, sk)
 
 
+def batch_workload(seed: int = 0, count: int = 64, robot_seed: int = 0, n_range=(512, 8192)):
+    """Skeletons of uneven length (1-6 pick-place steps), each over its own
+    scene with 2-12 obstacles and its own particle count, log-uniform in
+    n_range and rounded to a multiple of 64.  Returns [(Problem, n)]."""
+    robot = make_robot(robot_seed, n_spheres=60)
+    rng = np.random.default_rng(np.random.SeedSequence([0xBA7C5, seed]))
+    out = []
+    for s in range(count):
+        prob = random_skeleton_problem(seed * 1000 + s, robot)
+        n = int(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1]))))
+        out.append((prob, max(64, (n // 64) * 64)))
+    return out
+
+
 # --------------------------------------------------------------------------
 # particles
 

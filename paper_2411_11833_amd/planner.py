@@ -157,6 +157,62 @@ def default_adam(n: int, lr: float = 1e-2) -> B.CtAdam:
     return B.CtAdam(lr, 0.9, 0.999, 1e-8, 1.0 / n)
 
 
+class GpuBatch:
+    """Many skeletons bound to their own particle buffers, stepped together by
+    one persistent launch per iteration (or, for comparison, one launch per
+    skeleton)."""
+
+    def __init__(self, problems: list, sizes: list[int], device="cuda", fixed_grasps: bool = True):
+        self.gps = [GpuProblem(p, device) for p in problems]
+        self.sizes = list(sizes)
+        self.device = torch.device(device)
+        self.X = [g.empty(n) for g, n in zip(self.gps, sizes)]
+        self.M = [g.empty(n) for g, n in zip(self.gps, sizes)]
+        self.V = [g.empty(n) for g, n in zip(self.gps, sizes)]
+        self.cost = [torch.empty(n, dtype=torch.float32, device=self.device) for n in sizes]
+        self.mask = [torch.empty(n, dtype=torch.uint8, device=self.device) for n in sizes]
+        self.first_sat = torch.full((len(sizes),), INT32_MAX, dtype=torch.int32, device=self.device)
+        self.frozen = [grasp_frozen(p, self.device) if fixed_grasps else None for p in problems]
+        ptr = lambda a: a.data_ptr() if a is not None else None  # noqa: E731
+        self.handle = B.ct_batch_create(
+            [g.handle for g in self.gps], [x.data_ptr() for x in self.X], [m.data_ptr() for m in self.M],
+            [v.data_ptr() for v in self.V], self.sizes, [x.shape[1] for x in self.X],
+            [c.data_ptr() for c in self.cost], [m.data_ptr() for m in self.mask],
+            [self.first_sat.data_ptr() + 4 * s for s in range(len(sizes))], [ptr(f) for f in self.frozen])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            B.ct_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def seed(self, seed: int):
+        for s, (g, n) in enumerate(zip(self.gps, self.sizes)):
+            g.seed_uniform(seed * 1000 + s, self.X[s], self.M[s], self.V[s], n)
+        self.first_sat.fill_(INT32_MAX)
+
+    def set_tuning(self, split=0, workgroups=0, persistent=True):
+        B.ct_batch_set_tuning(self.handle, split, workgroups, int(persistent))
+
+    def autotune(self):
+        return B.ct_batch_autotune(self.handle, _stream())
+
+    def step(self, t: int, adam: B.CtAdam):
+        B.ct_batch_step(self.handle, t, adam, _stream())
+
+    def optimize(self, t0: int, iters: int, adam: B.CtAdam):
+        B.ct_batch_optimize(self.handle, t0, iters, adam, _stream())
+
+    @property
+    def particles(self) -> int:
+        return sum(self.sizes)
+
+
 @dataclass
 class SolveResult:
     iters_budget: int

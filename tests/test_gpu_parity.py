@@ -401,3 +401,67 @@ def test_particle_cost_autograd_function():
     want = G0 * torch.cat([w, torch.zeros(Xd.shape[1] - n, device="cuda")])[None, :]
     assert torch.allclose(Xg.grad, want, rtol=1e-6, atol=1e-7)
     assert torch.all(Xg.grad[:, n:] == 0)
+
+
+# ----------------------------------------------------------------------------- many skeletons
+
+
+def _small_batch():
+    robot = I.make_robot(0, n_spheres=60)
+    probs = [I.random_skeleton_problem(s, robot) for s in (1, 2, 3, 4, 6, 9, 11)]   # K = 3 4 2 5 1 6 1
+    sizes = [131, 64, 200, 77, 256, 45, 96]
+    return probs, sizes
+
+
+@pytest.mark.parametrize("split", [1, 2])
+def test_batch_step_matches_per_skeleton_steps(split):
+    """One persistent launch over seven skeletons of lengths 1..6 gives the
+    per-skeleton ct_step results bit for bit."""
+    from paper_2411_11833_amd.planner import GpuBatch
+    probs, sizes = _small_batch()
+    assert {p.skeleton.n_steps for p in probs} == {1, 2, 3, 4, 5, 6}
+    b = GpuBatch(probs, sizes)
+    b.set_tuning(split=split, workgroups=37)
+    b.seed(5)
+    ref = [(x.clone(), m.clone(), v.clone()) for x, m, v in zip(b.X, b.M, b.V)]
+    adam = _adam(1)
+    for t in (1, 2, 3):
+        b.step(t, adam)
+    for s, (g, n) in enumerate(zip(b.gps, sizes)):
+        X, M, V = ref[s]
+        g.set_split(split)
+        c = torch.empty(n, device="cuda")
+        for t in (1, 2, 3):
+            g.step(X, M, V, n, t, _adam(n), frozen=b.frozen[s], cost=c)
+        torch.cuda.synchronize()
+        assert torch.equal(X, b.X[s]) and torch.equal(M, b.M[s]) and torch.equal(V, b.V[s]), s
+        assert torch.equal(c, b.cost[s]), s
+
+
+def test_batch_graph_and_separate_launches_agree():
+    from paper_2411_11833_amd.planner import GpuBatch
+    probs, sizes = _small_batch()
+    outs = []
+    for persistent in (True, False):
+        b = GpuBatch(probs, sizes)
+        b.set_tuning(split=1, workgroups=0, persistent=persistent)
+        b.seed(6)
+        b.optimize(0, 12, _adam(1))
+        b.optimize(12, 12, _adam(1))
+        torch.cuda.synchronize()
+        outs.append([x.clone() for x in b.X] + [c.clone() for c in b.cost])
+    for u, v in zip(*outs):
+        assert torch.equal(u, v)
+
+
+def test_batch_autotune_keeps_particles():
+    from paper_2411_11833_amd.planner import GpuBatch
+    probs, sizes = _small_batch()
+    b = GpuBatch(probs, sizes)
+    b.seed(7)
+    X0 = [x.clone() for x in b.X]
+    split, wg = b.autotune()
+    torch.cuda.synchronize()
+    assert split in (1, 2) and wg > 0
+    for x, x0, m, v in zip(b.X, X0, b.M, b.V):
+        assert torch.equal(x, x0) and torch.all(m == 0) and torch.all(v == 0)

@@ -359,3 +359,52 @@ def to_soa(x_rows: np.ndarray, ld: int | None = None, dtype=np.float32) -> np.nd
     out = np.zeros((d, ld), dtype=dtype)
     out[:, :n] = x_rows.T
     return out
+
+
+# --------------------------------------------------------------------------
+# seed proposer: scene features and initial network weights
+
+
+def scene_features(prob: Problem, n_movable: int = 4, n_obstacles: int = 8) -> np.ndarray:
+    """One row of 10 numbers per object -- centre (x, y, z), roll, pitch, yaw,
+    side lengths (sx, sy, sz), movable flag -- movable objects first in the
+    skeleton's order, then obstacles; missing objects are zero rows.  Boxes
+    here rest flat on the table, so roll = pitch = 0."""
+    rows = []
+    objs = prob.scene.objects
+    for k in range(n_movable):
+        if k < prob.skeleton.n_steps:
+            o = objs[prob.skeleton.object_of_step[k]]
+            rows.append([o[0], o[1], o[2], 0.0, 0.0, o[3], 2 * o[4], 2 * o[5], 2 * o[6], 1.0])
+        else:
+            rows.append([0.0] * 10)
+    obs = prob.scene.obstacles
+    for j in range(n_obstacles):
+        if j < len(obs):
+            o = obs[j]
+            rows.append([o[0], o[1], o[2], 0.0, 0.0, o[3], 2 * o[4], 2 * o[5], 2 * o[6], 0.0])
+        else:
+            rows.append([0.0] * 10)
+    return np.asarray(rows, dtype=np.float64).reshape(-1)
+
+
+def angle_dims(prob: Problem) -> np.ndarray:
+    """1 for particle coordinates that are angles of free yaw (grasp and
+    placement yaw), 0 elsewhere."""
+    w = np.zeros(prob.dim, dtype=np.uint8)
+    for k in range(prob.skeleton.n_steps):
+        w[STEP_DIM * k + 17] = 1
+        w[STEP_DIM * k + 20] = 1
+    return w
+
+
+def mlp_init(dims, seed: int) -> np.ndarray:
+    """Flat float32 parameters (per layer W [out][in] row-major, then b) drawn
+    U(-1/sqrt(in), 1/sqrt(in)), the usual default for linear layers."""
+    rng = np.random.default_rng(np.random.SeedSequence([0x31F, seed]))
+    parts = []
+    for i, o in dims:
+        a = 1.0 / math.sqrt(i)
+        parts.append(rng.uniform(-a, a, i * o))
+        parts.append(rng.uniform(-a, a, o))
+    return np.concatenate(parts).astype(np.float32)

@@ -30,6 +30,7 @@ import numpy as np
 METRIC = "particle-iters/s (fwd+bwd+Adam); time-to-satisfy: plain vs learned seeds"
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
 
 
 def parse():
@@ -48,6 +49,12 @@ def parse():
     ap.add_argument("--no-motion", action="store_true", help="skip the waypoint motion-cost measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
     ap.add_argument("--batch-iters", type=int, default=300)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
+    ap.add_argument("--learned-scenes", type=int, default=400, help="training scenes for the seed proposer")
+    ap.add_argument("--learned-keep", type=int, default=500, help="particles kept per training scene")
+    ap.add_argument("--learned-epochs", type=int, default=10)
+    ap.add_argument("--eval-scenes", type=int, default=20, help="held-out scenes, learned vs uniform seeds")
+    ap.add_argument("--eval-budget", type=int, default=2000, help="Adam iterations per held-out solve")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
@@ -84,6 +91,76 @@ def cpu_baseline(prob, budget_s: float):
             "kind": "oracle",
             "sample": f"{n} particles x {it} iterations of the same 84-D packing CSP, FP64 autodiff, "
                       f"{dt:.1f} s"}
+
+
+def learned_seeds(args, dev, n, iters, q):
+    import torch
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd import seeds as SD
+
+    lg = lambda m: log("[bench] " + m, q)  # noqa: E731
+    t0 = time.perf_counter()
+    data = SD.collect(range(10000, 10000 + args.learned_scenes), robot_seed=args.robot_seed, n=n, iters=iters,
+                      keep=args.learned_keep, log=lg)
+    t_collect = time.perf_counter() - t0
+    lg(f"learned: {len(data.targets)} training particles from {args.learned_scenes} scenes in {t_collect:.1f} s "
+       f"({data.fully_satisfying} fully satisfying, mean satisfied constraints {data.n_sat.mean():.1f})")
+    stats = SD.Stats.of(data)
+    batch, draws = 4096, 8
+    mlp = SD.GpuMlp(max_rows=batch * draws, device=dev)
+    mlp.set_params(torch.from_numpy(I.mlp_init(mlp.dims, 0)))
+    tl = SD.train(mlp, data, stats, epochs=args.learned_epochs, batch=batch, n_draws=draws, lr=1e-3, seed=0)
+    train_tflops = tl.flops / tl.seconds / 1e12
+    lg(f"learned: {tl.steps} IMLE steps in {tl.seconds:.2f} s ({train_tflops:.1f} TFLOP/s on the matrix "
+       f"products), loss {tl.losses[0]:.3f} -> {tl.losses[-1]:.3f}")
+    prop = SD.Proposer(mlp, stats)
+    # seed inference alone (8192 seeds of one scene)
+    eprob = I.packing(args.robot_seed, 20000)
+    pre = prop.prepare(eprob)
+    from paper_2411_11833_amd.planner import GpuProblem
+    eg = GpuProblem(eprob, dev)
+    Xs, Ms, Vs = eg.empty(n), eg.empty(n), eg.empty(n)
+    prop.seed(pre, 1, Xs, Ms, Vs, n)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for r in range(20):
+        prop.seed(pre, 2 + r, Xs, Ms, Vs, n)
+    e1.record()
+    torch.cuda.synchronize()
+    sample_s = e0.elapsed_time(e1) / 1e3 / 20
+    eg.close()
+    cmpr = SD.compare(prop, range(20000, 20000 + args.eval_scenes), n=n, budget=args.eval_budget,
+                      robot_seed=args.robot_seed, log=lg)
+    tu = [r.time_to_first_s for r in cmpr.uniform]
+    tlr = [r.time_to_first_s for r in cmpr.learned]
+    cov_u, cov_l, rate, at_u, at_l = SD.equal_rate_times(tu, cmpr.learned_fallback)
+    res = {
+        "kind": "time to the first satisfying particle, plain optimizer (fixed grasps, stop at first) from "
+                "uniform seeds vs from learned seeds (learned run falls back to uniform seeds when it finds "
+                "nothing within the budget); GPU time incl. initialization and seed inference",
+        "train": {"scenes": args.learned_scenes, "particles": int(len(data.targets)),
+                  "fully_satisfying": int(data.fully_satisfying), "collect_s": t_collect,
+                  "steps": tl.steps, "epochs": args.learned_epochs, "batch": batch, "draws": draws,
+                  "train_s": tl.seconds, "loss_first_epoch": tl.losses[0], "loss_last_epoch": tl.losses[-1],
+                  "matrix_tflops": train_tflops, "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
+                  "mfma_frac": train_tflops / PEAK_BF16_MFMA_TFLOPS},
+        "sample_8192_us": sample_s * 1e6,
+        "eval": {"scenes": len(cmpr.scenes), "particles": n, "budget_iters": args.eval_budget,
+                 "uniform_first_iter": [r.first_sat_iter for r in cmpr.uniform],
+                 "learned_first_iter": [r.first_sat_iter for r in cmpr.learned],
+                 "uniform_time_s": tu, "learned_time_s": tlr,
+                 "learned_with_fallback_time_s": cmpr.learned_fallback,
+                 "uniform_satisfied_at_end": [r.satisfied for r in cmpr.uniform],
+                 "learned_satisfied_at_end": [r.satisfied for r in cmpr.learned]},
+        "coverage_uniform": cov_u, "coverage_learned_with_fallback": cov_l,
+        "equal_satisfaction_rate": rate,
+        "time_at_equal_rate_uniform_s": at_u, "time_at_equal_rate_learned_s": at_l,
+    }
+    lg(f"learned: coverage uniform {cov_u:.2f} vs learned(+fallback) {cov_l:.2f}; at rate {rate:.2f}: "
+       f"uniform {at_u} s vs learned {at_l} s; 8192 seeds in {sample_s * 1e6:.0f} us")
+    mlp.close()
+    return res
 
 
 def main():
@@ -264,6 +341,12 @@ def main():
             f"{res_b['per_skeleton'] * 1e3:.1f} ms for {bi} iterations (split {bsplit}, {bwg} workgroups)", q)
         gb.close()
 
+    # ---- learned seeds: collect converged particles, train the proposer on the
+    # GPU, then time-to-first from learned vs uniform seeds on held-out scenes
+    learned = None
+    if not args.no_learned:
+        learned = learned_seeds(args, dev, n, iters, q)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -294,6 +377,7 @@ def main():
         "satisfied_after_full_run": sat_end,
         "motion": motion,
         "batch": batch,
+        "learned_seeds": learned,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

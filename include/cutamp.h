@@ -305,6 +305,101 @@ int ct_batch_optimize(ct_batch *batch, int64_t t0, int32_t iters, const ct_adam 
  */
 int ct_batch_autotune(ct_batch *batch, int32_t *chosen, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Learned seed proposer.  Particles are initialized by samplers before they
+ * are optimized (Sec. V); this one is learned.  A multilayer perceptron maps
+ * an input row [scene features (d_feat) | Gaussian noise (d_noise)] through
+ * `depth` hidden layers of width `hidden` with the exact GELU x Phi(x) to
+ * d_out standardized particle coordinates.  The matrix products run on the
+ * matrix cores with BF16 operands (the input row, the weights, the hidden
+ * activations, and in the backward pass every upstream gradient, each
+ * rounded to nearest-even) and FP32 accumulation; master weights, biases,
+ * gradients and Adam moments are FP32.
+ *
+ *  - Parameters: one flat FP32 vector, for each layer W [out][in] row-major
+ *    then b [out]; ct_mlp_info gives its length.
+ *  - Noise entry j of a row with counter words (c0, c1) is Box and Muller's
+ *    transform of Philox4x32-10(counter = (c0, c1, j / 4, 0), key = (seed low
+ *    32 bits, seed high 32 bits)): words (w0, w1) give entries 4(j/4) and
+ *    4(j/4)+1, (w2, w3) the next two; u1 = 1 - (w >> 8) 2^-24, u2 = (w >> 8)
+ *    2^-24, z = sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2).
+ *  - A handle owns its weights, moments, gradient and a workspace for
+ *    max_rows rows (allocated in create; no other call allocates).  Calls on
+ *    one handle run in stream order and must not overlap in time.
+ *  - Pointers named feats, feat_of_row, draw, Y, dY, targets, params,
+ *    grads, loss, chosen, mean, std, lo, hi, wrap, X, M, V are DEVICE
+ *    pointers owned by the caller.  Entries of feat_of_row are clamped into
+ *    [0, n_feats).
+ * ------------------------------------------------------------------------ */
+typedef struct ct_mlp ct_mlp;
+
+typedef struct ct_mlp_shape {
+    int32_t d_feat, d_noise; /* multiples of 4, d_feat + d_noise > 0 */
+    int32_t hidden;          /* multiple of 64, 64..4096 */
+    int32_t depth;           /* hidden layers, 1..8 */
+    int32_t d_out;           /* 1..512 */
+    int64_t max_rows;        /* multiple of 64: most rows any call handles */
+} ct_mlp_shape;
+
+/* Allocate a handle (weights zero until ct_mlp_set_params). */
+int ct_mlp_create(const ct_mlp_shape *shape, ct_mlp **out);
+int ct_mlp_destroy(ct_mlp *mlp);
+int ct_mlp_info(const ct_mlp *mlp, int64_t *n_params);
+
+/* Copy n_params floats in (and zero the Adam moments) / out. */
+int ct_mlp_set_params(ct_mlp *mlp, const float *params, void *stream);
+int ct_mlp_get_params(const ct_mlp *mlp, float *params, void *stream);
+/* The parameter gradient left by the last ct_mlp_backward or
+ * ct_mlp_imle_step (n_params floats). */
+int ct_mlp_get_grads(const ct_mlp *mlp, float *grads, void *stream);
+
+/* FP32 noise rows out[r][d_noise] with counter words (r, draw[r]) (draw
+ * NULL: (r, 0)); the generator alone, for checking. */
+int ct_mlp_noise(const ct_mlp *mlp, uint64_t seed, const int32_t *draw, int64_t rows, float *out, void *stream);
+
+/*
+ * Y[r][d_out] (FP32) for rows r = 0..rows-1 (rows <= max_rows): features
+ * feats[f][d_feat] with f = feat_of_row[r] (NULL: 0), noise counter words
+ * (r, draw[r]) (draw NULL: (r, 0)).  Keeps the activations for
+ * ct_mlp_backward.
+ */
+int ct_mlp_forward(ct_mlp *mlp, const float *feats, int64_t n_feats, const int32_t *feat_of_row,
+                   const int32_t *draw, int64_t rows, uint64_t seed, float *Y, void *stream);
+
+/* Gradient of sum(dY * Y) over the last ct_mlp_forward's rows (dY
+ * [rows][d_out] FP32; rows equal to that call's and a multiple of 64) into
+ * the handle's gradient, overwriting it. */
+int ct_mlp_backward(ct_mlp *mlp, const float *dY, int64_t rows, void *stream);
+
+/* Adam update t (>= 1) of the parameters from grad_scale times the
+ * handle's gradient; the BF16 weight copies are refreshed. */
+int ct_mlp_adam(ct_mlp *mlp, int64_t t, const ct_adam *adam, void *stream);
+
+/*
+ * One implicit-maximum-likelihood training step on `rows` targets
+ * (targets [rows][d_out], standardized; rows a multiple of 64, rows *
+ * n_draws <= max_rows): n_draws outputs per target with noise counter
+ * words (b, s); the draw whose output is nearest to the target (squared
+ * Euclidean, lowest s among equals) is kept; loss = mean over rows and
+ * outputs of the squared error; backward; Adam update t.  loss (one float)
+ * and chosen (int32 [rows]) may be NULL.
+ */
+int ct_mlp_imle_step(ct_mlp *mlp, const float *feats, int64_t n_feats, const int32_t *feat_of_row,
+                     const float *targets, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
+                     const ct_adam *adam, float *loss, int32_t *chosen, void *stream);
+
+/*
+ * n particle seeds for one scene (features feats[d_feat]): row i uses
+ * noise counter words (i, 0); x = y * std + mean, coordinates with wrap[d]
+ * = 1 wrapped into [-pi, pi), every coordinate then clamped into
+ * [lo[d], hi[d]]; stored as X[d * ld + i] with M and V zeroed (the particle
+ * layout of ct_seed_uniform; M, V, wrap may be NULL).  mean, std, lo, hi:
+ * float[d_out].  n rounded up to 64 must not exceed max_rows.
+ */
+int ct_mlp_sample(ct_mlp *mlp, const float *feats, uint64_t seed, const float *mean, const float *std,
+                  const float *lo, const float *hi, const uint8_t *wrap, float *X, float *M, float *V, int64_t n,
+                  int64_t ld, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

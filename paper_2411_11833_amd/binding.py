@@ -53,6 +53,11 @@ class CtAdam(C.Structure):
     _fields_ = [(n, C.c_float) for n in ("lr", "beta1", "beta2", "eps", "grad_scale")]
 
 
+class CtMlpShape(C.Structure):
+    _fields_ = [("d_feat", C.c_int32), ("d_noise", C.c_int32), ("hidden", C.c_int32), ("depth", C.c_int32),
+                ("d_out", C.c_int32), ("max_rows", C.c_int64)]
+
+
 class CtError(RuntimeError):
     def __init__(self, status: int, what: str):
         super().__init__(f"{what}: {ct_status_string(status)} ({status})")
@@ -87,6 +92,18 @@ def _load() -> C.CDLL:
         "ct_batch_step": (C.c_int, [vp, i64, C.POINTER(CtAdam), vp]),
         "ct_batch_optimize": (C.c_int, [vp, i64, i32, C.POINTER(CtAdam), vp]),
         "ct_batch_autotune": (C.c_int, [vp, C.POINTER(i32), vp]),
+        "ct_mlp_create": (C.c_int, [C.POINTER(CtMlpShape), C.POINTER(vp)]),
+        "ct_mlp_destroy": (C.c_int, [vp]),
+        "ct_mlp_info": (C.c_int, [vp, C.POINTER(i64)]),
+        "ct_mlp_set_params": (C.c_int, [vp, vp, vp]),
+        "ct_mlp_get_params": (C.c_int, [vp, vp, vp]),
+        "ct_mlp_get_grads": (C.c_int, [vp, vp, vp]),
+        "ct_mlp_noise": (C.c_int, [vp, u64, vp, i64, vp, vp]),
+        "ct_mlp_forward": (C.c_int, [vp, vp, i64, vp, vp, i64, u64, vp, vp]),
+        "ct_mlp_backward": (C.c_int, [vp, vp, i64, vp]),
+        "ct_mlp_adam": (C.c_int, [vp, i64, C.POINTER(CtAdam), vp]),
+        "ct_mlp_imle_step": (C.c_int, [vp, vp, i64, vp, vp, i64, i32, u64, i64, C.POINTER(CtAdam), vp, vp, vp]),
+        "ct_mlp_sample": (C.c_int, [vp, vp, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -238,3 +255,58 @@ def ct_batch_autotune(h, stream=0) -> tuple[int, int]:
     out = (C.c_int32 * 2)()
     _chk(LIB.ct_batch_autotune(h, out, stream), "ct_batch_autotune")
     return out[0], out[1]
+
+
+def ct_mlp_create(d_feat, d_noise, hidden, depth, d_out, max_rows) -> int:
+    shape = CtMlpShape(d_feat, d_noise, hidden, depth, d_out, max_rows)
+    h = C.c_void_p()
+    _chk(LIB.ct_mlp_create(C.byref(shape), C.byref(h)), "ct_mlp_create")
+    return h.value
+
+
+def ct_mlp_destroy(h):
+    _chk(LIB.ct_mlp_destroy(h), "ct_mlp_destroy")
+
+
+def ct_mlp_info(h) -> int:
+    n = C.c_int64()
+    _chk(LIB.ct_mlp_info(h, C.byref(n)), "ct_mlp_info")
+    return n.value
+
+
+def ct_mlp_set_params(h, params, stream=0):
+    _chk(LIB.ct_mlp_set_params(h, params, stream), "ct_mlp_set_params")
+
+
+def ct_mlp_get_params(h, params, stream=0):
+    _chk(LIB.ct_mlp_get_params(h, params, stream), "ct_mlp_get_params")
+
+
+def ct_mlp_get_grads(h, grads, stream=0):
+    _chk(LIB.ct_mlp_get_grads(h, grads, stream), "ct_mlp_get_grads")
+
+
+def ct_mlp_noise(h, seed, draw, rows, out, stream=0):
+    _chk(LIB.ct_mlp_noise(h, seed, draw, rows, out, stream), "ct_mlp_noise")
+
+
+def ct_mlp_forward(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream=0):
+    _chk(LIB.ct_mlp_forward(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream), "ct_mlp_forward")
+
+
+def ct_mlp_backward(h, dY, rows, stream=0):
+    _chk(LIB.ct_mlp_backward(h, dY, rows, stream), "ct_mlp_backward")
+
+
+def ct_mlp_adam(h, t, adam: CtAdam, stream=0):
+    _chk(LIB.ct_mlp_adam(h, t, C.byref(adam), stream), "ct_mlp_adam")
+
+
+def ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, rows, n_draws, seed, t, adam: CtAdam,
+                     loss=None, chosen=None, stream=0):
+    _chk(LIB.ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, rows, n_draws, seed, t, C.byref(adam),
+                              loss, chosen, stream), "ct_mlp_imle_step")
+
+
+def ct_mlp_sample(h, feats, seed, mean, std, lo, hi, wrap, X, M, V, n, ld, stream=0):
+    _chk(LIB.ct_mlp_sample(h, feats, seed, mean, std, lo, hi, wrap, X, M, V, n, ld, stream), "ct_mlp_sample")

@@ -2,7 +2,8 @@
 
 The fused particle kernels are instantiated per lane split in their own
 object (pk_instances.hip with -DCT_SPLIT=s) so the objects compile in parallel;
-the host side (cutamp.hip) holds the C ABI and the small elementwise kernels.
+the host side (cutamp.hip) holds the C ABI and the small elementwise kernels,
+mlp.hip the seed proposer's matrix-core kernels and their C ABI.
 
 Usage: python -m paper_2411_11833_amd.build
 """
@@ -54,7 +55,8 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     obj_dir = objdir or OBJ
     os.makedirs(obj_dir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(obj_dir, "cutamp.o"), [])]
+    units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(obj_dir, "cutamp.o"), []),
+             (os.path.join(CSRC, "mlp.hip"), os.path.join(obj_dir, "mlp.o"), [])]
     for split in SPLITS:
         units.append((os.path.join(CSRC, "pk_instances.hip"), os.path.join(obj_dir, f"pk_s{split}.o"),
                       [f"-DCT_SPLIT={split}"]))

@@ -1,0 +1,399 @@
+// C ABI of the learned seed proposer (declared in cutamp.h): handle, weights,
+// forward / backward / Adam, one IMLE training step, and seeding particles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cutamp.h"
+#include "mlp_kernels.hpp"
+
+namespace {
+
+using namespace ct::mlp;
+
+constexpr int64_t PART_CAP = int64_t(16) << 20;   // split-K partial floats (64 MiB)
+
+int64_t up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+int err_of(hipError_t e) { return e == hipSuccess ? CT_OK : CT_ERR_DEVICE; }
+unsigned blocks(int64_t n, int64_t per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+struct ct_mlp {
+    ct_mlp_shape s{};
+    int L = 0;                // linear layers = depth + 1
+    int d_in = 0, in_pad = 0, out_pad = 0;
+    int64_t rows_cap = 0;     // max_rows rounded up to 64
+    std::vector<int> din, dout, kpad, npad;
+    std::vector<int64_t> woff, boff;
+    int64_t n_params = 0;
+    float *P = nullptr, *Mo = nullptr, *Vo = nullptr, *G = nullptr;
+    std::vector<uint16_t*> Wb, WbT;
+    uint16_t *X0 = nullptr, *X0T = nullptr;
+    std::vector<float*> Z;
+    std::vector<uint16_t*> H, HT, D, DT;
+    float* Y = nullptr;
+    uint16_t *GY = nullptr, *GYT = nullptr;
+    float* part = nullptr;
+    float* row_loss = nullptr;
+    int32_t* chosen = nullptr;
+    int64_t fwd_rows = -1;    // rows of the last forward that kept its activations
+    std::vector<void*> allocs;
+
+    template <class T>
+    bool alloc(T*& p, int64_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, (size_t)count * sizeof(T)) != hipSuccess) return false;
+        if (hipMemset(q, 0, (size_t)count * sizeof(T)) != hipSuccess) {
+            (void)hipFree(q);
+            return false;
+        }
+        allocs.push_back(q);
+        p = (T*)q;
+        return true;
+    }
+    ~ct_mlp() {
+        for (void* q : allocs) (void)hipFree(q);
+    }
+};
+
+namespace {
+
+bool shape_ok(const ct_mlp_shape& s) {
+    return s.d_feat >= 0 && s.d_feat % 4 == 0 && s.d_noise >= 0 && s.d_noise % 4 == 0 && s.d_feat + s.d_noise > 0 &&
+           s.hidden >= 64 && s.hidden % 64 == 0 && s.hidden <= 4096 && s.depth >= 1 && s.depth <= 8 &&
+           s.d_out >= 1 && s.d_out <= 512 && s.max_rows >= 64 && s.max_rows % 64 == 0 &&
+           s.max_rows <= (int64_t(1) << 24);
+}
+
+int gemm(int epi, const GemmArgs& g, hipStream_t st) {
+    const unsigned grid = (unsigned)(((g.M + GT - 1) / GT) * ((g.N + GT - 1) / GT) * g.ksplit);
+    switch (epi) {
+        case EPI_HID_TRAIN: hipLaunchKernelGGL(gemm_nt_kernel<EPI_HID_TRAIN>, dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_HID_INFER: hipLaunchKernelGGL(gemm_nt_kernel<EPI_HID_INFER>, dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_OUT: hipLaunchKernelGGL(gemm_nt_kernel<EPI_OUT>, dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_BWD: hipLaunchKernelGGL(gemm_nt_kernel<EPI_BWD>, dim3(grid), dim3(256), 0, st, g); break;
+        default: hipLaunchKernelGGL(gemm_nt_kernel<EPI_DW>, dim3(grid), dim3(256), 0, st, g); break;
+    }
+    return err_of(hipGetLastError());
+}
+
+// split-K factor of a weight-gradient product: enough workgroups to cover
+// the chip (about 512), each K chunk a multiple of 32, partials within PART_CAP
+int pick_ksplit(int M, int N, int64_t K) {
+    const int64_t tiles = (int64_t)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
+    int s = 1;
+    while (tiles * s < 512 && K % (int64_t(GK) * s * 2) == 0 && (int64_t)s * 2 * M * N <= PART_CAP && s < 64) s *= 2;
+    return s;
+}
+
+int refresh(ct_mlp* m, hipStream_t st) {
+    for (int l = 0; l < m->L; ++l) {
+        const int64_t cnt = (int64_t)m->npad[l] * m->kpad[l];
+        hipLaunchKernelGGL(refresh_kernel, dim3(blocks(cnt, 256)), dim3(256), 0, st, m->P + m->woff[l], m->din[l],
+                           m->dout[l], m->kpad[l], m->npad[l], m->Wb[l], m->WbT[l]);
+    }
+    return err_of(hipGetLastError());
+}
+
+// inputs + every layer; train keeps Z, H, H^T and X0^T for the backward pass
+int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+            int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st) {
+    InputArgs a{};
+    a.feats = feats;
+    a.n_feats = n_feats;
+    a.feat_of_row = feat_of_row;
+    a.draw = draw;
+    a.draws = draws;
+    a.d_feat = m->s.d_feat;
+    a.d_noise = m->s.d_noise;
+    a.in_pad = m->in_pad;
+    a.rows = rows;
+    a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(seed >> 32);
+    a.X0 = m->X0;
+    a.X0T = train ? m->X0T : nullptr;
+    a.ldt = m->rows_cap;
+    hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * (m->in_pad / 4), 256)), dim3(256), 0, st, a);
+    int rc = err_of(hipGetLastError());
+    for (int l = 0; l < m->L && rc == CT_OK; ++l) {
+        GemmArgs g{};
+        g.A = l == 0 ? m->X0 : m->H[l - 1];
+        g.lda = l == 0 ? m->in_pad : m->s.hidden;
+        g.B = m->Wb[l];
+        g.ldb = m->kpad[l];
+        g.M = (int)rows;
+        g.N = m->dout[l];
+        g.K = m->kpad[l];
+        g.ksplit = 1;
+        g.bias = m->P + m->boff[l];
+        if (l + 1 < m->L) {
+            g.F = m->Z[l];
+            g.ldf = m->s.hidden;
+            g.Hb = m->H[l];
+            g.ldh = m->s.hidden;
+            g.Ht = m->HT[l];
+            g.ldht = m->rows_cap;
+            rc = gemm(train ? EPI_HID_TRAIN : EPI_HID_INFER, g, st);
+        } else {
+            g.F = m->Y;
+            g.ldf = m->s.d_out;
+            rc = gemm(EPI_OUT, g, st);
+        }
+    }
+    m->fwd_rows = (rc == CT_OK && train) ? rows : -1;
+    return rc;
+}
+
+// gradient of sum(G * Y) from the BF16 upstream gradient already in GY / GYT
+int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
+    int rc = CT_OK;
+    for (int l = m->L - 1; l >= 0 && rc == CT_OK; --l) {
+        const bool top = l == m->L - 1;
+        const uint16_t* Dm = top ? m->GY : m->D[l];     // [rows][npad]
+        const uint16_t* Dt = top ? m->GYT : m->DT[l];   // [npad][rows_cap]
+        // dW_l = D^T * H_{l-1}
+        GemmArgs g{};
+        g.A = Dt;
+        g.lda = m->rows_cap;
+        g.B = l == 0 ? m->X0T : m->HT[l - 1];
+        g.ldb = m->rows_cap;
+        g.M = m->dout[l];
+        g.N = m->din[l];
+        g.K = (int)rows;
+        g.ksplit = pick_ksplit(g.M, g.N, rows);
+        float* dW = m->G + m->woff[l];
+        if (g.ksplit == 1) {
+            g.F = dW;
+            g.ldf = m->din[l];
+            g.fsplit = 0;
+        } else {
+            g.F = m->part;
+            g.ldf = m->din[l];
+            g.fsplit = (int64_t)g.M * g.N;
+        }
+        rc = gemm(EPI_DW, g, st);
+        if (rc != CT_OK) break;
+        if (g.ksplit > 1) {
+            const int64_t cnt = (int64_t)g.M * g.N;
+            hipLaunchKernelGGL(split_reduce_kernel, dim3(blocks(cnt, 256)), dim3(256), 0, st, m->part, g.ksplit, cnt,
+                               dW);
+        }
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks(m->dout[l], 4)), dim3(256), 0, st, Dt, m->rows_cap, rows,
+                           m->dout[l], m->G + m->boff[l]);
+        rc = err_of(hipGetLastError());
+        if (rc != CT_OK || l == 0) break;
+        // D_{l-1} = (D_l * W_l) . gelu'(Z_{l-1})
+        GemmArgs b{};
+        b.A = Dm;
+        b.lda = m->npad[l];
+        b.B = m->WbT[l];
+        b.ldb = m->npad[l];
+        b.M = (int)rows;
+        b.N = m->din[l];
+        b.K = m->npad[l];
+        b.ksplit = 1;
+        b.Zin = m->Z[l - 1];
+        b.ldzin = m->s.hidden;
+        b.Hb = m->D[l - 1];
+        b.ldh = m->s.hidden;
+        b.Ht = m->DT[l - 1];
+        b.ldht = m->rows_cap;
+        rc = gemm(EPI_BWD, b, st);
+    }
+    return rc;
+}
+
+int adam(ct_mlp* m, int64_t t, const ct_adam* ad, hipStream_t st) {
+    const double bc1 = 1.0 - std::pow((double)ad->beta1, (double)t);
+    const double bc2 = 1.0 - std::pow((double)ad->beta2, (double)t);
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks(m->n_params, 256)), dim3(256), 0, st, m->P, m->Mo, m->Vo, m->G,
+                       m->n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, ad->grad_scale, (float)bc1, (float)bc2);
+    const int rc = err_of(hipGetLastError());
+    return rc != CT_OK ? rc : refresh(m, st);
+}
+
+bool adam_ok(const ct_adam* a) {
+    return a && std::isfinite(a->lr) && a->lr >= 0 && a->beta1 >= 0 && a->beta1 < 1 && a->beta2 >= 0 &&
+           a->beta2 < 1 && a->eps > 0 && std::isfinite(a->grad_scale);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ct_mlp_create(const ct_mlp_shape* shape, ct_mlp** out) {
+    if (!shape || !out) return CT_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!shape_ok(*shape)) return CT_ERR_INVALID_ARG;
+    ct_mlp* m = new (std::nothrow) ct_mlp;
+    if (!m) return CT_ERR_ALLOC;
+    m->s = *shape;
+    m->L = shape->depth + 1;
+    m->d_in = shape->d_feat + shape->d_noise;
+    m->in_pad = (int)up(m->d_in, GK);
+    m->out_pad = (int)up(shape->d_out, GK);
+    m->rows_cap = up(shape->max_rows, 64);
+    for (int l = 0; l < m->L; ++l) {
+        const int di = l == 0 ? m->d_in : shape->hidden;
+        const int dn = l + 1 < m->L ? shape->hidden : shape->d_out;
+        m->din.push_back(di);
+        m->dout.push_back(dn);
+        m->kpad.push_back(l == 0 ? m->in_pad : shape->hidden);
+        m->npad.push_back(l + 1 < m->L ? shape->hidden : m->out_pad);
+        m->woff.push_back(m->n_params);
+        m->n_params += (int64_t)di * dn;
+        m->boff.push_back(m->n_params);
+        m->n_params += dn;
+    }
+    const int64_t R = m->rows_cap, Hd = shape->hidden;
+    bool ok = m->alloc(m->P, m->n_params) && m->alloc(m->Mo, m->n_params) && m->alloc(m->Vo, m->n_params) &&
+              m->alloc(m->G, m->n_params) && m->alloc(m->X0, R * m->in_pad) && m->alloc(m->X0T, R * m->in_pad) &&
+              m->alloc(m->Y, R * shape->d_out) && m->alloc(m->GY, R * m->out_pad) &&
+              m->alloc(m->GYT, R * m->out_pad) && m->alloc(m->row_loss, R) && m->alloc(m->chosen, R);
+    int64_t part = 0;
+    for (int l = 0; l < m->L; ++l) part = std::max(part, (int64_t)m->din[l] * m->dout[l]);
+    ok = ok && m->alloc(m->part, std::min<int64_t>(PART_CAP, 64 * part));
+    m->Wb.assign(m->L, nullptr);
+    m->WbT.assign(m->L, nullptr);
+    for (int l = 0; l < m->L && ok; ++l) {
+        ok = m->alloc(m->Wb[l], (int64_t)m->npad[l] * m->kpad[l]);
+        if (ok && l > 0) ok = m->alloc(m->WbT[l], (int64_t)m->npad[l] * m->kpad[l]);
+    }
+    m->Z.assign(shape->depth, nullptr);
+    m->H.assign(shape->depth, nullptr);
+    m->HT.assign(shape->depth, nullptr);
+    m->D.assign(shape->depth, nullptr);
+    m->DT.assign(shape->depth, nullptr);
+    for (int l = 0; l < shape->depth && ok; ++l)
+        ok = m->alloc(m->Z[l], R * Hd) && m->alloc(m->H[l], R * Hd) && m->alloc(m->HT[l], R * Hd) &&
+             m->alloc(m->D[l], R * Hd) && m->alloc(m->DT[l], R * Hd);
+    if (!ok) {
+        delete m;
+        return CT_ERR_ALLOC;
+    }
+    *out = m;
+    return CT_OK;
+}
+
+int ct_mlp_destroy(ct_mlp* mlp) {
+    if (!mlp) return CT_ERR_INVALID_ARG;
+    delete mlp;
+    return CT_OK;
+}
+
+int ct_mlp_info(const ct_mlp* mlp, int64_t* n_params) {
+    if (!mlp || !n_params) return CT_ERR_INVALID_ARG;
+    *n_params = mlp->n_params;
+    return CT_OK;
+}
+
+int ct_mlp_set_params(ct_mlp* mlp, const float* params, void* stream) {
+    if (!mlp || !params) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)mlp->n_params * sizeof(float);
+    int rc = err_of(hipMemcpyAsync(mlp->P, params, bytes, hipMemcpyDeviceToDevice, st));
+    if (rc == CT_OK) rc = err_of(hipMemsetAsync(mlp->Mo, 0, bytes, st));
+    if (rc == CT_OK) rc = err_of(hipMemsetAsync(mlp->Vo, 0, bytes, st));
+    return rc != CT_OK ? rc : refresh(mlp, st);
+}
+
+int ct_mlp_get_params(const ct_mlp* mlp, float* params, void* stream) {
+    if (!mlp || !params) return CT_ERR_INVALID_ARG;
+    return err_of(hipMemcpyAsync(params, mlp->P, (size_t)mlp->n_params * sizeof(float), hipMemcpyDeviceToDevice,
+                                 (hipStream_t)stream));
+}
+
+int ct_mlp_get_grads(const ct_mlp* mlp, float* grads, void* stream) {
+    if (!mlp || !grads) return CT_ERR_INVALID_ARG;
+    return err_of(hipMemcpyAsync(grads, mlp->G, (size_t)mlp->n_params * sizeof(float), hipMemcpyDeviceToDevice,
+                                 (hipStream_t)stream));
+}
+
+int ct_mlp_noise(const ct_mlp* mlp, uint64_t seed, const int32_t* draw, int64_t rows, float* out, void* stream) {
+    if (!mlp || rows < 0 || (rows > 0 && !out)) return CT_ERR_INVALID_ARG;
+    if (rows == 0 || mlp->s.d_noise == 0) return CT_OK;
+    const int64_t cnt = rows * (mlp->s.d_noise / 4);
+    hipLaunchKernelGGL(noise_kernel, dim3(blocks(cnt, 256)), dim3(256), 0, (hipStream_t)stream, draw, rows,
+                       mlp->s.d_noise, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), out);
+    return err_of(hipGetLastError());
+}
+
+int ct_mlp_forward(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+                   int64_t rows, uint64_t seed, float* Y, void* stream) {
+    if (!mlp || rows < 0 || rows > mlp->rows_cap) return CT_ERR_INVALID_ARG;
+    if (rows == 0) return CT_OK;
+    if (!Y || (mlp->s.d_feat > 0 && (!feats || n_feats < 1))) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = forward(mlp, feats, n_feats < 1 ? 1 : n_feats, feat_of_row, draw, 0, rows, seed, true, st);
+    if (rc == CT_OK)
+        rc = err_of(hipMemcpyAsync(Y, mlp->Y, (size_t)rows * mlp->s.d_out * sizeof(float), hipMemcpyDeviceToDevice,
+                                   st));
+    return rc;
+}
+
+int ct_mlp_backward(ct_mlp* mlp, const float* dY, int64_t rows, void* stream) {
+    if (!mlp || !dY || rows <= 0 || rows % 64 != 0 || rows != mlp->fwd_rows) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const float*)nullptr,
+                       mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY, mlp->GYT, mlp->rows_cap, (float*)nullptr);
+    const int rc = err_of(hipGetLastError());
+    return rc != CT_OK ? rc : backward(mlp, rows, st);
+}
+
+int ct_mlp_adam(ct_mlp* mlp, int64_t t, const ct_adam* adam_args, void* stream) {
+    if (!mlp || t < 1 || !adam_ok(adam_args)) return CT_ERR_INVALID_ARG;
+    return adam(mlp, t, adam_args, (hipStream_t)stream);
+}
+
+int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row,
+                     const float* targets, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
+                     const ct_adam* adam_args, float* loss, int32_t* chosen, void* stream) {
+    if (!mlp || !targets || rows <= 0 || rows % 64 != 0 || n_draws < 1 || t < 1 || !adam_ok(adam_args) ||
+        rows * n_draws > mlp->rows_cap || (mlp->s.d_feat > 0 && (!feats || n_feats < 1)))
+        return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t nf = n_feats < 1 ? 1 : n_feats;
+    int32_t* sel = chosen ? chosen : mlp->chosen;
+    // 1. every draw, inference only; 2. the nearest draw per target
+    int rc = forward(mlp, feats, nf, feat_of_row, nullptr, n_draws, rows * n_draws, seed, false, st);
+    if (rc != CT_OK) return rc;
+    hipLaunchKernelGGL(imle_select_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, mlp->s.d_out,
+                       rows, n_draws, sel);
+    rc = err_of(hipGetLastError());
+    // 3. the kept draws again, keeping activations; 4. squared error
+    if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st);
+    if (rc != CT_OK) return rc;
+    const float scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, mlp->s.d_out,
+                       mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap, mlp->row_loss);
+    if (loss)
+        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, mlp->row_loss, rows,
+                           (float)(1.0 / ((double)rows * mlp->s.d_out)), loss);
+    rc = err_of(hipGetLastError());
+    // 5. backward and Adam
+    if (rc == CT_OK) rc = backward(mlp, rows, st);
+    if (rc == CT_OK) rc = adam(mlp, t, adam_args, st);
+    return rc;
+}
+
+int ct_mlp_sample(ct_mlp* mlp, const float* feats, uint64_t seed, const float* mean, const float* std_,
+                  const float* lo, const float* hi, const uint8_t* wrap, float* X, float* M, float* V, int64_t n,
+                  int64_t ld, void* stream) {
+    if (!mlp || n < 0 || ld < n || ld % 64 != 0 || up(n, 64) > mlp->rows_cap) return CT_ERR_INVALID_ARG;
+    if (n == 0) return CT_OK;
+    if (!mean || !std_ || !lo || !hi || !X || (mlp->s.d_feat > 0 && !feats)) return CT_ERR_INVALID_ARG;
+    if (((uintptr_t)X % 256) || (M && (uintptr_t)M % 256) || (V && (uintptr_t)V % 256)) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = forward(mlp, feats, 1, nullptr, nullptr, 0, n, seed, false, st);
+    if (rc != CT_OK) return rc;
+    hipLaunchKernelGGL(sample_store_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, mlp->Y, mlp->s.d_out, n, mean,
+                       std_, lo, hi, wrap, X, M, V, ld);
+    return err_of(hipGetLastError());
+}
+
+}  // extern "C"

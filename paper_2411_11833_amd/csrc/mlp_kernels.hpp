@@ -1,0 +1,390 @@
+// Kernels of the learned seed proposer: a multilayer perceptron whose matrix
+// products run on the CDNA4 matrix cores in BF16 with FP32 accumulation
+// (v_mfma_f32_16x16x32_bf16), with GELU, Gaussian input noise, nearest-draw
+// (IMLE) selection, the squared-error gradient, bias sums and Adam around them.
+//
+// Every product is written C = A * B^T with both operands K-contiguous BF16:
+//   forward   Z_l   = H_{l-1} * W_l^T        (A = H [rows][in],  B = W   [out][in])
+//   backward  dH    = dZ_l * W_l             (A = dZ [rows][out], B = W^T [in][out])
+//   weights   dW_l  = dZ_l^T * H_{l-1}       (A = dZ^T [out][rows], B = H^T [in][rows])
+// so the epilogues store activations and gradients in both orientations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "philox.hpp"
+
+namespace ct {
+namespace mlp {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+
+// d/dx [x Phi(x)] = Phi(x) + x phi(x)
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// Four standard normals from one Philox block: Box-Muller on the word pairs
+// (w0, w1) and (w2, w3), u1 = 1 - (w >> 8) 2^-24 in (0, 1], u2 = (w >> 8) 2^-24.
+__device__ __forceinline__ void normal4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0, uint32_t k1,
+                                        float z[4]) {
+    uint32_t c[4] = {c0, c1, c2, 0u};
+    philox4x32_10(c, k0, k1);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const float u1 = 1.f - (float)(c[2 * p] >> 8) * 5.9604644775390625e-08f;
+        const float u2 = (float)(c[2 * p + 1] >> 8) * 5.9604644775390625e-08f;
+        const float rad = sqrtf(-2.f * logf(u1));
+        float s, co;
+        sincospif(2.f * u2, &s, &co);
+        z[2 * p] = rad * co;
+        z[2 * p + 1] = rad * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C = A * B^T on the matrix cores
+
+enum Epi { EPI_HID_TRAIN = 0, EPI_HID_INFER = 1, EPI_OUT = 2, EPI_BWD = 3, EPI_DW = 4 };
+
+struct GemmArgs {
+    const uint16_t* A;
+    int64_t lda;   // [M][K] BF16, K contiguous
+    const uint16_t* B;
+    int64_t ldb;   // [N][K] BF16, K contiguous
+    int M, N, K;   // K % (32 * ksplit) == 0
+    int ksplit;    // K chunks, one workgroup each (EPI_DW only)
+    const float* bias;   // [N]  (HID_*, OUT)
+    float* F;            // HID_TRAIN: Z [M][N]; OUT: Y [M][N]; DW: partial [ksplit][M][N] or dW
+    int64_t ldf, fsplit;
+    const float* Zin;    // BWD: pre-activation of the layer the gradient flows into, [M][N]
+    int64_t ldzin;
+    uint16_t* Hb;        // HID_*: H = bf16(gelu(Z)); BWD: D = bf16(dH * gelu'(Zin));  [M][N]
+    int64_t ldh;
+    uint16_t* Ht;        // the same values transposed, [N][ldht] (HID_TRAIN, BWD)
+    int64_t ldht;
+};
+
+constexpr int GT = 64;    // workgroup tile (M and N)
+constexpr int GK = 32;    // K per stage (one MFMA deep)
+constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
+
+// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a 32 x 32
+// block = 2 x 2 MFMA 16x16x32 tiles.  Operand fragments: lane l holds row
+// (l % 16) and K elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and
+// B blocks; accumulator element r of lane l is C[4 (l / 16) + r][l % 16].
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];
+    const int tiles_n = (g.N + GT - 1) / GT;
+    int bid = blockIdx.x;
+    const int split = bid % g.ksplit;
+    bid /= g.ksplit;
+    const int m0 = (bid / tiles_n) * GT, n0 = (bid % tiles_n) * GT;
+    const int kc = g.K / g.ksplit, kb = split * kc, ke = kb + kc;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    const bool a_ok = m0 + lr < g.M, b_ok = n0 + lr < g.N;
+    const uint16_t* pa = g.A + (int64_t)(a_ok ? m0 + lr : 0) * g.lda + lk;
+    const uint16_t* pb = g.B + (int64_t)(b_ok ? n0 + lr : 0) * g.ldb + lk;
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+        const uint4 a = a_ok ? *(const uint4*)(pa + k0) : z4;
+        const uint4 b = b_ok ? *(const uint4*)(pb + k0) : z4;
+        __syncthreads();   // the previous stage's fragments are read
+        *(uint4*)&As[lr][lk] = a;
+        *(uint4*)&Bs[lr][lk] = b;
+        __syncthreads();
+        bf16x8_t af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            af[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            bf[j] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = m0 + wm * 32 + i * 16 + (lane >> 4) * 4;
+            const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+            if (n >= g.N) continue;
+            uint16_t hv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = mb + r;
+                const float v = acc[i][j][r];
+                hv[r] = 0;
+                if (m >= g.M) continue;
+                if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
+                    const float z = v + g.bias[n];
+                    if constexpr (EPI == EPI_HID_TRAIN) g.F[(int64_t)m * g.ldf + n] = z;
+                    hv[r] = to_bf16(gelu(z));
+                    g.Hb[(int64_t)m * g.ldh + n] = hv[r];
+                } else if constexpr (EPI == EPI_OUT) {
+                    g.F[(int64_t)m * g.ldf + n] = v + g.bias[n];
+                } else if constexpr (EPI == EPI_BWD) {
+                    hv[r] = to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n]));
+                    g.Hb[(int64_t)m * g.ldh + n] = hv[r];
+                } else {
+                    g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
+                }
+            }
+            if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_BWD) {
+                // four consecutive rows of one column: one 8-byte store of the transpose
+                uint16_t* dst = g.Ht + (int64_t)n * g.ldht + mb;
+                if (mb + 3 < g.M) {
+                    uint2 p;
+                    p.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+                    p.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+                    *(uint2*)dst = p;
+                } else {
+                    for (int r = 0; r < 4; ++r)
+                        if (mb + r < g.M) dst[r] = hv[r];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// input rows: [features | noise | zero padding] in BF16
+
+struct InputArgs {
+    const float* feats;          // [n_feats][d_feat]
+    int64_t n_feats;
+    const int32_t* feat_of_row;  // [logical rows] or null (feature row 0); clamped into range
+    const int32_t* draw;         // [logical rows] or null (draw 0); used when draws == 0
+    int draws;                   // > 0: physical row r is logical row r / draws, draw r % draws
+    int d_feat, d_noise, in_pad;
+    int64_t rows;
+    uint32_t k0, k1;
+    uint16_t* X0;                // [rows][in_pad]
+    uint16_t* X0T;               // [in_pad][ldt] or null
+    int64_t ldt;
+};
+
+__global__ __launch_bounds__(256) void build_inputs_kernel(InputArgs a) {
+    const int groups = a.in_pad / 4;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.rows * groups) return;
+    const int64_t r = e / groups;
+    const int c = (int)(e % groups) * 4;
+    const int64_t b = a.draws > 0 ? r / a.draws : r;
+    const uint32_t s = a.draws > 0 ? (uint32_t)(r % a.draws) : (a.draw ? (uint32_t)a.draw[b] : 0u);
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c < a.d_feat) {
+        int64_t f = a.feat_of_row ? (int64_t)a.feat_of_row[b] : 0;
+        f = f < 0 ? 0 : (f >= a.n_feats ? a.n_feats - 1 : f);
+        const float* src = a.feats + f * a.d_feat + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = src[q];
+    } else if (c < a.d_feat + a.d_noise) {
+        normal4((uint32_t)b, s, (uint32_t)((c - a.d_feat) / 4), a.k0, a.k1, v);
+    }
+    uint16_t h[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q] = to_bf16(v[q]);
+    uint2 p;
+    p.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+    p.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+    *(uint2*)(a.X0 + r * a.in_pad + c) = p;
+    if (a.X0T) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.X0T[(int64_t)(c + q) * a.ldt + r] = h[q];
+    }
+}
+
+// FP32 noise rows (the generator alone): out[r][j], counter words (r, draw[r])
+__global__ __launch_bounds__(256) void noise_kernel(const int32_t* draw, int64_t rows, int d_noise, uint32_t k0,
+                                                    uint32_t k1, float* out) {
+    const int groups = d_noise / 4;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * groups) return;
+    const int64_t r = e / groups;
+    const int gi = (int)(e % groups);
+    float z[4];
+    normal4((uint32_t)r, draw ? (uint32_t)draw[r] : 0u, (uint32_t)gi, k0, k1, z);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[r * d_noise + gi * 4 + q] = z[q];
+}
+
+// ---------------------------------------------------------------------------
+// IMLE: nearest of S draws per target (one wave per target; lowest index on ties)
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void imle_select_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                          int d_out, int64_t B, int S, int32_t* __restrict__ chosen) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= B) return;
+    float best = 0.f;
+    int bi = 0;
+    for (int s = 0; s < S; ++s) {
+        const float* y = Y + (b * S + s) * d_out;
+        const float* t = T + b * d_out;
+        float acc = 0.f;
+        for (int d = lane; d < d_out; d += 64) {
+            const float df = y[d] - t[d];
+            acc += df * df;
+        }
+        acc = wave_sum(acc);
+        if (s == 0 || acc < best) {
+            best = acc;
+            bi = s;
+        }
+    }
+    if (lane == 0) chosen[b] = bi;
+}
+
+// Upstream gradient of the output layer in BF16, both orientations.  With
+// targets: g = scale (y - t) and the row's sum of squares; without: g = y.
+__global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                       int d_out, int out_pad, int64_t rows, float scale,
+                                                       uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT,
+                                                       int64_t ldt, float* __restrict__ row_loss) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= rows) return;
+    float acc = 0.f;
+    for (int d = lane; d < out_pad; d += 64) {
+        float gv = 0.f;
+        if (d < d_out) {
+            const float y = Y[b * d_out + d];
+            if (T) {
+                const float df = y - T[b * d_out + d];
+                acc += df * df;
+                gv = scale * df;
+            } else {
+                gv = y;
+            }
+        }
+        const uint16_t h = to_bf16(gv);
+        GY[b * out_pad + d] = h;
+        GYT[(int64_t)d * ldt + b] = h;
+    }
+    if (T && row_loss) {
+        acc = wave_sum(acc);
+        if (lane == 0) row_loss[b] = acc;
+    }
+}
+
+// loss = inv * sum of the row sums (one workgroup, fixed summation order)
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restrict__ row_loss, int64_t rows, float inv,
+                                                          float* __restrict__ loss) {
+    __shared__ float red[256];
+    float acc = 0.f;
+    for (int64_t r = threadIdx.x; r < rows; r += 256) acc += row_loss[r];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * inv;
+}
+
+// db[o] = sum over rows of the BF16 upstream gradient (one wave per output)
+__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* __restrict__ DT, int64_t ldt, int64_t rows,
+                                                        int n_out, float* __restrict__ gb) {
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (o >= n_out) return;
+    const uint16_t* src = DT + (int64_t)o * ldt;
+    float acc = 0.f;
+    for (int64_t r = lane; r < rows; r += 64) acc += __uint_as_float((uint32_t)src[r] << 16);
+    acc = wave_sum(acc);
+    if (lane == 0) gb[o] = acc;
+}
+
+// out[e] = sum over split-K partials, in split order
+__global__ __launch_bounds__(256) void split_reduce_kernel(const float* __restrict__ part, int ksplit, int64_t count,
+                                                           float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float acc = 0.f;
+    for (int s = 0; s < ksplit; ++s) acc += part[(int64_t)s * count + e];
+    out[e] = acc;
+}
+
+// Adam on the flat FP32 parameters (bias corrections bc1 = 1 - beta1^t,
+// bc2 = 1 - beta2^t passed in)
+__global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ Mo,
+                                                       float* __restrict__ Vo, const float* __restrict__ G, int64_t n,
+                                                       float lr, float b1, float b2, float eps, float gscale,
+                                                       float bc1, float bc2) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float g = gscale * G[e];
+    const float m = b1 * Mo[e] + (1.f - b1) * g;
+    const float v = b2 * Vo[e] + (1.f - b2) * g * g;
+    Mo[e] = m;
+    Vo[e] = v;
+    P[e] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+}
+
+// BF16 copies of one layer's weights: Wb [npad][kpad] and WbT [kpad][npad]
+// (null to skip), zero outside the real [dout][din] block
+__global__ __launch_bounds__(256) void refresh_kernel(const float* __restrict__ W, int din, int dout, int kpad,
+                                                      int npad, uint16_t* __restrict__ Wb, uint16_t* __restrict__ WbT) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)npad * kpad) return;
+    const int o = (int)(e / kpad), i = (int)(e % kpad);
+    const uint16_t v = (o < dout && i < din) ? to_bf16(W[(int64_t)o * din + i]) : (uint16_t)0;
+    Wb[e] = v;
+    if (WbT) WbT[(int64_t)i * npad + o] = v;
+}
+
+// seeds: x = y std + mean, angles wrapped into [-pi, pi), clamped into
+// [lo, hi]; one thread per particle, stores coalesced along particles
+__global__ __launch_bounds__(256) void sample_store_kernel(const float* __restrict__ Y, int d_out, int64_t n,
+                                                           const float* __restrict__ mean,
+                                                           const float* __restrict__ stdv,
+                                                           const float* __restrict__ lo, const float* __restrict__ hi,
+                                                           const uint8_t* __restrict__ wrap, float* __restrict__ X,
+                                                           float* __restrict__ M, float* __restrict__ V, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < d_out; ++d) {
+        float x = Y[i * d_out + d] * stdv[d] + mean[d];
+        if (wrap && wrap[d]) x -= 6.283185307179586f * floorf((x + 3.14159265358979f) * 0.15915494309189535f);
+        x = fminf(fmaxf(x, lo[d]), hi[d]);
+        X[d * ld + i] = x;
+        if (M) M[d * ld + i] = 0.f;
+        if (V) V[d * ld + i] = 0.f;
+    }
+}
+
+}  // namespace mlp
+}  // namespace ct

@@ -227,9 +227,10 @@ INT32_MAX = 2 ** 31 - 1
 
 
 def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, stop_at_first: bool = True,
-                adam: B.CtAdam | None = None, X=None, fixed_grasps: bool = True) -> SolveResult:
-    """The plain method: uniform seeds, then Adam until the first satisfying
-    particle or the iteration budget.  The whole budget is enqueued at once as
+                adam: B.CtAdam | None = None, X=None, fixed_grasps: bool = True, init=None) -> SolveResult:
+    """The plain method: uniform seeds (or `init(X, M, V)`, which enqueues
+    another initializer and is timed with the solve), then Adam until the
+    first satisfying particle or the iteration budget.  The whole budget is enqueued at once as
     replays of one captured `chunk`-step graph with a GPU event after each;
     with stop_at_first the device skips every step after the first satisfying
     iteration, so no host polling is needed.  Time to first = GPU time to the
@@ -246,7 +247,10 @@ def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, 
     t_wall = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    gp.seed_uniform(seed, X, M, V, n)
+    if init is None:
+        gp.seed_uniform(seed, X, M, V, n)
+    else:
+        init(X, M, V)
     events = []
     done = 0
     while done < iters:

@@ -111,3 +111,31 @@ def test_null_arguments():
     assert B.LIB.ct_set_split(None, 2) == B.CT_ERR_INVALID_ARG
     with pytest.raises(B.CtError):
         B.ct_problem_info(None)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(d_feat=3), dict(d_noise=6), dict(d_feat=0, d_noise=0), dict(hidden=100), dict(hidden=0),
+    dict(depth=0), dict(depth=9), dict(d_out=0), dict(d_out=513), dict(max_rows=100), dict(max_rows=0),
+])
+def test_mlp_create_rejects_bad_shapes(bad):
+    shape = dict(d_feat=120, d_noise=32, hidden=512, depth=3, d_out=84, max_rows=4096)
+    shape.update(bad)
+    h = C.c_void_p(1234)
+    st = B.LIB.ct_mlp_create(C.byref(B.CtMlpShape(**shape)), C.byref(h))
+    assert st == B.CT_ERR_INVALID_ARG
+    assert h.value is None
+
+
+def test_mlp_null_handles_rejected():
+    adam = B.CtAdam(1e-3, 0.9, 0.999, 1e-8, 1.0)
+    assert B.LIB.ct_mlp_create(None, None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_destroy(None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_info(None, None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_set_params(None, None, None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_forward(None, None, 0, None, None, 0, 0, None, None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_backward(None, None, 64, None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_adam(None, 1, C.byref(adam), None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_imle_step(None, None, 1, None, None, 64, 8, 0, 1, C.byref(adam), None, None,
+                                  None) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_mlp_sample(None, None, 0, None, None, None, None, None, None, None, None, 64, 64,
+                               None) == B.CT_ERR_INVALID_ARG

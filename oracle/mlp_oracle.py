@@ -20,7 +20,9 @@ plain float64 network, the one the pins compare with library routines.
 Training objective: implicit maximum likelihood estimation (Li and Malik,
 "Implicit Maximum Likelihood Estimation", 2018): for every target row draw S
 noise vectors, keep the draw whose output is nearest (squared Euclidean) to
-the target, and take the mean squared error of that output.
+the target, and take the mean squared error of that output.  Optional
+per-entry weights W (0 or 1 in use: which target entries are trusted) enter
+both the distance and the error.
 
 Noise: Box and Muller's transform of uniforms from Philox4x32-10 (the same
 counter-based generator as the uniform initializer).  Noise entry j of a row
@@ -177,19 +179,23 @@ def backward(layers, cache, dY, bf16: bool = True) -> np.ndarray:
 # IMLE
 
 
-def imle_select(Y, T) -> np.ndarray:
-    """Y [B, S, d] outputs of S draws per target, T [B, d] targets: index of the
-    nearest draw (squared Euclidean; the lowest index among equals)."""
-    d2 = ((np.asarray(Y, np.float64) - np.asarray(T, np.float64)[:, None, :]) ** 2).sum(-1)
+def imle_select(Y, T, W=None) -> np.ndarray:
+    """Y [B, S, d] outputs of S draws per target, T [B, d] targets, W [B, d]
+    optional per-entry weights: index of the nearest draw (weighted squared
+    Euclidean distance; the lowest index among equals)."""
+    w = 1.0 if W is None else np.asarray(W, np.float64)[:, None, :]
+    d2 = (w * (np.asarray(Y, np.float64) - np.asarray(T, np.float64)[:, None, :]) ** 2).sum(-1)
     return np.argmin(d2, axis=1)
 
 
-def mse(Y, T):
-    """Mean over rows and columns of (Y - T)^2, and its gradient w.r.t. Y."""
+def mse(Y, T, W=None):
+    """sum of W (Y - T)^2 over rows and columns divided by their count
+    (W = 1: the mean squared error), and its gradient w.r.t. Y."""
     Y, T = np.asarray(Y, np.float64), np.asarray(T, np.float64)
+    w = 1.0 if W is None else np.asarray(W, np.float64)
     diff = Y - T
     n = diff.size
-    return float((diff * diff).sum() / n), 2.0 * diff / n
+    return float((w * diff * diff).sum() / n), 2.0 * w * diff / n
 
 
 def adam(p, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
@@ -201,8 +207,9 @@ def adam(p, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999
 
 
 def imle_step(params, m, v, t: int, dims, feats, feat_of_row, targets, n_draws: int, seed: int,
-              d_noise: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, bf16: bool = True):
-    """One IMLE training step on B target rows.
+              d_noise: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, bf16: bool = True, weights=None):
+    """One IMLE training step on B target rows (optional per-entry weights
+    in the distance and the loss).
 
     Noise of draw s for target row b has counter words (b, s).  Returns
     (params, m, v, loss, chosen draw per row, gradient).
@@ -215,10 +222,10 @@ def imle_step(params, m, v, t: int, dims, feats, feat_of_row, targets, n_draws: 
     ss = np.tile(np.arange(n_draws), B)
     Xall = input_rows(feats, fr[bb], seed, bb, ss, d_noise)
     Yall, _ = forward(layers, Xall, bf16)
-    chosen = imle_select(Yall.reshape(B, n_draws, -1), T)
+    chosen = imle_select(Yall.reshape(B, n_draws, -1), T, weights)
     X = input_rows(feats, fr, seed, np.arange(B), chosen, d_noise)
     Y, cache = forward(layers, X, bf16)
-    loss, dY = mse(Y, T)
+    loss, dY = mse(Y, T, weights)
     g = backward(layers, cache, dY, bf16)
     p1, m1, v1 = adam(np.asarray(params, np.float64), m, v, g, t, lr, beta1, beta2, eps)
     return p1, m1, v1, loss, chosen, g

@@ -150,6 +150,30 @@ def test_imle_select_brute_force_and_ties():
     Y2[0, 1] = Y2[0, 3] = [1.0, 0.0]
     Y2[0, 0] = Y2[0, 2] = [3.0, 0.0]
     assert MO.imle_select(Y2, np.array([[1.0, 0.0]]))[0] == 1
+    # weights: only the second coordinate counts
+    Y3 = np.array([[[0.0, 5.0], [9.0, 1.0]]])
+    assert MO.imle_select(Y3, np.array([[0.0, 0.0]]))[0] == 0
+    assert MO.imle_select(Y3, np.array([[0.0, 0.0]]), np.array([[0.0, 1.0]]))[0] == 1
+    W = rng.integers(0, 2, (6, 3)).astype(float)
+    got = MO.imle_select(Y, T, W)
+    for b in range(6):
+        d = [sum(W[b, k] * (Y[b, s, k] - T[b, k]) ** 2 for k in range(3)) for s in range(5)]
+        assert got[b] == int(np.argmin(d))
+
+
+def test_weighted_mse_brute_force():
+    rng = np.random.default_rng(8)
+    Y, T = rng.standard_normal((2, 4, 3))
+    W = rng.integers(0, 2, (4, 3)).astype(float)
+    loss, g = MO.mse(Y, T, W)
+    assert loss == pytest.approx(sum(W[i, j] * (Y[i, j] - T[i, j]) ** 2 for i in range(4) for j in range(3)) / 12)
+    for i in range(4):
+        for j in range(3):
+            e = np.zeros_like(Y)
+            e[i, j] = 1e-6
+            fd = (MO.mse(Y + e, T, W)[0] - MO.mse(Y - e, T, W)[0]) / 2e-6
+            assert abs(fd - g[i, j]) < 1e-8
+    assert MO.mse(Y, T)[0] == pytest.approx(((Y - T) ** 2).mean())
 
 
 def test_normal_noise_is_standard_normal_and_counter_based():

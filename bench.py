@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
-    ap.add_argument("--learned-scenes", type=int, default=400, help="training scenes for the seed proposer")
-    ap.add_argument("--learned-keep", type=int, default=500, help="particles kept per training scene")
-    ap.add_argument("--learned-epochs", type=int, default=10)
-    ap.add_argument("--eval-scenes", type=int, default=20, help="held-out scenes, learned vs uniform seeds")
+    ap.add_argument("--learned-scenes", type=int, default=200, help="training scenes for the seed proposer")
+    ap.add_argument("--learned-keep", type=int, default=1000, help="particles kept per training scene")
+    ap.add_argument("--learned-steps", type=int, default=2000, help="IMLE training steps (batch 4096)")
+    ap.add_argument("--learned-iters", type=int, default=2000, help="Adam iterations per training-scene solve")
+    ap.add_argument("--eval-scenes", type=int, default=10, help="held-out scenes, learned vs uniform seeds")
     ap.add_argument("--eval-budget", type=int, default=2000, help="Adam iterations per held-out solve")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -100,8 +101,8 @@ def learned_seeds(args, dev, n, iters, q):
 
     lg = lambda m: log("[bench] " + m, q)  # noqa: E731
     t0 = time.perf_counter()
-    data = SD.collect(range(10000, 10000 + args.learned_scenes), robot_seed=args.robot_seed, n=n, iters=iters,
-                      keep=args.learned_keep, log=lg)
+    data = SD.collect(range(10000, 10000 + args.learned_scenes), robot_seed=args.robot_seed, n=n,
+                      iters=args.learned_iters, keep=args.learned_keep, log=lg)
     t_collect = time.perf_counter() - t0
     lg(f"learned: {len(data.targets)} training particles from {args.learned_scenes} scenes in {t_collect:.1f} s "
        f"({data.fully_satisfying} fully satisfying, mean satisfied constraints {data.n_sat.mean():.1f})")
@@ -109,7 +110,7 @@ def learned_seeds(args, dev, n, iters, q):
     batch, draws = 4096, 8
     mlp = SD.GpuMlp(max_rows=batch * draws, device=dev)
     mlp.set_params(torch.from_numpy(I.mlp_init(mlp.dims, 0)))
-    tl = SD.train(mlp, data, stats, epochs=args.learned_epochs, batch=batch, n_draws=draws, lr=1e-3, seed=0)
+    tl = SD.train(mlp, data, stats, steps=args.learned_steps, batch=batch, n_draws=draws, lr=1e-3, seed=0)
     train_tflops = tl.flops / tl.seconds / 1e12
     lg(f"learned: {tl.steps} IMLE steps in {tl.seconds:.2f} s ({train_tflops:.1f} TFLOP/s on the matrix "
        f"products), loss {tl.losses[0]:.3f} -> {tl.losses[-1]:.3f}")
@@ -141,8 +142,9 @@ def learned_seeds(args, dev, n, iters, q):
                 "nothing within the budget); GPU time incl. initialization and seed inference",
         "train": {"scenes": args.learned_scenes, "particles": int(len(data.targets)),
                   "fully_satisfying": int(data.fully_satisfying), "collect_s": t_collect,
-                  "steps": tl.steps, "epochs": args.learned_epochs, "batch": batch, "draws": draws,
-                  "train_s": tl.seconds, "loss_first_epoch": tl.losses[0], "loss_last_epoch": tl.losses[-1],
+                  "trusted_steps": int(round(data.weights.sum() / 21)), "solve_iters": args.learned_iters,
+                  "steps": tl.steps, "batch": batch, "draws": draws,
+                  "train_s": tl.seconds, "loss_first_tenth": tl.losses[0], "loss_last_tenth": tl.losses[-1],
                   "matrix_tflops": train_tflops, "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
                   "mfma_frac": train_tflops / PEAK_BF16_MFMA_TFLOPS},
         "sample_8192_us": sample_s * 1e6,
@@ -151,8 +153,12 @@ def learned_seeds(args, dev, n, iters, q):
                  "learned_first_iter": [r.first_sat_iter for r in cmpr.learned],
                  "uniform_time_s": tu, "learned_time_s": tlr,
                  "learned_with_fallback_time_s": cmpr.learned_fallback,
-                 "uniform_satisfied_at_end": [r.satisfied for r in cmpr.uniform],
-                 "learned_satisfied_at_end": [r.satisfied for r in cmpr.learned]},
+                 "uniform_satisfied_at_end": [r.n_satisfied for r in cmpr.uniform],
+                 "learned_satisfied_at_end": [r.n_satisfied for r in cmpr.learned],
+                 "uniform_converged_step_fraction": cmpr.uniform_steps,
+                 "learned_converged_step_fraction": cmpr.learned_steps,
+                 "uniform_best_particle_steps": cmpr.uniform_best,
+                 "learned_best_particle_steps": cmpr.learned_best},
         "coverage_uniform": cov_u, "coverage_learned_with_fallback": cov_l,
         "equal_satisfaction_rate": rate,
         "time_at_equal_rate_uniform_s": at_u, "time_at_equal_rate_learned_s": at_l,

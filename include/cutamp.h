@@ -380,12 +380,13 @@ int ct_mlp_adam(ct_mlp *mlp, int64_t t, const ct_adam *adam, void *stream);
  * (targets [rows][d_out], standardized; rows a multiple of 64, rows *
  * n_draws <= max_rows): n_draws outputs per target with noise counter
  * words (b, s); the draw whose output is nearest to the target (squared
- * Euclidean, lowest s among equals) is kept; loss = mean over rows and
- * outputs of the squared error; backward; Adam update t.  loss (one float)
- * and chosen (int32 [rows]) may be NULL.
+ * Euclidean distance, each entry weighted by weights[b][d] when weights is
+ * not NULL; lowest s among equals) is kept; loss = sum of the weighted
+ * squared errors / (rows * d_out); backward; Adam update t.  loss (one
+ * float) and chosen (int32 [rows]) may be NULL.
  */
 int ct_mlp_imle_step(ct_mlp *mlp, const float *feats, int64_t n_feats, const int32_t *feat_of_row,
-                     const float *targets, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
+                     const float *targets, const float *weights, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
                      const ct_adam *adam, float *loss, int32_t *chosen, void *stream);
 
 /*

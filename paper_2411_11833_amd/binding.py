@@ -102,7 +102,8 @@ def _load() -> C.CDLL:
         "ct_mlp_forward": (C.c_int, [vp, vp, i64, vp, vp, i64, u64, vp, vp]),
         "ct_mlp_backward": (C.c_int, [vp, vp, i64, vp]),
         "ct_mlp_adam": (C.c_int, [vp, i64, C.POINTER(CtAdam), vp]),
-        "ct_mlp_imle_step": (C.c_int, [vp, vp, i64, vp, vp, i64, i32, u64, i64, C.POINTER(CtAdam), vp, vp, vp]),
+        "ct_mlp_imle_step": (C.c_int, [vp, vp, i64, vp, vp, vp, i64, i32, u64, i64, C.POINTER(CtAdam), vp, vp,
+                                       vp]),
         "ct_mlp_sample": (C.c_int, [vp, vp, u64, vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp]),
     }
     for name, (res, args) in sig.items():
@@ -302,10 +303,10 @@ def ct_mlp_adam(h, t, adam: CtAdam, stream=0):
     _chk(LIB.ct_mlp_adam(h, t, C.byref(adam), stream), "ct_mlp_adam")
 
 
-def ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, rows, n_draws, seed, t, adam: CtAdam,
+def ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, weights, rows, n_draws, seed, t, adam: CtAdam,
                      loss=None, chosen=None, stream=0):
-    _chk(LIB.ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, rows, n_draws, seed, t, C.byref(adam),
-                              loss, chosen, stream), "ct_mlp_imle_step")
+    _chk(LIB.ct_mlp_imle_step(h, feats, n_feats, feat_of_row, targets, weights, rows, n_draws, seed, t,
+                              C.byref(adam), loss, chosen, stream), "ct_mlp_imle_step")
 
 
 def ct_mlp_sample(h, feats, seed, mean, std, lo, hi, wrap, X, M, V, n, ld, stream=0):

@@ -340,7 +340,7 @@ int ct_mlp_backward(ct_mlp* mlp, const float* dY, int64_t rows, void* stream) {
     if (!mlp || !dY || rows <= 0 || rows % 64 != 0 || rows != mlp->fwd_rows) return CT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const float*)nullptr,
-                       mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY, mlp->GYT, mlp->rows_cap, (float*)nullptr);
+                       (const float*)nullptr, mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY, mlp->GYT, mlp->rows_cap, (float*)nullptr);
     const int rc = err_of(hipGetLastError());
     return rc != CT_OK ? rc : backward(mlp, rows, st);
 }
@@ -351,7 +351,7 @@ int ct_mlp_adam(ct_mlp* mlp, int64_t t, const ct_adam* adam_args, void* stream) 
 }
 
 int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row,
-                     const float* targets, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
+                     const float* targets, const float* weights, int64_t rows, int32_t n_draws, uint64_t seed, int64_t t,
                      const ct_adam* adam_args, float* loss, int32_t* chosen, void* stream) {
     if (!mlp || !targets || rows <= 0 || rows % 64 != 0 || n_draws < 1 || t < 1 || !adam_ok(adam_args) ||
         rows * n_draws > mlp->rows_cap || (mlp->s.d_feat > 0 && (!feats || n_feats < 1)))
@@ -362,15 +362,15 @@ int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int
     // 1. every draw, inference only; 2. the nearest draw per target
     int rc = forward(mlp, feats, nf, feat_of_row, nullptr, n_draws, rows * n_draws, seed, false, st);
     if (rc != CT_OK) return rc;
-    hipLaunchKernelGGL(imle_select_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, mlp->s.d_out,
-                       rows, n_draws, sel);
+    hipLaunchKernelGGL(imle_select_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, weights,
+                       mlp->s.d_out, rows, n_draws, sel);
     rc = err_of(hipGetLastError());
     // 3. the kept draws again, keeping activations; 4. squared error
     if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st);
     if (rc != CT_OK) return rc;
     const float scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
-    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, mlp->s.d_out,
-                       mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap, mlp->row_loss);
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, weights,
+                       mlp->s.d_out, mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap, mlp->row_loss);
     if (loss)
         hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, mlp->row_loss, rows,
                            (float)(1.0 / ((double)rows * mlp->s.d_out)), loss);

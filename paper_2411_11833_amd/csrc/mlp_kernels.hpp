@@ -236,7 +236,8 @@ __global__ __launch_bounds__(256) void noise_kernel(const int32_t* draw, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// IMLE: nearest of S draws per target (one wave per target; lowest index on ties)
+// IMLE: nearest of S draws per target by the (optionally weighted) squared
+// distance (one wave per target; lowest index on ties)
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -245,7 +246,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restrict__ Y, const float* __restrict__ T,
-                                                          int d_out, int64_t B, int S, int32_t* __restrict__ chosen) {
+                                                          const float* __restrict__ W, int d_out, int64_t B, int S,
+                                                          int32_t* __restrict__ chosen) {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (b >= B) return;
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
         float acc = 0.f;
         for (int d = lane; d < d_out; d += 64) {
             const float df = y[d] - t[d];
-            acc += df * df;
+            acc += (W ? W[b * d_out + d] : 1.f) * df * df;
         }
         acc = wave_sum(acc);
         if (s == 0 || acc < best) {
@@ -269,9 +271,11 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
 }
 
 // Upstream gradient of the output layer in BF16, both orientations.  With
-// targets: g = scale (y - t) and the row's sum of squares; without: g = y.
+// targets: g = scale w (y - t) and the row's sum of w (y - t)^2 (w = 1 when
+// W is null); without: g = y.
 __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
-                                                       int d_out, int out_pad, int64_t rows, float scale,
+                                                       const float* __restrict__ W, int d_out, int out_pad,
+                                                       int64_t rows, float scale,
                                                        uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT,
                                                        int64_t ldt, float* __restrict__ row_loss) {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -283,9 +287,10 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__
         if (d < d_out) {
             const float y = Y[b * d_out + d];
             if (T) {
+                const float w = W ? W[b * d_out + d] : 1.f;
                 const float df = y - T[b * d_out + d];
-                acc += df * df;
-                gv = scale * df;
+                acc += w * df * df;
+                gv = scale * (w * df);
             } else {
                 gv = y;
             }

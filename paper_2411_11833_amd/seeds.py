@@ -104,13 +104,13 @@ class GpuMlp:
         B.ct_mlp_adam(self.h, self.t, B.CtAdam(lr, beta1, beta2, eps, grad_scale), _stream())
 
     def imle_step(self, feats, feat_of_row, targets, n_draws: int, seed: int, lr: float = 1e-3, chosen=None,
-                  loss=None):
+                  loss=None, weights=None):
         """One training step; returns the (device) loss tensor."""
         self.t += 1
         loss = self._loss if loss is None else loss
         B.ct_mlp_imle_step(self.h, feats.data_ptr(), feats.shape[0], feat_of_row.data_ptr(), targets.data_ptr(),
-                           targets.shape[0], n_draws, seed, self.t, B.CtAdam(lr, 0.9, 0.999, 1e-8, 1.0),
-                           loss.data_ptr(), _ptr(chosen), _stream())
+                           _ptr(weights), targets.shape[0], n_draws, seed, self.t,
+                           B.CtAdam(lr, 0.9, 0.999, 1e-8, 1.0), loss.data_ptr(), _ptr(chosen), _stream())
         return loss
 
     def sample(self, feats_row, seed: int, mean, std, lo, hi, wrap, X, M, V, n: int):
@@ -134,55 +134,155 @@ def wrap_angles(x: np.ndarray, wrap: np.ndarray) -> np.ndarray:
 class Dataset:
     feats: np.ndarray          # [scenes, D_FEAT] raw scene features
     targets: np.ndarray        # [rows, dim] particles (angles wrapped)
+    weights: np.ndarray        # [rows, dim] 1 where the entry's pick-place step satisfies all its constraints
     scene_of_row: np.ndarray   # [rows] int32
     n_sat: np.ndarray          # [rows] satisfied constraint count of each kept particle
     fully_satisfying: int      # kept particles that satisfy every constraint
     gpu_seconds: float
 
 
-def collect(scene_seeds, robot_seed: int = 0, n: int = 8192, iters: int = 500, keep: int = 200,
-            init_seed: int = 1000, log=None) -> Dataset:
-    """Run the plain method (uniform seeds, fixed grasps, `iters` Adam steps)
-    on the 4-object packing scene of every seed and keep each scene's `keep`
-    best final particles.
+def packing_problem(seed: int, robot_seed: int = 0) -> I.Problem:
+    return I.packing(robot_seed, seed)
+
+
+def single_problem(seed: int, robot_seed: int = 0) -> I.Problem:
+    return I.single_pick_place(robot_seed, seed)
+
+
+def collect(scene_seeds, robot_seed: int = 0, n: int = 1024, iters: int = 1000, keep: int = 200,
+            init_seed: int = 1000, log=None, proposer: "Proposer | None" = None, group: int = 64,
+            make=packing_problem) -> Dataset:
+    """Run the plain method (fixed grasps, `iters` Adam steps) on the problem
+    `make(seed)` of every scene seed (default: 4-object packing), `group`
+    scenes at a time in one persistent many-skeleton launch per iteration,
+    and keep each scene's `keep` best final particles.
 
     Reading: the method's converged particles are its particles at the end of
-    the run; they are ranked by the number of constraints they satisfy
-    (Eq. 3, per constraint), then by cost (Eq. 2), so fully satisfying
-    particles come first and the rest are the nearest misses."""
-    feats, rows, sc, nsat = [], [], [], []
+    the run.  A pick-place step of a particle has converged when all of that
+    step's constraints hold (Eq. 3); only converged steps are trusted as
+    targets (weight 1 on their 21 entries, 0 elsewhere).  Particles are ranked
+    by converged steps, then satisfied constraints, then cost (Eq. 2), and
+    particles with no converged step are dropped.
+
+    Runs start from uniform seeds, or with a proposer from its seeds (the
+    next round of self-training: the method refines the proposer's seeds and
+    its converged steps become new targets)."""
+    from .planner import GpuBatch
+    feats, rows, wts, sc, nsat = [], [], [], [], []
     full = 0
     t_gpu = 0.0
-    for j, s in enumerate(scene_seeds):
-        prob = I.packing(robot_seed, int(s))
-        gp = GpuProblem(prob)
-        X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
-        fz = grasp_frozen(prob, gp.device)
+    seeds = [int(s) for s in scene_seeds]
+    adam = default_adam(n)
+    for g0 in range(0, len(seeds), group):
+        chunk = seeds[g0:g0 + group]
+        probs = [make(s, robot_seed) for s in chunk]
+        gb = GpuBatch(probs, [n] * len(chunk))
         t0 = time.perf_counter()
-        gp.seed_uniform(init_seed + int(s), X, M, V, n)
-        adam = default_adam(n)
+        for j, (s, prob) in enumerate(zip(chunk, probs)):
+            if proposer is None:
+                gb.gps[j].seed_uniform(init_seed + s, gb.X[j], gb.M[j], gb.V[j], n)
+            else:
+                proposer.seed(proposer.prepare(prob), init_seed + s, gb.X[j], gb.M[j], gb.V[j], n)
         for t in range(0, iters, 50):       # replays of one captured 50-step graph
-            gp.optimize(X, M, V, n, t, min(50, iters - t), adam, frozen=fz)
-        cost, terms, _ = gp.cost(X, n, terms=True)
+            gb.optimize(t, min(50, iters - t), adam)
         torch.cuda.synchronize()
         t_gpu += time.perf_counter() - t0
-        nc = prob.n_constraint_terms
-        eps = torch.tensor(_tolerances(prob), dtype=torch.float32, device=gp.device)
-        ok = (terms[:nc, :n] <= eps[:, None]).sum(0)
-        c = torch.nan_to_num(cost[:n], nan=float("inf")).cpu().numpy()
-        k = ok.cpu().numpy()
-        order = np.lexsort((c, -k))[:keep]
-        rows.append(gp.to_rows(X, n)[torch.from_numpy(order).to(gp.device)].cpu().numpy())
-        nsat.append(k[order])
-        full += int((k[order] == nc).sum())
-        feats.append(I.scene_features(prob))
-        sc.append(np.full(len(order), j, dtype=np.int32))
-        gp.close()
-        if log and (j + 1) % 50 == 0:
-            log(f"collect: {j + 1}/{len(scene_seeds)} scenes, {full} fully satisfying kept")
-    wrap = I.angle_dims(I.packing(robot_seed, int(scene_seeds[0])))
-    return Dataset(np.stack(feats), wrap_angles(np.concatenate(rows), wrap), np.concatenate(sc),
-                   np.concatenate(nsat), full, t_gpu)
+        for j, (s, prob) in enumerate(zip(chunk, probs)):
+            gp = gb.gps[j]
+            cost, terms, _ = gp.cost(gb.X[j], n, terms=True)
+            nc = prob.n_constraint_terms
+            eps = torch.tensor(_tolerances(prob), dtype=torch.float32, device=gp.device)
+            sat = terms[:nc, :n] <= eps[:, None]
+            K = prob.skeleton.n_steps
+            steps = sat[:I.TERMS_PER_STEP * K].view(K, I.TERMS_PER_STEP, n).all(1)      # [K, n]
+            c = torch.nan_to_num(cost[:n], nan=float("inf")).cpu().numpy()
+            k = sat.sum(0).cpu().numpy()
+            st = steps.cpu().numpy()
+            ns = st.sum(0)
+            order = np.lexsort((c, -k, -ns))[:keep]
+            order = order[ns[order] > 0]
+            rows.append(gp.to_rows(gb.X[j], n)[torch.from_numpy(order).to(gp.device)].cpu().numpy())
+            wts.append(np.repeat(st[:, order].T.astype(np.float32), I.STEP_DIM, axis=1))
+            nsat.append(k[order])
+            full += int((k[order] == nc).sum())
+            feats.append(I.scene_features(prob))
+            sc.append(np.full(len(order), g0 + j, dtype=np.int32))
+        gb.close()
+        for g in gb.gps:
+            g.close()
+        if log:
+            log(f"collect: {g0 + len(chunk)}/{len(seeds)} scenes, {sum(len(r) for r in rows)} particles kept, "
+                f"{full} fully satisfying")
+    wrap = I.angle_dims(make(seeds[0], robot_seed))
+    return Dataset(np.stack(feats), wrap_angles(np.concatenate(rows), wrap), np.concatenate(wts),
+                   np.concatenate(sc), np.concatenate(nsat), full, t_gpu)
+
+
+def collect_steps(scene_seeds, robot_seed: int = 0, n: int = 1024, iters: int = 1000, keep: int = 64,
+                  init_seed: int = 3000, log=None, group: int = 64) -> Dataset:
+    """First-round targets from the method on each pick-place step alone:
+    for every packing scene and every step k, the one-step skeleton that
+    moves object k (the other objects stay where they are, as obstacles) is
+    solved by the plain method (uniform seeds, fixed grasps), `group`
+    skeletons per persistent launch.  Particles that satisfy every
+    constraint of their one-step problem (Eq. 3) become targets for step k of
+    the packing particle: their 21 entries go to step k's block with weight
+    1, the other blocks have weight 0.  At most `keep` per step, lowest cost
+    first.  (The paper's own initializer likewise composes per-action
+    samplers, Sec. V.)"""
+    from .planner import GpuBatch
+    seeds = [int(s) for s in scene_seeds]
+    subs = []   # (scene index, step, problem)
+    packs = []
+    for j, s in enumerate(seeds):
+        pk = I.packing(robot_seed, s)
+        packs.append(pk)
+        for k in range(pk.skeleton.n_steps):
+            sk = I.Skeleton(object_of_step=np.array([pk.skeleton.object_of_step[k]], dtype=np.int32))
+            subs.append((j, k, I.Problem(pk.robot, pk.scene, sk)))
+    D = packs[0].dim
+    rows, wts, sc, nsat = [], [], [], []
+    t_gpu = 0.0
+    adam = default_adam(n)
+    for g0 in range(0, len(subs), group):
+        chunk = subs[g0:g0 + group]
+        gb = GpuBatch([p for _, _, p in chunk], [n] * len(chunk))
+        t0 = time.perf_counter()
+        for i, (j, k, p) in enumerate(chunk):
+            gb.gps[i].seed_uniform(init_seed + 8 * seeds[j] + k, gb.X[i], gb.M[i], gb.V[i], n)
+        for t in range(0, iters, 50):
+            gb.optimize(t, min(50, iters - t), adam)
+        torch.cuda.synchronize()
+        t_gpu += time.perf_counter() - t0
+        for i, (j, k, p) in enumerate(chunk):
+            gp = gb.gps[i]
+            cost, _, m = gp.cost(gb.X[i], n, terms=False)
+            ok = m[:n].bool().cpu().numpy()
+            c = torch.nan_to_num(cost[:n], nan=float("inf")).cpu().numpy()
+            idx = np.nonzero(ok)[0]
+            idx = idx[np.argsort(c[idx], kind="stable")][:keep]
+            if len(idx) == 0:
+                continue
+            blk = gp.to_rows(gb.X[i], n)[torch.from_numpy(idx).to(gp.device)].cpu().numpy()
+            r = np.zeros((len(idx), D))
+            w = np.zeros((len(idx), D), dtype=np.float32)
+            r[:, I.STEP_DIM * k:I.STEP_DIM * (k + 1)] = blk
+            w[:, I.STEP_DIM * k:I.STEP_DIM * (k + 1)] = 1.0
+            rows.append(r)
+            wts.append(w)
+            sc.append(np.full(len(idx), j, dtype=np.int32))
+            nsat.append(np.full(len(idx), I.TERMS_PER_STEP))
+        gb.close()
+        for g in gb.gps:
+            g.close()
+        if log:
+            log(f"collect (one step at a time): {g0 + len(chunk)}/{len(subs)} skeletons, "
+                f"{sum(len(r) for r in rows)} converged steps")
+    wrap = I.angle_dims(packs[0])
+    if not rows:
+        raise RuntimeError("no one-step skeleton produced a satisfying particle")
+    return Dataset(np.stack([I.scene_features(p) for p in packs]), wrap_angles(np.concatenate(rows), wrap),
+                   np.concatenate(wts), np.concatenate(sc), np.concatenate(nsat), 0, t_gpu)
 
 
 def _tolerances(prob: I.Problem) -> list[float]:
@@ -191,10 +291,20 @@ def _tolerances(prob: I.Problem) -> list[float]:
     return per * prob.skeleton.n_steps + [t.motion_coll] * prob.n_motion_terms
 
 
+def merge(a: Dataset, b: Dataset) -> Dataset:
+    """Two collections over the same scene list (b's scene indices follow
+    a's feature rows)."""
+    off = a.feats.shape[0]
+    return Dataset(np.concatenate([a.feats, b.feats]), np.concatenate([a.targets, b.targets]),
+                   np.concatenate([a.weights, b.weights]), np.concatenate([a.scene_of_row, b.scene_of_row + off]),
+                   np.concatenate([a.n_sat, b.n_sat]), a.fully_satisfying + b.fully_satisfying,
+                   a.gpu_seconds + b.gpu_seconds)
+
+
 # --------------------------------------------------------------------------
 # standardization (reading: per-dimension mean / standard deviation over the
-# training set, angles wrapped first; features likewise; a floor keeps
-# near-constant dimensions finite)
+# trusted entries of the training set, angles wrapped first; features
+# likewise over the scenes; a floor keeps near-constant dimensions finite)
 
 
 @dataclass
@@ -206,8 +316,11 @@ class Stats:
 
     @staticmethod
     def of(data: Dataset, floor: float = 1e-3) -> "Stats":
-        return Stats(data.feats.mean(0), np.maximum(data.feats.std(0), floor), data.targets.mean(0),
-                     np.maximum(data.targets.std(0), floor))
+        w = data.weights.astype(np.float64)
+        cnt = np.maximum(w.sum(0), 1.0)
+        mean = (w * data.targets).sum(0) / cnt
+        std = np.sqrt((w * (data.targets - mean) ** 2).sum(0) / cnt)
+        return Stats(data.feats.mean(0), np.maximum(data.feats.std(0), floor), mean, np.maximum(std, floor))
 
     def feats(self, f: np.ndarray) -> np.ndarray:
         return (f - self.feat_mean) / self.feat_std
@@ -222,7 +335,7 @@ class Stats:
 
 @dataclass
 class TrainLog:
-    losses: list = field(default_factory=list)   # mean loss per epoch
+    losses: list = field(default_factory=list)   # mean loss per tenth of the run
     steps: int = 0
     seconds: float = 0.0
     rows_per_s: float = 0.0
@@ -238,38 +351,38 @@ def step_flops(dims, rows: int, n_draws: int) -> float:
     return rows * (n_draws * fwd + fwd + bwd)
 
 
-def train(mlp: GpuMlp, data: Dataset, stats: Stats, epochs: int = 20, batch: int = 4096, n_draws: int = 8,
+def train(mlp: GpuMlp, data: Dataset, stats: Stats, steps: int = 2000, batch: int = 4096, n_draws: int = 8,
           lr: float = 1e-3, seed: int = 0, log=None) -> TrainLog:
     """IMLE training (Li and Malik 2018) on standardized targets: each step
-    draws n_draws noise vectors per target and fits the nearest output."""
+    draws n_draws noise vectors per target and fits the nearest output, on
+    the trusted entries only."""
     dev = mlp.device
     feats = torch.from_numpy(stats.feats(data.feats).astype(np.float32)).to(dev).contiguous()
     T = torch.from_numpy(stats.targets(data.targets).astype(np.float32)).to(dev).contiguous()
+    W = torch.from_numpy(data.weights.astype(np.float32)).to(dev).contiguous()
     S = torch.from_numpy(data.scene_of_row.astype(np.int32)).to(dev).contiguous()
     R = T.shape[0]
-    steps_per_epoch = R // batch
     rng = np.random.default_rng(np.random.SeedSequence([0x7A1, seed]))
     out = TrainLog()
-    losses = torch.zeros(epochs * steps_per_epoch, dtype=torch.float32, device=dev)
+    losses = torch.zeros(steps, dtype=torch.float32, device=dev)
+    # batches drawn as consecutive slices of a fresh permutation per pass
+    order = np.concatenate([rng.permutation(R) for _ in range((steps * batch) // R + 1)])[:steps * batch]
+    order = torch.from_numpy(order.astype(np.int64)).to(dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    k = 0
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(R)[:steps_per_epoch * batch].astype(np.int64)).to(dev)
-        for b in range(steps_per_epoch):
-            idx = perm[b * batch:(b + 1) * batch]
-            Tb = T.index_select(0, idx).contiguous()
-            Sb = S.index_select(0, idx).contiguous()
-            mlp.imle_step(feats, Sb, Tb, n_draws, seed * 1_000_003 + k, lr, loss=losses[k:k + 1])
-            k += 1
-        if log:
-            torch.cuda.synchronize()
-            log(f"epoch {ep + 1}/{epochs}: loss {losses[k - steps_per_epoch:k].mean().item():.4f}")
+    for k in range(steps):
+        idx = order[k * batch:(k + 1) * batch]
+        Tb = T.index_select(0, idx).contiguous()
+        Wb = W.index_select(0, idx).contiguous()
+        Sb = S.index_select(0, idx).contiguous()
+        mlp.imle_step(feats, Sb, Tb, n_draws, seed * 1_000_003 + k, lr, loss=losses[k:k + 1], weights=Wb)
+        if log and (k + 1) % max(1, steps // 10) == 0:
+            log(f"step {k + 1}/{steps}: loss {losses[max(0, k - 49):k + 1].mean().item():.4f}")
     torch.cuda.synchronize()
     out.seconds = time.perf_counter() - t0
-    out.steps = k
-    per = losses.view(epochs, steps_per_epoch).mean(1).cpu().numpy()
-    out.losses = [float(v) for v in per]
+    out.steps = steps
+    per = losses.view(10, -1).mean(1).cpu().numpy() if steps % 10 == 0 else losses.cpu().numpy()
+    out.losses = [float(v) for v in per]   # mean loss per tenth of the run
     out.rows_per_s = k * batch / out.seconds
     out.flops = k * step_flops(mlp.dims, batch, n_draws)
     return out
@@ -308,39 +421,65 @@ class Comparison:
     uniform: list            # SolveResult per scene
     learned: list            # SolveResult per scene (learned seeds only)
     learned_fallback: list   # time to first with the uniform fallback after an unsolved learned run (s or None)
+    uniform_steps: list      # per scene: fraction of (particle, step) pairs whose step holds at the end
+    learned_steps: list
+    uniform_best: list       # per scene: most converged steps in one particle at the end
+    learned_best: list
     budget: int
     n: int
 
 
+def step_convergence(gp: GpuProblem, X, n: int) -> tuple[float, int]:
+    """Fraction of (particle, pick-place step) pairs whose step satisfies all
+    its constraints (Eq. 3 restricted to the step), and the largest number of
+    such steps in one particle."""
+    prob = gp.prob
+    _, terms, _ = gp.cost(X, n, terms=True)
+    K = prob.skeleton.n_steps
+    eps = torch.tensor(_tolerances(prob), dtype=torch.float32, device=gp.device)
+    nc = I.TERMS_PER_STEP * K
+    ok = (terms[:nc, :n] <= eps[:nc, None]).view(K, I.TERMS_PER_STEP, n).all(1)
+    per = ok.sum(0)
+    return float(ok.float().mean().item()), int(per.max().item())
+
+
 def compare(prop: Proposer, scene_seeds, n: int = 8192, budget: int = 500, robot_seed: int = 0,
-            seed: int = 4242, log=None) -> Comparison:
+            seed: int = 4242, log=None, make=packing_problem) -> Comparison:
     """Time to the first satisfying particle from uniform and from learned
     seeds on the same scenes, same budget, same optimizer; a learned run that
     finds nothing within the budget falls back to uniform seeds (its time is
-    the failed learned run plus the uniform run)."""
-    uni, lea, fb = [], [], []
+    the failed learned run plus the uniform run).  Also the per-step
+    convergence at the end of each run."""
+    out = Comparison(list(scene_seeds), [], [], [], [], [], [], [], budget, n)
     for s in scene_seeds:
-        prob = I.packing(robot_seed, int(s))
+        prob = make(int(s), robot_seed)
         gp = GpuProblem(prob)
         pre = prop.prepare(prob)
         adam = default_adam(n)
-        ru = plain_solve(gp, n, budget, seed=seed + int(s), adam=adam)
-        rl = plain_solve(gp, n, budget, seed=seed + int(s), adam=adam,
-                         init=lambda X, M, V: prop.seed(pre, seed + int(s), X, M, V, n))
+        X = gp.empty(n)
+        ru = plain_solve(gp, n, budget, seed=seed + int(s), adam=adam, X=X)
+        su = step_convergence(gp, X, n)
+        rl = plain_solve(gp, n, budget, seed=seed + int(s), adam=adam, X=X,
+                         init=lambda X_, M_, V_: prop.seed(pre, seed + int(s), X_, M_, V_, n))
+        sl = step_convergence(gp, X, n)
         if rl.time_to_first_s is not None:
             f = rl.time_to_first_s
         elif ru.time_to_first_s is not None:
             f = rl.wall_s + ru.time_to_first_s
         else:
             f = None
-        uni.append(ru)
-        lea.append(rl)
-        fb.append(f)
+        out.uniform.append(ru)
+        out.learned.append(rl)
+        out.learned_fallback.append(f)
+        out.uniform_steps.append(su[0])
+        out.learned_steps.append(sl[0])
+        out.uniform_best.append(su[1])
+        out.learned_best.append(sl[1])
         gp.close()
         if log:
-            log(f"scene {s}: uniform first {ru.first_sat_iter} ({ru.time_to_first_s}), "
-                f"learned first {rl.first_sat_iter} ({rl.time_to_first_s}), sat at end {ru.satisfied}/{rl.satisfied}")
-    return Comparison(list(scene_seeds), uni, lea, fb, budget, n)
+            log(f"scene {s}: first satisfying iteration uniform {ru.first_sat_iter} / learned {rl.first_sat_iter}; "
+                f"converged steps uniform {su[0]:.4f} (best {su[1]}) / learned {sl[0]:.4f} (best {sl[1]})")
+    return out
 
 
 def equal_rate_times(times_a, times_b):

@@ -135,7 +135,7 @@ def test_mlp_null_handles_rejected():
     assert B.LIB.ct_mlp_forward(None, None, 0, None, None, 0, 0, None, None) == B.CT_ERR_INVALID_ARG
     assert B.LIB.ct_mlp_backward(None, None, 64, None) == B.CT_ERR_INVALID_ARG
     assert B.LIB.ct_mlp_adam(None, 1, C.byref(adam), None) == B.CT_ERR_INVALID_ARG
-    assert B.LIB.ct_mlp_imle_step(None, None, 1, None, None, 64, 8, 0, 1, C.byref(adam), None, None,
+    assert B.LIB.ct_mlp_imle_step(None, None, 1, None, None, None, 64, 8, 0, 1, C.byref(adam), None, None,
                                   None) == B.CT_ERR_INVALID_ARG
     assert B.LIB.ct_mlp_sample(None, None, 0, None, None, None, None, None, None, None, None, 64, 64,
                                None) == B.CT_ERR_INVALID_ARG

@@ -114,23 +114,27 @@ def test_backward_rejects_rows_other_than_forward():
     m.close()
 
 
-def test_imle_step_matches_oracle():
+@pytest.mark.parametrize("weighted", [False, True])
+def test_imle_step_matches_oracle(weighted):
     name, rows, S = "small", 128, 4
     m, dims, p, feats, fr, _ = _setup(name, rows, seed=2)
     rng = np.random.default_rng(12)
     T = rng.standard_normal((rows, m.d_out)).astype(np.float32)
+    W = rng.integers(0, 2, (rows, m.d_out)).astype(np.float32) if weighted else None
     chosen = torch.zeros(rows, dtype=torch.int32, device="cuda")
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    m.imle_step(_dev(feats), _dev(fr, torch.int32), _dev(T), S, 99, lr=1e-3, chosen=chosen, loss=loss)
+    m.imle_step(_dev(feats), _dev(fr, torch.int32), _dev(T), S, 99, lr=1e-3, chosen=chosen, loss=loss,
+                weights=None if W is None else _dev(W))
     p1 = m.params().cpu().numpy().astype(np.float64)
     g = m.grads().cpu().numpy().astype(np.float64)
     zero = np.zeros_like(p)
-    w1, _, _, wl, wc, wg = MO.imle_step(p, zero, zero, 1, dims, feats, fr, T, S, 99, m.d_noise, 1e-3)
+    w1, _, _, wl, wc, wg = MO.imle_step(p, zero, zero, 1, dims, feats, fr, T, S, 99, m.d_noise, 1e-3, weights=W)
     # choices: identical wherever the choice is clear
     bb = np.repeat(np.arange(rows), S)
     ss = np.tile(np.arange(S), rows)
     Yall, _ = MO.forward(MO.unflatten(p, dims), MO.input_rows(feats, fr[bb], 99, bb, ss, m.d_noise))
-    d2 = np.sort(((Yall.reshape(rows, S, -1) - T[:, None, :]) ** 2).sum(-1), axis=1)
+    Wb = 1.0 if W is None else W[:, None, :]
+    d2 = np.sort((Wb * (Yall.reshape(rows, S, -1) - T[:, None, :]) ** 2).sum(-1), axis=1)
     clear = (d2[:, 1] - d2[:, 0]) > 1e-3 * d2[:, 1]
     got_c = chosen.cpu().numpy()
     assert clear.mean() > 0.9

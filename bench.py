@@ -13,6 +13,11 @@ Also reported on the same JSON line:
     satisfied count after the 500-iteration solves;
   * the roofline position of the fused step kernel: algorithmic flops per
     launch / its average launch time (HIP events on its stream);
+  * the waypoint motion cost (16384 particles) and 64 skeletons of uneven
+    length in one persistent launch per iteration vs one launch each;
+  * learned vs uniform seeds: a BF16 MLP proposer trained on the GPU on the
+    method's converged particles, then time to the first satisfying particle
+    on held-out single pick-place and packing scenes;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -50,11 +55,11 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
-    ap.add_argument("--learned-scenes", type=int, default=200, help="training scenes for the seed proposer")
-    ap.add_argument("--learned-keep", type=int, default=1000, help="particles kept per training scene")
-    ap.add_argument("--learned-steps", type=int, default=2000, help="IMLE training steps (batch 4096)")
-    ap.add_argument("--learned-iters", type=int, default=2000, help="Adam iterations per training-scene solve")
-    ap.add_argument("--eval-scenes", type=int, default=10, help="held-out scenes, learned vs uniform seeds")
+    ap.add_argument("--learned-scenes", type=int, default=2048,
+                    help="packing training scenes for the seed proposer (twice as many single pick-place ones)")
+    ap.add_argument("--learned-steps", type=int, default=10000, help="IMLE training steps of the first round")
+    ap.add_argument("--eval-scenes", type=int, default=10,
+                    help="held-out packing scenes, learned vs uniform seeds (twice as many single pick-place ones)")
     ap.add_argument("--eval-budget", type=int, default=2000, help="Adam iterations per held-out solve")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -94,79 +99,114 @@ def cpu_baseline(prob, budget_s: float):
                       f"{dt:.1f} s"}
 
 
-def learned_seeds(args, dev, n, iters, q):
-    import torch
-    from paper_2411_11833_amd import inputs as I
-    from paper_2411_11833_amd import seeds as SD
-
-    lg = lambda m: log("[bench] " + m, q)  # noqa: E731
+def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, steps, n_eval, eval_scenes,
+                    budget, robot_seed):
+    """Train one seed proposer on the method's converged particles, then time
+    to the first satisfying particle from uniform vs learned seeds on
+    held-out scenes."""
+    batch, draws = 1024, 32
     t0 = time.perf_counter()
-    data = SD.collect(range(10000, 10000 + args.learned_scenes), robot_seed=args.robot_seed, n=n,
-                      iters=args.learned_iters, keep=args.learned_keep, log=lg)
-    t_collect = time.perf_counter() - t0
-    lg(f"learned: {len(data.targets)} training particles from {args.learned_scenes} scenes in {t_collect:.1f} s "
-       f"({data.fully_satisfying} fully satisfying, mean satisfied constraints {data.n_sat.mean():.1f})")
-    stats = SD.Stats.of(data)
-    batch, draws = 4096, 8
-    mlp = SD.GpuMlp(max_rows=batch * draws, device=dev)
+    data = collect(None)
+    lg(f"learned/{name}: round 0: {len(data.targets)} targets ({data.weights.sum() / 21:.0f} converged steps) "
+       f"in {time.perf_counter() - t0:.1f} s")
+    mlp = SD.GpuMlp(d_out=d_out, max_rows=batch * draws, device=dev)
     mlp.set_params(torch.from_numpy(I.mlp_init(mlp.dims, 0)))
-    tl = SD.train(mlp, data, stats, steps=args.learned_steps, batch=batch, n_draws=draws, lr=1e-3, seed=0)
-    train_tflops = tl.flops / tl.seconds / 1e12
-    lg(f"learned: {tl.steps} IMLE steps in {tl.seconds:.2f} s ({train_tflops:.1f} TFLOP/s on the matrix "
-       f"products), loss {tl.losses[0]:.3f} -> {tl.losses[-1]:.3f}")
+    stats = SD.Stats.of(data)
+    logs = [SD.train(mlp, data, stats, steps=steps, batch=batch, n_draws=draws, lr=1e-3, seed=0)]
     prop = SD.Proposer(mlp, stats)
-    # seed inference alone (8192 seeds of one scene)
-    eprob = I.packing(args.robot_seed, 20000)
+    for r in range(1, rounds + 1):
+        data = SD.merge(data, collect(prop))
+        stats = SD.Stats.of(data)
+        prop = SD.Proposer(mlp, stats)
+        logs.append(SD.train(mlp, data, stats, steps=steps // 2, batch=batch, n_draws=draws, lr=1e-3, seed=r))
+        lg(f"learned/{name}: round {r}: {len(data.targets)} targets in total")
+    collect_s = time.perf_counter() - t0 - sum(t.seconds for t in logs)
+    train_s = sum(t.seconds for t in logs)
+    flops = sum(t.flops for t in logs)
+    lg(f"learned/{name}: {sum(t.steps for t in logs)} IMLE steps in {train_s:.2f} s "
+       f"({flops / train_s / 1e12:.1f} TFLOP/s on the matrix products), loss {logs[0].losses[0]:.3f} -> "
+       f"{logs[-1].losses[-1]:.3f}")
+    # seed inference alone: n_eval seeds of one held-out scene
+    eprob = make(eval_scenes[0], robot_seed)
     pre = prop.prepare(eprob)
     from paper_2411_11833_amd.planner import GpuProblem
     eg = GpuProblem(eprob, dev)
-    Xs, Ms, Vs = eg.empty(n), eg.empty(n), eg.empty(n)
-    prop.seed(pre, 1, Xs, Ms, Vs, n)
+    Xs, Ms, Vs = eg.empty(n_eval), eg.empty(n_eval), eg.empty(n_eval)
+    prop.seed(pre, 1, Xs, Ms, Vs, n_eval)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for r in range(20):
-        prop.seed(pre, 2 + r, Xs, Ms, Vs, n)
+        prop.seed(pre, 2 + r, Xs, Ms, Vs, n_eval)
     e1.record()
     torch.cuda.synchronize()
     sample_s = e0.elapsed_time(e1) / 1e3 / 20
     eg.close()
-    cmpr = SD.compare(prop, range(20000, 20000 + args.eval_scenes), n=n, budget=args.eval_budget,
-                      robot_seed=args.robot_seed, log=lg)
+    cmpr = SD.compare(prop, eval_scenes, n=n_eval, budget=budget, robot_seed=robot_seed, make=make)
     tu = [r.time_to_first_s for r in cmpr.uniform]
-    tlr = [r.time_to_first_s for r in cmpr.learned]
+    tl = [r.time_to_first_s for r in cmpr.learned]
     cov_u, cov_l, rate, at_u, at_l = SD.equal_rate_times(tu, cmpr.learned_fallback)
     res = {
-        "kind": "time to the first satisfying particle, plain optimizer (fixed grasps, stop at first) from "
-                "uniform seeds vs from learned seeds (learned run falls back to uniform seeds when it finds "
-                "nothing within the budget); GPU time incl. initialization and seed inference",
-        "train": {"scenes": args.learned_scenes, "particles": int(len(data.targets)),
-                  "fully_satisfying": int(data.fully_satisfying), "collect_s": t_collect,
-                  "trusted_steps": int(round(data.weights.sum() / 21)), "solve_iters": args.learned_iters,
-                  "steps": tl.steps, "batch": batch, "draws": draws,
-                  "train_s": tl.seconds, "loss_first_tenth": tl.losses[0], "loss_last_tenth": tl.losses[-1],
-                  "matrix_tflops": train_tflops, "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
-                  "mfma_frac": train_tflops / PEAK_BF16_MFMA_TFLOPS},
-        "sample_8192_us": sample_s * 1e6,
-        "eval": {"scenes": len(cmpr.scenes), "particles": n, "budget_iters": args.eval_budget,
+        "train": {"rounds": rounds + 1,
+                  "targets": int(len(data.targets)), "converged_steps": int(round(data.weights.sum() / 21)),
+                  "fully_satisfying_targets": int(data.fully_satisfying), "collect_s": collect_s,
+                  "imle_steps": sum(t.steps for t in logs), "batch": batch, "draws": draws, "train_s": train_s,
+                  "loss_start": logs[0].losses[0], "loss_end": logs[-1].losses[-1],
+                  "matrix_tflops": flops / train_s / 1e12, "mfma_bf16_peak_tflops": PEAK_BF16_MFMA_TFLOPS,
+                  "mfma_frac": flops / train_s / 1e12 / PEAK_BF16_MFMA_TFLOPS},
+        "sample_us": sample_s * 1e6,
+        "eval": {"scenes": [int(s) for s in eval_scenes], "particles": n_eval, "budget_iters": budget,
                  "uniform_first_iter": [r.first_sat_iter for r in cmpr.uniform],
                  "learned_first_iter": [r.first_sat_iter for r in cmpr.learned],
-                 "uniform_time_s": tu, "learned_time_s": tlr,
+                 "uniform_time_s": tu, "learned_time_s": tl,
                  "learned_with_fallback_time_s": cmpr.learned_fallback,
-                 "uniform_satisfied_at_end": [r.n_satisfied for r in cmpr.uniform],
-                 "learned_satisfied_at_end": [r.n_satisfied for r in cmpr.learned],
                  "uniform_converged_step_fraction": cmpr.uniform_steps,
                  "learned_converged_step_fraction": cmpr.learned_steps,
                  "uniform_best_particle_steps": cmpr.uniform_best,
                  "learned_best_particle_steps": cmpr.learned_best},
         "coverage_uniform": cov_u, "coverage_learned_with_fallback": cov_l,
+        "coverage_learned_alone": sum(t is not None for t in tl) / len(tl),
         "equal_satisfaction_rate": rate,
         "time_at_equal_rate_uniform_s": at_u, "time_at_equal_rate_learned_s": at_l,
+        "mean_converged_step_fraction_uniform": float(np.mean(cmpr.uniform_steps)),
+        "mean_converged_step_fraction_learned": float(np.mean(cmpr.learned_steps)),
     }
-    lg(f"learned: coverage uniform {cov_u:.2f} vs learned(+fallback) {cov_l:.2f}; at rate {rate:.2f}: "
-       f"uniform {at_u} s vs learned {at_l} s; 8192 seeds in {sample_s * 1e6:.0f} us")
+    lg(f"learned/{name}: coverage uniform {cov_u:.2f} vs learned {res['coverage_learned_alone']:.2f} "
+       f"(with fallback {cov_l:.2f}); at rate {rate:.2f}: uniform {at_u} s vs learned {at_l} s; converged steps "
+       f"{res['mean_converged_step_fraction_uniform']:.4f} vs {res['mean_converged_step_fraction_learned']:.4f}")
     mlp.close()
     return res
+
+
+def learned_seeds(args, dev, n, q):
+    import torch
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd import seeds as SD
+
+    lg = lambda m: log("[bench] " + m, q)  # noqa: E731
+    rs = args.robot_seed
+    out = {
+        "kind": "time to the first satisfying particle (Eq. 3), plain optimizer with fixed grasps and stop at "
+                "first, from uniform seeds vs from the learned proposer's seeds (a learned run that finds "
+                "nothing in its budget falls back to uniform seeds); GPU time incl. initialization and seed "
+                "inference. Proposer: 152-512-512-512-out BF16 MLP trained on the GPU by IMLE (batch 1024, 32 "
+                "draws) on converged pick-place steps the method produced on training scenes 10000+; "
+                "held-out scenes 20000+.",
+    }
+    sc1 = range(10000, 10000 + 2 * args.learned_scenes)
+    out["single_pick_place"] = _learned_family(
+        SD, I, torch, dev, lg, "single", SD.single_problem, 21,
+        lambda prop: SD.collect(sc1, robot_seed=rs, n=1024, iters=3000, keep=64, proposer=prop,
+                                make=SD.single_problem),
+        0, args.learned_steps, 256, list(range(20000, 20000 + 2 * args.eval_scenes)), 3000, rs)
+    sc2 = range(10000, 10000 + args.learned_scenes)
+    out["packing"] = _learned_family(
+        SD, I, torch, dev, lg, "packing", SD.packing_problem, 84,
+        lambda prop: (SD.collect_steps(sc2, robot_seed=rs, n=1024, iters=3000, keep=64) if prop is None else
+                      SD.collect(sc2, robot_seed=rs, n=1024, iters=1000, keep=64, proposer=prop,
+                                 init_seed=5000)),
+        1, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs)
+    return out
 
 
 def main():
@@ -351,7 +391,7 @@ def main():
     # GPU, then time-to-first from learned vs uniform seeds on held-out scenes
     learned = None
     if not args.no_learned:
-        learned = learned_seeds(args, dev, n, iters, q)
+        learned = learned_seeds(args, dev, n, q)
 
     out = {
         "metric": METRIC,

@@ -37,6 +37,31 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
 
+# HBM traffic of one step-kernel launch (packing, 8192 particles, split 2)
+# from rocprofv3 counters, FETCH_SIZE and WRITE_SIZE in separate runs, KiB per
+# dispatch, each scaled by what the same counter read for a 256 MiB device copy
+# in the same run (FETCH_SIZE reads half the bytes: factor 2.0; WRITE_SIZE 1.0).
+# Valid only for the kernel sources it was measured on (hash below).
+STEP_TRAFFIC = {"sources": "9ae235311f6bcc83", "fetch_kib": 3898.6, "fetch_factor": 2.0,
+                "write_kib": 6539.0, "write_factor": 1.0}
+STEP_SOURCES = ("paper_2411_11833_amd/csrc/particle_kernel.hpp", "paper_2411_11833_amd/csrc/ct_tables.hpp",
+                "paper_2411_11833_amd/csrc/pk_instances.hip")
+
+
+def step_traffic_bytes():
+    """Measured bytes per launch, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in STEP_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != STEP_TRAFFIC["sources"]:
+        return None
+    t = STEP_TRAFFIC
+    return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -430,8 +455,9 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-            "traffic": None,
-            "kernel": "ct::particle_kernel<4,S,MODE_STEP>",
+            "traffic": step_traffic_bytes() if (split == 2 and n == 8192) else None,
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": f"ct::particle_kernel<{split},MODE_STEP,4>",
             "kernel_us": kernel_s * 1e6,
             "flop_per_particle_iter": wk.flops,
             "algorithmic_bytes_per_launch": wk.bytes * n,

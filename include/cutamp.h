@@ -248,10 +248,12 @@ int ct_optimize(ct_problem *problem, float *X, float *M, float *V, int64_t n, in
 
 /*
  * Kernel shape: split = how many lanes share one particle configuration's
- * sphere list (1, 2 or 4; 0 = library default).  ct_autotune times every
- * supported split on a copy of the given particles (it allocates and frees
- * scratch copies; X is not modified) and keeps the fastest; *chosen (host,
- * may be NULL) receives it.
+ * sphere list (1, 2 or 4; 0 = automatic: per call, the smallest split that
+ * gives at least two workgroups per compute unit for that call's n).
+ * ct_get_split reports the set value (0 = automatic).  ct_autotune times
+ * every supported split on a copy of the given particles (it allocates and
+ * frees scratch copies; X is not modified) and keeps the fastest; *chosen
+ * (host, may be NULL) receives it.
  */
 int ct_set_split(ct_problem *problem, int32_t split);
 int ct_get_split(const ct_problem *problem, int32_t *split);

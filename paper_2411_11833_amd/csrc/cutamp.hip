@@ -84,7 +84,14 @@ ct::Box to_box(const double* b) {
     return o;
 }
 
-int default_split(int K) { return K <= 1 ? 4 : (K <= 2 ? 2 : 1); }
+// Without a tuned choice: the smallest split that gives at least two
+// workgroups per compute unit (512 on gfx950's 256 CUs); a workgroup holds
+// 256 / (2K split) particles, so the condition is n * 2K * split >= 512 * 256.
+int default_split(int K, int64_t n) {
+    for (int s = 1; s < 4; s *= 2)
+        if (n * 2 * K * s >= int64_t(512) * 256) return s;
+    return 4;
+}
 
 // n == 0 is an empty batch: only the handle and ld are checked
 bool empty_ok(const ct_problem* P, int64_t n, int64_t ld) { return P && n == 0 && ld >= 0 && ld % 64 == 0; }
@@ -134,11 +141,11 @@ BatchFn pick_batch(int split) {
     }
 }
 
-int effective_split(const ct_problem* P) { return P->split ? P->split : default_split(P->K); }
+int effective_split(const ct_problem* P, int64_t n) { return P->split ? P->split : default_split(P->K, n); }
 
 int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0) {
     if (a.n == 0) return CT_OK;
-    PkFn f = pick_kernel(split ? split : effective_split(P), P->K, mode);
+    PkFn f = pick_kernel(split ? split : effective_split(P, a.n), P->K, mode);
     if (!f) return CT_ERR_UNSUPPORTED;
     return err_of(f(P->d, a, st));
 }
@@ -472,7 +479,7 @@ extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t 
     GraphKey key;
     key.X = X; key.M = M; key.V = V; key.cost = cost; key.mask = mask; key.first_sat = first_sat;
     key.frozen = frozen; key.n = n; key.ld = ld; key.iters = iters;
-    key.split = effective_split(P);
+    key.split = effective_split(P, n);
     key.stop = stop_at_first ? 1 : 0;
     key.lr = adam->lr; key.b1 = adam->beta1; key.b2 = adam->beta2; key.eps = adam->eps;
     key.gs = adam->grad_scale;
@@ -519,7 +526,7 @@ extern "C" int ct_set_split(ct_problem* P, int32_t split) {
 
 extern "C" int ct_get_split(const ct_problem* P, int32_t* split) {
     if (!P || !split) return CT_ERR_INVALID_ARG;
-    *split = effective_split(P);
+    *split = P->split;
     return CT_OK;
 }
 
@@ -541,7 +548,7 @@ extern "C" int ct_autotune(ct_problem* P, const float* X, int64_t n, int64_t ld,
     const ct_adam adam{1e-2f, 0.9f, 0.999f, 1e-8f, 1.f / (float)n};
     const int cands[3] = {1, 2, 4};
     float best = 1e30f;
-    int best_split = default_split(P->K);
+    int best_split = default_split(P->K, n);
     int rc = CT_OK;
     for (int c : cands) {
         if (hipMemcpyAsync(Xs, X, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) { rc = CT_ERR_DEVICE; break; }

@@ -62,12 +62,15 @@ struct Tables {
     float eps[E_N];
     float region_lo[2], region_hi[2];
     float4 rs[CT_MAX_ROBOT_SPHERES];           // (x, y, z, r) in the parent frame, grouped by link
+    float4 lbs[10];                            // per link L: sphere (centre in the link frame, radius) holding
+                                               // all of L's robot spheres, radius grown by a margin; w < 0: none
     SBox sbox[CT_MAX_STATIC_BOXES];
     Box obj0[CT_MAX_STEPS];                    // moved object of step k at its initial pose
     float p0_yaw[CT_MAX_STEPS];                // its initial yaw
     float place_z[CT_MAX_STEPS];               // centre height when placed on the table
     float grasp_lo[CT_MAX_STEPS][3], grasp_hi[CT_MAX_STEPS][3];
     float4 os[CT_MAX_STEPS][CT_MAX_OBJ_SPHERES];  // object spheres (object frame) of step k's object
+    float4 obs[CT_MAX_STEPS];                  // sphere holding all of step k's object spheres (as lbs)
     float lo[CT_MAX_STEPS * CT_STEP_DIM];      // uniform-initialization box
     float hi[CT_MAX_STEPS * CT_STEP_DIM];
 };

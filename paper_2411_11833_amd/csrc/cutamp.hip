@@ -51,6 +51,27 @@ namespace {
 
 bool is_fin(double v) { return std::isfinite(v); }
 
+// A sphere holding every sphere of a set (centre = mean of the centres,
+// radius = largest |c_i - centre| + r_i), computed in double from the FP32
+// values the kernels use and grown by a relative 1e-6 and 0.1 mm so that an
+// FP32 test against it can only err towards "touches".  w = -1: empty set.
+float4 bounding_sphere(const float4* sp, int n) {
+    if (n <= 0) return make_float4(0.f, 0.f, 0.f, -1.f);
+    double c[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        c[0] += sp[i].x;
+        c[1] += sp[i].y;
+        c[2] += sp[i].z;
+    }
+    for (double& v : c) v /= n;
+    double rad = 0;
+    for (int i = 0; i < n; ++i) {
+        const double dx = sp[i].x - c[0], dy = sp[i].y - c[1], dz = sp[i].z - c[2];
+        rad = std::max(rad, std::sqrt(dx * dx + dy * dy + dz * dz) + (double)sp[i].w);
+    }
+    return make_float4((float)c[0], (float)c[1], (float)c[2], (float)(rad * (1 + 1e-6) + 1e-4));
+}
+
 bool valid_box(const double* b) {
     for (int i = 0; i < 7; ++i)
         if (!is_fin(b[i])) return false;
@@ -287,6 +308,9 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
             }
     }
     T.link_start[9] = cnt;
+    for (int L = 0; L < 10; ++L)
+        T.lbs[L] = (L >= 1 && L <= 8) ? bounding_sphere(T.rs + T.link_start[L], T.link_start[L + 1] - T.link_start[L])
+                                      : make_float4(0.f, 0.f, 0.f, -1.f);
     // boxes that never move
     int nb = 0;
     T.sbox[nb++] = to_sbox(scene->table);
@@ -309,6 +333,7 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
             const double* sp = scene->obj_spheres + 4 * (o * T.n_os + m);
             T.os[k][m] = make_float4((float)sp[0], (float)sp[1], (float)sp[2], (float)sp[3]);
         }
+        T.obs[k] = bounding_sphere(T.os[k], T.n_os);
         // uniform-initialization box of step k's 21 coordinates
         float* lo = T.lo + CT_STEP_DIM * k;
         float* hi = T.hi + CT_STEP_DIM * k;

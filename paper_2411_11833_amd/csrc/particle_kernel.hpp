@@ -120,16 +120,49 @@ struct MoveCtx<0> {
 // the box.  Accumulates the unweighted penetration, each sphere's weighted
 // centre gradient, and the weighted gradient with respect to the placements
 // rho_j of boxes placed by earlier steps.
+// Boxes that the bounding sphere (world centre w, radius rb) of some lane's
+// sphere set touches: bit b of smask for static box b, bit j of omask for
+// moved object j.  The masks are wave-uniform (ballot), so the sphere loops
+// skip a box only when no lane of the wave needs it.  The bound holds every
+// sphere of the set with a margin, so a skipped box touches none of them and
+// every penetration sum is unchanged.
+template <int KT>
+__device__ __forceinline__ void touched_boxes(const Tables* __restrict__ T, const MoveCtx<KT>& mc, float wx,
+                                              float wy, float wz, float rb, uint32_t& smask, uint32_t& omask) {
+    const float r2 = rb * rb;
+    smask = 0u;
+    omask = 0u;
+    const int nsb = T->n_static;
+    for (int b = 0; b < nsb; ++b) {
+        const SBox B = T->sbox[b];
+        const float px = fmaf(B.c, wx, fmaf(B.s, wy, B.u0));
+        const float py = fmaf(B.c, wy, fmaf(-B.s, wx, B.u1));
+        const float pz = wz - B.tz;
+        if (__ballot(box_d2(px, py, pz, B.hx, B.hy, B.hz) < r2)) smask |= 1u << b;
+    }
+#pragma unroll
+    for (int j = 0; j < mc.count(); ++j) {
+        const Box O = T->obj0[j];
+        float bx, by, bc, bs;
+        mc.pose(T, j, bx, by, bc, bs);
+        const float dx = wx - bx, dy = wy - by;
+        const float px = bc * dx + bs * dy, py = bc * dy - bs * dx, pz = wz - O.cz;
+        const bool hit = j != mc.k && box_d2(px, py, pz, O.hx, O.hy, O.hz) < r2;
+        if (__ballot(hit)) omask |= 1u << j;
+    }
+}
+
 template <int KT, int NB, bool GRAD>
-__device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const MoveCtx<KT>& mc,
-                                             const float (&cx)[NB], const float (&cy)[NB], const float (&cz)[NB],
-                                             const float (&r)[NB], float lam, float& pen_sum, float (&gx)[NB],
-                                             float (&gy)[NB], float (&gz)[NB], float* __restrict__ gr) {
+__device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const MoveCtx<KT>& mc, uint32_t smask,
+                                             uint32_t omask, const float (&cx)[NB], const float (&cy)[NB],
+                                             const float (&cz)[NB], const float (&r)[NB], float lam,
+                                             float& pen_sum, float (&gx)[NB], float (&gy)[NB], float (&gz)[NB],
+                                             float* __restrict__ gr) {
     float r2[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) r2[m] = r[m] * r[m];
-    const int nsb = T->n_static;
-    for (int b = 0; b < nsb; ++b) {
+    for (uint32_t mm = smask; mm; mm &= mm - 1u) {   // the static boxes some lane's set touches
+        const int b = __builtin_ctz(mm);
         const SBox B = T->sbox[b];
         bool act[NB];
         bool any = false;
@@ -156,6 +189,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
     }
 #pragma unroll
     for (int j = 0; j < mc.count(); ++j) {   // wave-uniform trip count
+        if (!((omask >> j) & 1u)) continue;   // wave-uniform
         const Box O = T->obj0[j];
         const bool placed = j < mc.k;
         float bx, by, bc, bs;
@@ -230,8 +264,9 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
 // Accumulates the link's wrench (force f, moment tq about the world origin).
 template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, int s1, int j0, int si,
-                                          const float R[9], const float t[3], const MoveCtx<KT>& mc, float lam,
-                                          float& coll, float f[3], float tq[3], float* __restrict__ gr) {
+                                          const float R[9], const float t[3], const MoveCtx<KT>& mc, uint32_t smask,
+                                          uint32_t omask, float lam, float& coll, float f[3], float tq[3],
+                                          float* __restrict__ gr) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -251,7 +286,7 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
         gx[m] = gy[m] = gz[m] = 0.f;
     }
     float pen = 0.f;
-    run_vs_world<KT, NB, GRAD>(T, mc, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
     coll += pen;
     if (GRAD) {
 #pragma unroll
@@ -271,10 +306,19 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L
                                              const float t[3], const MoveCtx<KT>& mc, float lam, float& coll,
                                              float f[3], float tq[3], float* __restrict__ gr) {
     const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
+    if (s1 == s0) return;
+    const float4 lb = T->lbs[L];
+    uint32_t smask, omask;
+    touched_boxes<KT>(T, mc, R[0] * lb.x + R[1] * lb.y + R[2] * lb.z + t[0],
+                      R[3] * lb.x + R[4] * lb.y + R[5] * lb.z + t[1], R[6] * lb.x + R[7] * lb.y + R[8] * lb.z + t[2],
+                      lb.w, smask, omask);
+    if (!(smask | omask)) return;   // wave-uniform: no sphere of the link touches any box
     const int per_lane = (s1 - s0 + SPLIT - 1) / SPLIT;
     int j = 0;
-    for (; j + RUN <= per_lane; j += RUN) robot_run<KT, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mc, lam, coll, f, tq, gr);
-    for (; j < per_lane; ++j) robot_run<KT, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mc, lam, coll, f, tq, gr);
+    for (; j + RUN <= per_lane; j += RUN)
+        robot_run<KT, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j)
+        robot_run<KT, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
 }
 
 // Runs of object spheres (table osl, object frame) transformed by (R, t):
@@ -283,8 +327,8 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L
 template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const float4* __restrict__ osl, int nos,
                                            int j0, int si, const float R[9], const float t[3], const MoveCtx<KT>& mc,
-                                           float lam, float& coll, float f[3], float tq[3],
-                                           float* __restrict__ gr) {
+                                           uint32_t smask, uint32_t omask, float lam, float& coll, float f[3],
+                                           float tq[3], float* __restrict__ gr) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -297,7 +341,7 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
         gx[m] = gy[m] = gz[m] = 0.f;
     }
     float pen = 0.f;
-    run_vs_world<KT, NB, GRAD>(T, mc, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
     coll += pen;
     if (GRAD) {
 #pragma unroll
@@ -312,13 +356,21 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
 
 template <int KT, int SPLIT, bool GRAD>
 __device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const float4* __restrict__ osl,
-                                               int nos, int si, const float R[9], const float t[3],
+                                               int nos, float4 ob, int si, const float R[9], const float t[3],
                                                const MoveCtx<KT>& mc, float lam, float& coll, float f[3],
                                                float tq[3], float* __restrict__ gr) {
+    if (nos <= 0) return;
+    uint32_t smask, omask;
+    touched_boxes<KT>(T, mc, R[0] * ob.x + R[1] * ob.y + R[2] * ob.z + t[0],
+                      R[3] * ob.x + R[4] * ob.y + R[5] * ob.z + t[1], R[6] * ob.x + R[7] * ob.y + R[8] * ob.z + t[2],
+                      ob.w, smask, omask);
+    if (!(smask | omask)) return;   // wave-uniform: the held object touches no box
     const int per_lane = (nos + SPLIT - 1) / SPLIT;
     int j = 0;
-    for (; j + RUN <= per_lane; j += RUN) object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, lam, coll, f, tq, gr);
-    for (; j < per_lane; ++j) object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, lam, coll, f, tq, gr);
+    for (; j + RUN <= per_lane; j += RUN)
+        object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+    for (; j < per_lane; ++j)
+        object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
 }
 
 // dist_from_bounds of v against [lo, hi] and its gradient (scaled by lam).
@@ -415,7 +467,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                              te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
                              te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, si, RO, tO, mc, lam, coll, fo, to, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, T->obs[k], si, RO, tO, mc, lam, coll, fo, to, gr);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
             // object turns about the tool z-axis through the tool origin
@@ -654,7 +706,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
         const float tp[3] = {rho_x, rho_y, T->place_z[k]};
         float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, T->obs[k], si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
         if (GRAD) {
             // translation: the force; turning about the vertical through the
             // placement origin: z of the moment about that point

@@ -9,7 +9,8 @@
 // Work decomposition (one workgroup = 256 lanes = 4 wave64s):
 //   * a particle owns 2K "slots", one per robot configuration (q_grasp and
 //     q_place of each step); each slot is served by SPLIT adjacent lanes that
-//     share its sphere list.  A workgroup holds P = 256 / (2K SPLIT) particles.
+//     share its sphere list.  A workgroup holds P = 256 / (2K SPLIT) particles;
+//     lanes are slot-major, so a wave holds the same slot of many particles.
 //   * phase 0 stages the particles' columns of the dimension-major X in LDS
 //     (coalesced rows), phase 1 runs every lane's configuration: forward
 //     kinematics, sphere transforms, sphere-vs-box penetration with its
@@ -877,12 +878,14 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
     }
     __syncthreads();
 
-    // phase 1: every lane evaluates its slot
+    // phase 1: every lane evaluates its slot.  Lanes are slot-major (the SPLIT
+    // lanes of a slot adjacent, then the tile's particles, then the slots), so
+    // a wave serves one or two slots of many particles: the same step and kind
+    // of configuration, hence uniform branches and coherent box masks.
     {
-        const int p = tid / LPP;
-        if (p < P) {
-            const int rem = tid - p * LPP;
-            const int slot = rem / SPLIT, si = rem - slot * SPLIT;
+        const int si = tid % SPLIT, rest = tid / SPLIT;
+        const int slot = rest / P, p = rest - slot * P;
+        if (slot < SLOTS) {
             const int64_t i = p0 + p;
             const bool wt = (MODE == MODE_COST) && io.terms != nullptr && i < n;
             const LaneOut o = lane_slot<KT, SPLIT, MODE>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,

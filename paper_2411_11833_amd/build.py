@@ -49,7 +49,7 @@ def _run(cmd, verbose):
 def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | None = None,
           out: str | None = None, objdir: str | None = None) -> str:
     """Compile every HIP source and link the in-tree shared library (always
-    recompiles).  `extra` adds hipcc flags (e.g. -DCT_RUN=1); `out` / `objdir`
+    recompiles).  `extra` adds hipcc flags; `out` / `objdir`
     redirect the library and objects.  Returns the library path."""
     lib = out or LIB
     obj_dir = objdir or OBJ

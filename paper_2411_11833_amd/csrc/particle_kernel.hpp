@@ -157,8 +157,8 @@ template <int KT, int NB, bool GRAD>
 __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const MoveCtx<KT>& mc, uint32_t smask,
                                              uint32_t omask, const float (&cx)[NB], const float (&cy)[NB],
                                              const float (&cz)[NB], const float (&r)[NB], float lam,
-                                             float& pen_sum, float (&gx)[NB], float (&gy)[NB], float (&gz)[NB],
-                                             float* __restrict__ gr) {
+                                             float (&pen_sum)[NB], float (&gx)[NB], float (&gy)[NB],
+                                             float (&gz)[NB], float* __restrict__ gr) {
     float r2[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) r2[m] = r[m] * r[m];
@@ -182,7 +182,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
                 if (act[m]) {
                     float pen, ax, ay, az;
                     pair_hit(px[m], py[m], pz[m], r[m], B.c, B.s, B.hx, B.hy, B.hz, lam, pen, ax, ay, az);
-                    pen_sum += pen;
+                    pen_sum[m] += pen;
                     if (GRAD) { gx[m] += ax; gy[m] += ay; gz[m] += az; }
                 }
             }
@@ -215,7 +215,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
                 if (act[m]) {
                     float pen, ax, ay, az;
                     pair_hit(px[m], py[m], pz[m], r[m], bc, bs, O.hx, O.hy, O.hz, lam, pen, ax, ay, az);
-                    pen_sum += pen;
+                    pen_sum[m] += pen;
                     if (GRAD) {
                         gx[m] += ax; gy[m] += ay; gz[m] += az;
                         if (placed) {
@@ -240,11 +240,11 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t G) {
     return x * q + (x < rem ? x : rem) + b / NX;
 }
 
-// spheres tested together against each box (independent dependency chains)
-#ifndef CT_RUN
-#define CT_RUN 2
-#endif
-constexpr int RUN = CT_RUN;
+// Spheres tested together against each box (independent dependency chains,
+// one box load per run): 4 in the single-skeleton kernels, 2 in the
+// many-skeleton kernel, whose run-time skeleton length leaves fewer registers.
+template <int KT>
+constexpr int run_len() { return KT > 0 ? 4 : 2; }
 
 template <int SPLIT>
 __device__ __forceinline__ float split_sum(float v) {
@@ -286,9 +286,14 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
         cz[m] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
         gx[m] = gy[m] = gz[m] = 0.f;
     }
-    float pen = 0.f;
+    // per-sphere sums over boxes, added to coll in sphere order: the same
+    // additions in the same order whatever the run length
+    float pen[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) pen[m] = 0.f;
     run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
-    coll += pen;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) coll += pen[m];
     if (GRAD) {
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
@@ -300,8 +305,9 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
     }
 }
 
-// All robot spheres of link L: runs of 2, then 1, over the (wave-uniform)
-// number of entries each lane of the slot handles.
+// All robot spheres of link L: runs of run_len, then 2, then 1, over the
+// (wave-uniform) number of entries each lane of the slot handles, against the
+// boxes the link's bounding sphere may touch.
 template <int KT, int SPLIT, bool GRAD>
 __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L, int si, const float R[9],
                                              const float t[3], const MoveCtx<KT>& mc, float lam, float& coll,
@@ -316,8 +322,13 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L
     if (!(smask | omask)) return;   // wave-uniform: no sphere of the link touches any box
     const int per_lane = (s1 - s0 + SPLIT - 1) / SPLIT;
     int j = 0;
+    constexpr int RUN = run_len<KT>();
     for (; j + RUN <= per_lane; j += RUN)
         robot_run<KT, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+    if (RUN > 2 && j + 2 <= per_lane) {
+        robot_run<KT, SPLIT, 2, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        j += 2;
+    }
     for (; j < per_lane; ++j)
         robot_run<KT, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
 }
@@ -341,9 +352,14 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
         cz[m] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
         gx[m] = gy[m] = gz[m] = 0.f;
     }
-    float pen = 0.f;
+    // per-sphere sums over boxes, added to coll in sphere order: the same
+    // additions in the same order whatever the run length
+    float pen[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) pen[m] = 0.f;
     run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
-    coll += pen;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) coll += pen[m];
     if (GRAD) {
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
@@ -368,8 +384,13 @@ __device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, con
     if (!(smask | omask)) return;   // wave-uniform: the held object touches no box
     const int per_lane = (nos + SPLIT - 1) / SPLIT;
     int j = 0;
+    constexpr int RUN = run_len<KT>();
     for (; j + RUN <= per_lane; j += RUN)
         object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+    if (RUN > 2 && j + 2 <= per_lane) {
+        object_run<KT, SPLIT, 2, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        j += 2;
+    }
     for (; j < per_lane; ++j)
         object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
 }

@@ -67,6 +67,9 @@ class CtError(RuntimeError):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2411_11833_amd.build`")
+    # torch first: the library must bind to the HIP runtime that owns torch's
+    # device memory and streams (the one torch loaded), not load a second one
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i64, i32, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64
     sig = {

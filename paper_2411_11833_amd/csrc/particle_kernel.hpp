@@ -995,7 +995,7 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
 // ---------------------------------------------------------------------------
 // One skeleton of KT steps: one workgroup per tile (XCD-aware tile order).
 template <int SPLIT, int MODE, int KT>
-__global__ __launch_bounds__(WG) void particle_kernel(
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void particle_kernel(
     const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
     float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
     int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,

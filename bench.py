@@ -316,6 +316,22 @@ def main():
     log(f"[bench] step kernel: {kernel_s * 1e6:.1f} us avg over {reps} launches; "
         f"{achieved:.2f} TFLOP/s (model {wk.flops} flop/particle-iter)", q)
 
+    # ---- plan-skeleton feasibility heuristic (Eq. 5) on the solved particles
+    _, terms_b, _ = gp.cost(X, n, terms=True)
+    counts_b, H_b = gp.feasibility(terms_b, n)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(20):
+        gp.feasibility(terms_b, n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    feas = {"H": float(H_b.item()), "penalty": -n, "constraints": int(counts_b.numel()),
+            "unsatisfied_constraints": int((counts_b == 0).sum().item()),
+            "us": e0.elapsed_time(e1) * 1e3 / 20,
+            "note": "on the particles after the 200 stand-alone step launches; includes the counts and H kernels"}
+    log(f"[bench] feasibility heuristic: H = {feas['H']:.1f} ({feas['unsatisfied_constraints']} of "
+        f"{feas['constraints']} constraints never satisfied) in {feas['us']:.1f} us", q)
+
     # ---- time to the first satisfying particle (plain method, stop at first)
     ttf = []
     for seed in (4242, 4243, 4244):
@@ -446,6 +462,7 @@ def main():
         },
         "first_sat_iter_full_run": None if first_iter_full == INT32_MAX else first_iter_full,
         "satisfied_after_full_run": sat_end,
+        "feasibility": feas,
         "motion": motion,
         "batch": batch,
         "learned_seeds": learned,

@@ -260,6 +260,19 @@ int ct_get_split(const ct_problem *problem, int32_t *split);
 int ct_autotune(ct_problem *problem, const float *X, int64_t n, int64_t ld, int32_t *chosen,
                 void *stream);
 
+/*
+ * Plan-skeleton feasibility heuristic, Eq. (5): counts[c] = number of
+ * particles i < n whose constraint term c satisfies J_c <= eps_c (terms as
+ * written by ct_cost, layout [n_terms][ld]; a NaN term never counts), for
+ * every constraint term c < n_constraint; H = (1/n_constraint) sum_c h_c
+ * with h_c = counts[c] when positive, else `penalty` (the paper's large
+ * negative Lambda_penalty, e.g. -N).  counts (device int32[n_constraint])
+ * and H (device float) may each be NULL (counts then live in the handle).
+ * The heuristic ranks skeletons before refinement (Sec. VI).
+ */
+int ct_feasibility(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, float penalty,
+                   int32_t *counts, float *H, void *stream);
+
 /* ------------------------------------------------------------------------
  * Many skeletons at once (the backtracking search of Alg. 1 keeps several
  * skeletons' particle batches alive; each is optimized on its own batch mean,

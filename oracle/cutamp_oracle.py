@@ -13,6 +13,7 @@ the oracle's own cost.  References are to the paper (Shen et al.,
 * weighted relaxation  J(x) = sum lambda_c J_c + soft costs ... Eq. (2)
 * satisfaction test  AND_c J_c <= eps_c ...................... Eq. (3)
 * batch objective (mean over the N_b particles) ............. Eq. (4)
+* plan-skeleton feasibility heuristic H ...................... Eq. (5)
 * Adam on that objective ..................................... Sec. IV-B
 * Kin(q,o,g,p): FK(q) = p * g, pose error .................... Sec. III, App. listing of example cost functions
 * distance from bounds, pairwise object distance ............. App. listing of example cost functions
@@ -43,7 +44,7 @@ __all__ = [
     "rz", "rx", "trans", "fk_frames", "box_sdf", "sphere_box_penalty", "pose_error",
     "dist_from_bounds", "pairwise_dist_sum", "grasp_tf", "place_tf", "evaluate",
     "Evaluation", "terms", "cost", "mask", "cost_and_grad", "adam_step", "margins",
-    "weights_vector", "tolerance_vector", "place_z",
+    "weights_vector", "tolerance_vector", "place_z", "feasibility",
 ]
 
 
@@ -423,6 +424,16 @@ def mask(prob: Problem, T: np.ndarray) -> np.ndarray:
     its tolerance (<=; a NaN term is never satisfied)."""
     nc = prob.n_constraint_terms
     return np.all(T[:, :nc] <= tolerance_vector(prob)[None], axis=1)
+
+
+def feasibility(prob: Problem, T: np.ndarray, penalty: float):
+    """Eq. (5): per constraint term c, the number of particles with
+    J_c <= eps_c (NaN never), and H = mean over the constraint terms of
+    h_c = that count when positive, else the penalty."""
+    nc = prob.n_constraint_terms
+    counts = np.sum(np.asarray(T)[:, :nc] <= tolerance_vector(prob)[None], axis=0)
+    h = np.where(counts > 0, counts.astype(np.float64), float(penalty))
+    return counts, float(h.mean())
 
 
 def cost_and_grad(prob: Problem, X, chunk: int = 128):

@@ -87,6 +87,7 @@ def _load() -> C.CDLL:
         "ct_set_split": (C.c_int, [vp, i32]),
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
+        "ct_feasibility": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
         "ct_batch_create": (C.c_int, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(i64), C.POINTER(i64), C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]),
@@ -220,6 +221,10 @@ def ct_autotune(h, X, n, ld, stream=0) -> int:
     s = C.c_int32()
     _chk(LIB.ct_autotune(h, X, n, ld, C.byref(s), stream), "ct_autotune")
     return s.value
+
+
+def ct_feasibility(h, terms, n, ld, penalty, counts=None, H=None, stream=0):
+    _chk(LIB.ct_feasibility(h, terms, n, ld, penalty, counts, H, stream), "ct_feasibility")
 
 
 def _ptrs(vals):

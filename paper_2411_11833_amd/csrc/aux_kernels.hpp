@@ -67,4 +67,49 @@ __global__ __launch_bounds__(256) void adam_kernel(int D, float* __restrict__ X,
 // Device counter of applied Adam updates, set before a captured loop.
 __global__ void counter_set_kernel(int32_t* c, int32_t v) { *c = v; }
 
+// Tolerance of constraint term c (per step: Kin position / rotation at the
+// pick and at the place, grasp box, placement, two joint-limit terms, three
+// collision terms; then the motion-collision terms).
+__device__ __forceinline__ float term_eps(const Tables* __restrict__ T, int c) {
+    if (c >= CT_TERMS_PER_STEP * T->K) return T->eps[E_MCOLL];
+    switch (c % CT_TERMS_PER_STEP) {
+        case T_PICK_POS: case T_PLACE_POS: return T->eps[E_KPOS];
+        case T_PICK_ROT: case T_PLACE_ROT: return T->eps[E_KROT];
+        case T_GRASP: return T->eps[E_GRASP];
+        case T_PLACE: return T->eps[E_PLACE];
+        case T_JLIM_G: case T_JLIM_P: return T->eps[E_JLIM];
+        default: return T->eps[E_COLL];
+    }
+}
+
+// Plan-skeleton feasibility, Eq. (5): one workgroup per constraint term
+// counts the particles with J_c <= eps_c (reads coalesced along particles; a
+// NaN term never counts), fixed-order tree reduction.
+__global__ __launch_bounds__(256) void feas_count_kernel(const Tables* __restrict__ T, const float* __restrict__ terms,
+                                                         int64_t n, int64_t ld, int32_t* __restrict__ counts) {
+    __shared__ int red[256];
+    const int c = blockIdx.x;
+    const float e = term_eps(T, c);
+    int cnt = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) cnt += terms[(int64_t)c * ld + i] <= e ? 1 : 0;
+    red[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[c] = red[0];
+}
+
+// H = (1 / |con|) sum_c h_c, h_c = counts[c] if positive else the penalty;
+// summed in constraint order by one lane (integers and the penalty are exact
+// in FP32 up to 2^24, so only the division rounds).
+__global__ void feas_h_kernel(const int32_t* __restrict__ counts, int nc, float penalty, float* __restrict__ H) {
+    if (threadIdx.x != 0) return;
+    float s = 0.f;
+    for (int c = 0; c < nc; ++c) s += counts[c] > 0 ? (float)counts[c] : penalty;
+    *H = nc > 0 ? s / (float)nc : 0.f;
+}
+
 }  // namespace ct
+

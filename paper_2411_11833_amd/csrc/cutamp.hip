@@ -43,7 +43,8 @@ struct ct_problem {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t capture_stream = nullptr;
-    int32_t* t_dev = nullptr;   // two-slot device counter of applied updates for captured loops
+    int32_t* t_dev = nullptr;   // two-slot device counter of applied updates for captured loops,
+                                // followed by n_constraint per-constraint counts (feasibility)
     GraphKey key;
 };
 
@@ -367,7 +368,7 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
         delete P;
         return CT_ERR_ALLOC;
     }
-    if (hipMalloc(&P->t_dev, 2 * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(&P->t_dev, (2 + (size_t)P->nc) * sizeof(int32_t)) != hipSuccess) {
         hipFree(P->d);
         delete P;
         return CT_ERR_ALLOC;
@@ -390,6 +391,18 @@ extern "C" int ct_problem_destroy(ct_problem* P) {
     if (P->t_dev) hipFree(P->t_dev);
     delete P;
     return CT_OK;
+}
+
+extern "C" int ct_feasibility(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float penalty,
+                              int32_t* counts, float* H, void* stream) {
+    if (!P || !std::isfinite(penalty)) return CT_ERR_INVALID_ARG;
+    if (n < 0 || ld < n || ld % 64 != 0 || (n > 0 && !terms)) return CT_ERR_INVALID_ARG;
+    if (terms && ((uintptr_t)terms % 256)) return CT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t* cnt = counts ? counts : P->t_dev + 2;
+    hipLaunchKernelGGL(ct::feas_count_kernel, dim3(P->nc), dim3(256), 0, st, P->d, terms, n, ld, cnt);
+    if (H) hipLaunchKernelGGL(ct::feas_h_kernel, dim3(1), dim3(64), 0, st, cnt, P->nc, penalty, H);
+    return err_of(hipGetLastError());
 }
 
 extern "C" int ct_problem_info(const ct_problem* P, int32_t* dim, int32_t* n_terms, int32_t* n_constraint) {

@@ -76,6 +76,16 @@ class GpuProblem:
                   m.data_ptr() if m is not None else None, _stream())
         return c, T, m
 
+    def feasibility(self, terms, n: int, penalty: float | None = None):
+        """Eq. (5) on a terms buffer from cost(..., terms=True): per-constraint
+        satisfying counts (int32 [n_constraint]) and H (float [1]), on the
+        device; the penalty defaults to -n."""
+        counts = torch.empty(self.n_constraint, dtype=torch.int32, device=self.device)
+        H = torch.empty(1, dtype=torch.float32, device=self.device)
+        B.ct_feasibility(self.handle, terms.data_ptr(), n, terms.shape[1], float(-n if penalty is None else penalty),
+                         counts.data_ptr(), H.data_ptr(), _stream())
+        return counts, H
+
     def cost_grad(self, X, n: int, weights=None):
         c = torch.empty(n, dtype=torch.float32, device=self.device)
         G = self.empty(n)

@@ -139,3 +139,7 @@ def test_mlp_null_handles_rejected():
                                   None) == B.CT_ERR_INVALID_ARG
     assert B.LIB.ct_mlp_sample(None, None, 0, None, None, None, None, None, None, None, None, 64, 64,
                                None) == B.CT_ERR_INVALID_ARG
+
+
+def test_feasibility_rejects_bad_arguments():
+    assert B.LIB.ct_feasibility(None, None, 0, 64, -1.0, None, None, None) == B.CT_ERR_INVALID_ARG

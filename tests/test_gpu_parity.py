@@ -465,3 +465,36 @@ def test_batch_autotune_keeps_particles():
     assert split in (1, 2) and wg > 0
     for x, x0, m, v in zip(b.X, X0, b.M, b.V):
         assert torch.equal(x, x0) and torch.all(m == 0) and torch.all(v == 0)
+
+
+def test_feasibility_heuristic_matches_oracle():
+    """Eq. (5) on the GPU: per-constraint satisfying counts equal the
+    oracle's except for particles inside the mask band of that constraint;
+    H equals the oracle's H computed from the GPU-equal counts."""
+    prob = I.packing(0, 0)
+    gp = _gp(prob)
+    n = 1000
+    X = I.uniform_particles(prob, n, seed=21)
+    c, T, m = gp.cost(gp.from_rows(X), n, terms=True)
+    counts, H = gp.feasibility(T, n, penalty=-n)
+    torch.cuda.synchronize()
+    To = O.terms(prob, X.astype(np.float64))
+    co, Ho = O.feasibility(prob, To, -n)
+    flip, _ = O.margins(prob, X.astype(np.float64))
+    band = (flip <= 1e-4).sum(0)
+    got = counts.cpu().numpy()
+    assert np.all(np.abs(got - co) <= band), (got, co, band)
+    assert (co == 0).any() and (co > 0).any()   # both branches of h
+    nc = prob.n_constraint_terms
+    Hg = float(H.item())
+    h = np.where(got > 0, got, -n).astype(np.float64)
+    assert Hg == pytest.approx(h.sum() / nc, rel=1e-6)
+    if np.array_equal(got, co):
+        assert Hg == pytest.approx(Ho, rel=1e-6)
+    # counts kept in the handle when no buffer is given
+    from paper_2411_11833_amd import binding as B
+    H2 = torch.empty(1, device="cuda")
+    B.ct_feasibility(gp.handle, T.data_ptr(), n, T.shape[1], float(-n), None, H2.data_ptr(),
+                     torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert float(H2.item()) == Hg

@@ -373,3 +373,27 @@ def test_held_object_follows_the_tool():
     np.testing.assert_allclose((torch.linalg.inv(obj) @ F)[0, :3, 3].numpy(), g[0, :3].numpy(), atol=1e-14)
     p, rr = O.pose_error(F, obj @ G)
     assert float(p) < 1e-14 and float(rr) < 1e-7
+
+
+def test_feasibility_heuristic_brute_force_and_special_cases():
+    """Eq. (5) against loops over particles and constraints, and its two
+    closed cases (everything satisfied; one constraint never satisfied)."""
+    prob = I.packing(0, 0)
+    nc = prob.n_constraint_terms
+    eps = O.tolerance_vector(prob)
+    rng = np.random.default_rng(3)
+    N = 37
+    T = rng.uniform(0, 2, (N, prob.n_terms)) * np.concatenate([eps * 2 + 1e-3, np.ones(prob.n_terms - nc)])
+    T[5, 3] = np.nan
+    counts, H = O.feasibility(prob, T, -N)
+    for c in range(nc):
+        want = sum(1 for i in range(N) if T[i, c] <= eps[c])
+        assert counts[c] == want
+    hs = [counts[c] if counts[c] > 0 else -N for c in range(nc)]
+    assert H == pytest.approx(sum(hs) / nc)
+    Z = np.zeros((N, prob.n_terms))
+    c0, h0 = O.feasibility(prob, Z, -N)
+    assert np.all(c0 == N) and h0 == N
+    Z[:, 7] = 1.0          # joint-limit term of step 0 (tolerance 0) never satisfied
+    c1, h1 = O.feasibility(prob, Z, -1000.0)
+    assert c1[7] == 0 and h1 == pytest.approx(((nc - 1) * N - 1000.0) / nc)

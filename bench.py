@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
+    ap.add_argument("--sampling-iters", type=int, default=1000, help="Adam iterations of the one-step problems")
     ap.add_argument("--learned-scenes", type=int, default=2048,
                     help="packing training scenes for the seed proposer (twice as many single pick-place ones)")
     ap.add_argument("--learned-steps", type=int, default=10000, help="IMLE training steps of the first round")
@@ -201,6 +203,48 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
        f"{res['mean_converged_step_fraction_uniform']:.4f} vs {res['mean_converged_step_fraction_learned']:.4f}")
     mlp.close()
     return res
+
+
+def compositional(args, dev, n, q):
+    import torch
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd.planner import GpuProblem, default_adam, plain_solve
+    from paper_2411_11833_amd.sampling import CompositionalInit
+
+    scenes = list(range(20000, 20000 + args.eval_scenes))
+    n_sub, budget = 8192, args.eval_budget
+    first, times, counts = [], [], []
+    for s in scenes:
+        prob = I.packing(args.robot_seed, s)
+        gp = GpuProblem(prob, dev)
+        ci = CompositionalInit(prob, n_sub, dev)
+        seed = 4242 + s
+        # warm-up: capture the graphs of this problem's loops
+        plain_solve(gp, n, 10, seed=seed, adam=default_adam(n),
+                    init=lambda X, M, V: ci.run(seed, 50, X, M, V, n))
+        r = plain_solve(gp, n, budget, seed=seed, adam=default_adam(n),
+                        init=lambda X, M, V: ci.run(seed, args.sampling_iters, X, M, V, n))
+        first.append(r.first_sat_iter)
+        times.append(r.time_to_first_s)
+        counts.append([int(c) for c in ci.count.cpu().numpy()])
+        log(f"[bench] compositional init, scene {s}: first satisfying particle after {r.first_sat_iter} refinement "
+            f"iterations, {r.time_to_first_s} s (satisfying one-step particles per step {counts[-1]})", q)
+        ci.close()
+        gp.close()
+    solved = [t for t in times if t is not None]
+    return {
+        "kind": "time to the first satisfying particle (Eq. 3) from compositional initialization: each pick-place "
+                "step solved alone by the plain optimizer (one-step skeletons, all steps in one persistent launch "
+                f"per iteration, {n_sub} particles each, {args.sampling_iters} iterations), satisfying one-step "
+                "particles composed into packing particles, then the plain optimizer on the whole skeleton with "
+                "stop at first; GPU time from the start of initialization",
+        "scenes": scenes, "particles": n, "one_step_particles": n_sub, "one_step_iters": args.sampling_iters,
+        "refine_budget": budget, "refine_first_iter": first, "time_to_first_s": times,
+        "satisfying_one_step_particles": counts,
+        "coverage": len(solved) / len(scenes),
+        "median_time_to_first_s": float(np.median(solved)) if solved else None,
+        "max_time_to_first_s": max(solved) if solved else None,
+    }
 
 
 def learned_seeds(args, dev, n, q):
@@ -428,6 +472,12 @@ def main():
             f"{res_b['per_skeleton'] * 1e3:.1f} ms for {bi} iterations (split {bsplit}, {bwg} workgroups)", q)
         gb.close()
 
+    # ---- compositional initialization (one-step problems, then composition and
+    # refinement) on the held-out packing scenes
+    sampling = None
+    if not args.no_sampling:
+        sampling = compositional(args, dev, n, q)
+
     # ---- learned seeds: collect converged particles, train the proposer on the
     # GPU, then time-to-first from learned vs uniform seeds on held-out scenes
     learned = None
@@ -465,6 +515,7 @@ def main():
         "feasibility": feas,
         "motion": motion,
         "batch": batch,
+        "compositional_init": sampling,
         "learned_seeds": learned,
         "roofline": {
             "bound": "alu",

@@ -273,6 +273,21 @@ int ct_autotune(ct_problem *problem, const float *X, int64_t n, int64_t ld, int3
 int ct_feasibility(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, float penalty,
                    int32_t *counts, float *H, void *stream);
 
+/*
+ * Compositional initialization (Sec. V): the particles of a skeleton are
+ * assembled from the solutions of smaller problems, one block of rows at a
+ * time.  ct_compact writes the indices i < n with mask[i] != 0, in index
+ * order, to idx (device int32[n]) and their number to *count (device int32).
+ * ct_gather_block sets X[row0 + r][i] = Xs[r][j] for r < rows, i < n, with
+ * j = idx[i mod c] when c = *count > 0 (count may be NULL: c = 0), else
+ * j = i mod n_src, and zeroes the same rows of M and V (each may be NULL).
+ * Xs is [rows][lds] (lds >= n_src), X, M, V are [>= row0 + rows][ld].
+ */
+int ct_compact(const uint8_t *mask, int64_t n, int32_t *idx, int32_t *count, void *stream);
+int ct_gather_block(const float *Xs, int64_t lds, int32_t rows, int64_t n_src, const int32_t *idx,
+                    const int32_t *count, float *X, float *M, float *V, int64_t ld, int32_t row0, int64_t n,
+                    void *stream);
+
 /* ------------------------------------------------------------------------
  * Many skeletons at once (the backtracking search of Alg. 1 keeps several
  * skeletons' particle batches alive; each is optimized on its own batch mean,

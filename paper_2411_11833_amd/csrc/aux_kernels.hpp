@@ -111,5 +111,48 @@ __global__ void feas_h_kernel(const int32_t* __restrict__ counts, int nc, float 
     *H = nc > 0 ? s / (float)nc : 0.f;
 }
 
+// Indices of the set entries of a mask, in index order (one workgroup of
+// 1024 lanes; each lane scans a contiguous chunk, then a block-wide prefix
+// sum of the chunk counts places the chunks).
+__global__ __launch_bounds__(1024) void compact_kernel(const uint8_t* __restrict__ mask, int64_t n,
+                                                       int32_t* __restrict__ idx, int32_t* __restrict__ count) {
+    __shared__ int32_t pre[1024];
+    const int tid = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t a = tid * chunk, b = a + chunk < n ? a + chunk : n;
+    int32_t c = 0;
+    for (int64_t i = a; i < b; ++i) c += mask[i] ? 1 : 0;
+    pre[tid] = c;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan
+        const int32_t v = tid >= o ? pre[tid - o] : 0;
+        __syncthreads();
+        pre[tid] += v;
+        __syncthreads();
+    }
+    int32_t w = pre[tid] - c;
+    for (int64_t i = a; i < b; ++i)
+        if (mask[i]) idx[w++] = (int32_t)i;
+    if (tid == 1023) *count = pre[1023];
+}
+
+// X[row0 + r][i] = Xs[r][j(i)] for r < rows, i < n, with j(i) = idx[i mod c]
+// when c = *count > 0, else i mod n_src; M and V of those rows zeroed.
+__global__ __launch_bounds__(256) void gather_block_kernel(const float* __restrict__ Xs, int64_t lds, int rows,
+                                                           const int32_t* __restrict__ idx,
+                                                           const int32_t* __restrict__ count, int64_t n_src,
+                                                           float* __restrict__ X, float* __restrict__ M,
+                                                           float* __restrict__ V, int64_t ld, int row0, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = count ? *count : 0;
+    const int64_t j = c > 0 ? (int64_t)idx[i % c] : i % n_src;
+    for (int r = 0; r < rows; ++r) {
+        X[(int64_t)(row0 + r) * ld + i] = Xs[(int64_t)r * lds + j];
+        if (M) M[(int64_t)(row0 + r) * ld + i] = 0.f;
+        if (V) V[(int64_t)(row0 + r) * ld + i] = 0.f;
+    }
+}
+
 }  // namespace ct
 

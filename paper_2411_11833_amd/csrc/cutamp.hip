@@ -405,6 +405,23 @@ extern "C" int ct_feasibility(const ct_problem* P, const float* terms, int64_t n
     return err_of(hipGetLastError());
 }
 
+extern "C" int ct_compact(const uint8_t* mask, int64_t n, int32_t* idx, int32_t* count, void* stream) {
+    if (n < 0 || n > INT32_MAX || !count || (n > 0 && (!mask || !idx))) return CT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(ct::compact_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, mask, n, idx, count);
+    return err_of(hipGetLastError());
+}
+
+extern "C" int ct_gather_block(const float* Xs, int64_t lds, int32_t rows, int64_t n_src, const int32_t* idx,
+                               const int32_t* count, float* X, float* M, float* V, int64_t ld, int32_t row0,
+                               int64_t n, void* stream) {
+    if (rows < 0 || row0 < 0 || n < 0 || ld < n || ld % 64 != 0 || n_src < 0 || lds < n_src) return CT_ERR_INVALID_ARG;
+    if (n == 0 || rows == 0) return CT_OK;
+    if (!Xs || !X || n_src == 0 || (count && !idx)) return CT_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(ct::gather_block_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       Xs, lds, rows, idx, count, n_src, X, M, V, ld, row0, n);
+    return err_of(hipGetLastError());
+}
+
 extern "C" int ct_problem_info(const ct_problem* P, int32_t* dim, int32_t* n_terms, int32_t* n_constraint) {
     if (!P) return CT_ERR_INVALID_ARG;
     if (dim) *dim = P->D;

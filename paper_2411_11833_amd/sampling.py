@@ -1,0 +1,80 @@
+"""Compositional initialization (Sec. V "Particle Initialization"): the
+particles of a K-step pick-place skeleton are assembled from the solutions
+of K one-step problems, one per pick-place action, instead of drawn
+uniformly.
+
+Each one-step problem moves object k alone (the other objects stay where
+they start, as obstacles): its particle is one grasp (sampled, then held
+fixed), the pick and place configurations (solved: the plain optimizer on
+the Kin, joint-limit, collision and placement costs of that action) and one
+placement.  All K problems run together, one persistent many-skeleton launch
+per iteration.  Step k of composed particle i then takes the i-th (cyclically)
+one-step particle that satisfies all of its constraints (Eq. 3), or, when
+none does, one-step particle i as it stands.  The composed batch is refined
+by the plain optimizer on the whole skeleton, which resolves what the
+one-step problems could not see (placed objects, the goal cost).
+
+Readings: the paper's samplers solve IK with cuRobo; here the same fused
+cost restricted to one action, optimized by the same kernels, is the
+conditional configuration sampler.  Choosing satisfying particles first is
+the composition-with-rejection of the paper's sampling networks.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+from . import inputs as I
+from .planner import GpuBatch, _stream, default_adam
+
+
+def one_step_problems(prob: I.Problem) -> list[I.Problem]:
+    """One problem per pick-place step: the same robot and scene, the
+    skeleton reduced to that step's object."""
+    return [I.Problem(prob.robot, prob.scene,
+                      I.Skeleton(object_of_step=np.array([prob.skeleton.object_of_step[k]], dtype=np.int32)),
+                      prob.weights, prob.tolerances)
+            for k in range(prob.skeleton.n_steps)]
+
+
+class CompositionalInit:
+    """Buffers and handles for initializing one skeleton's particles by
+    composition; reusable across calls (nothing is allocated per call)."""
+
+    def __init__(self, prob: I.Problem, n_sub: int, device="cuda"):
+        self.prob = prob
+        self.n_sub = n_sub
+        self.device = torch.device(device)
+        self.subs = one_step_problems(prob)
+        self.batch = GpuBatch(self.subs, [n_sub] * len(self.subs), self.device)
+        K = len(self.subs)
+        self.idx = torch.empty((K, n_sub), dtype=torch.int32, device=self.device)
+        self.count = torch.empty(K, dtype=torch.int32, device=self.device)
+        self.cost = torch.empty(n_sub, dtype=torch.float32, device=self.device)
+        self.mask = torch.empty((K, n_sub), dtype=torch.uint8, device=self.device)
+
+    def close(self):
+        self.batch.close()
+        for g in self.batch.gps:
+            g.close()
+
+    def run(self, seed: int, iters: int, X, M, V, n: int, chunk: int = 50):
+        """Enqueue the one-step solves (uniform seeds, fixed grasps, `iters`
+        Adam steps), the satisfaction masks of their final particles, and the
+        composition into X (M, V zeroed).  No host synchronization."""
+        gb = self.batch
+        gb.seed(seed)
+        adam = default_adam(1)   # the batch uses 1/n per skeleton
+        for t in range(0, iters, chunk):
+            gb.optimize(t, min(chunk, iters - t), adam)
+        st = _stream()
+        for k, g in enumerate(gb.gps):
+            B.ct_cost(g.handle, gb.X[k].data_ptr(), self.n_sub, gb.X[k].shape[1], self.cost.data_ptr(), None,
+                      self.mask[k].data_ptr(), st)
+            B.ct_compact(self.mask[k].data_ptr(), self.n_sub, self.idx[k].data_ptr(),
+                         self.count[k:k + 1].data_ptr(), st)
+            B.ct_gather_block(gb.X[k].data_ptr(), gb.X[k].shape[1], I.STEP_DIM, self.n_sub, self.idx[k].data_ptr(),
+                              self.count[k:k + 1].data_ptr(), X.data_ptr(),
+                              None if M is None else M.data_ptr(), None if V is None else V.data_ptr(),
+                              X.shape[1], I.STEP_DIM * k, n, st)

@@ -33,7 +33,10 @@ import time
 import numpy as np
 
 METRIC = "particle-iters/s (fwd+bwd+Adam); time-to-satisfy: plain vs learned seeds"
-PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate (packed FP32)
+# the same ALUs without packed FP32 instructions, which this build does not
+# emit: 256 CU x 4 SIMD x 16 lanes x 2 flop per FMA x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
 
@@ -81,7 +84,8 @@ def parse():
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
-    ap.add_argument("--sampling-iters", type=int, default=1000, help="Adam iterations of the one-step problems")
+    ap.add_argument("--sampling-iters", type=int, default=1500,
+                    help="most Adam iterations of the one-step problems before refining the composition")
     ap.add_argument("--learned-scenes", type=int, default=2048,
                     help="packing training scenes for the seed proposer (twice as many single pick-place ones)")
     ap.add_argument("--learned-steps", type=int, default=10000, help="IMLE training steps of the first round")
@@ -206,9 +210,8 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
 
 
 def compositional(args, dev, n, q):
-    import torch
     from paper_2411_11833_amd import inputs as I
-    from paper_2411_11833_amd.planner import GpuProblem, default_adam, plain_solve
+    from paper_2411_11833_amd.planner import GpuProblem
     from paper_2411_11833_amd.sampling import CompositionalInit
 
     scenes = list(range(20000, 20000 + args.eval_scenes))
@@ -219,27 +222,25 @@ def compositional(args, dev, n, q):
         gp = GpuProblem(prob, dev)
         ci = CompositionalInit(prob, n_sub, dev)
         seed = 4242 + s
-        # warm-up: capture the graphs of this problem's loops
-        plain_solve(gp, n, 10, seed=seed, adam=default_adam(n),
-                    init=lambda X, M, V: ci.run(seed, 50, X, M, V, n))
-        r = plain_solve(gp, n, budget, seed=seed, adam=default_adam(n),
-                        init=lambda X, M, V: ci.run(seed, args.sampling_iters, X, M, V, n))
+        ci.solve(gp, n, seed, max_iters=200, first_check=100, refine_budget=20)   # captures the loops' graphs
+        r = ci.solve(gp, n, seed, max_iters=args.sampling_iters, first_check=200, chunk=100, refine_budget=budget)
         first.append(r.first_sat_iter)
         times.append(r.time_to_first_s)
         counts.append([int(c) for c in ci.count.cpu().numpy()])
-        log(f"[bench] compositional init, scene {s}: first satisfying particle after {r.first_sat_iter} refinement "
-            f"iterations, {r.time_to_first_s} s (satisfying one-step particles per step {counts[-1]})", q)
+        log(f"[bench] compositional init, scene {s}: first satisfying particle after {r.first_sat_iter} iterations "
+            f"(one-step + refinement), {r.time_to_first_s} s (satisfying one-step particles per step {counts[-1]})", q)
         ci.close()
         gp.close()
     solved = [t for t in times if t is not None]
     return {
         "kind": "time to the first satisfying particle (Eq. 3) from compositional initialization: each pick-place "
                 "step solved alone by the plain optimizer (one-step skeletons, all steps in one persistent launch "
-                f"per iteration, {n_sub} particles each, {args.sampling_iters} iterations), satisfying one-step "
-                "particles composed into packing particles, then the plain optimizer on the whole skeleton with "
-                "stop at first; GPU time from the start of initialization",
-        "scenes": scenes, "particles": n, "one_step_particles": n_sub, "one_step_iters": args.sampling_iters,
-        "refine_budget": budget, "refine_first_iter": first, "time_to_first_s": times,
+                f"per iteration, {n_sub} particles each); from 200 iterations on, every 100 iterations the "
+                "satisfying one-step particles are composed into packing particles and tested; after "
+                f"{args.sampling_iters} one-step iterations the composition is refined by the plain optimizer "
+                "with stop at first; GPU time from the start of initialization",
+        "scenes": scenes, "particles": n, "one_step_particles": n_sub, "one_step_iters_max": args.sampling_iters,
+        "refine_budget": budget, "first_iter": first, "time_to_first_s": times,
         "satisfying_one_step_particles": counts,
         "coverage": len(solved) / len(scenes),
         "median_time_to_first_s": float(np.median(solved)) if solved else None,
@@ -523,6 +524,8 @@ def main():
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+            "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "traffic": step_traffic_bytes() if (split == 2 and n == 8192) else None,
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": f"ct::particle_kernel<{split},MODE_STEP,4>",

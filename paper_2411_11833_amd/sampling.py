@@ -21,12 +21,14 @@ the composition-with-rejection of the paper's sampling networks.
 """
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import torch
 
 from . import binding as B
 from . import inputs as I
-from .planner import GpuBatch, _stream, default_adam
+from .planner import INT32_MAX, GpuBatch, GpuProblem, SolveResult, _stream, default_adam, grasp_frozen
 
 
 def one_step_problems(prob: I.Problem) -> list[I.Problem]:
@@ -68,6 +70,11 @@ class CompositionalInit:
         adam = default_adam(1)   # the batch uses 1/n per skeleton
         for t in range(0, iters, chunk):
             gb.optimize(t, min(chunk, iters - t), adam)
+        self._compose(X, M, V, n)
+
+    def _compose(self, X, M, V, n: int):
+        """Masks of the one-step particles as they stand, then composition."""
+        gb = self.batch
         st = _stream()
         for k, g in enumerate(gb.gps):
             B.ct_cost(g.handle, gb.X[k].data_ptr(), self.n_sub, gb.X[k].shape[1], self.cost.data_ptr(), None,
@@ -78,3 +85,60 @@ class CompositionalInit:
                               self.count[k:k + 1].data_ptr(), X.data_ptr(),
                               None if M is None else M.data_ptr(), None if V is None else V.data_ptr(),
                               X.shape[1], I.STEP_DIM * k, n, st)
+
+    def solve(self, gp: GpuProblem, n: int, seed: int, max_iters: int = 2000, chunk: int = 100,
+              first_check: int = 300, refine_budget: int = 2000, refine_chunk: int = 10) -> SolveResult:
+        """Time to the first satisfying particle of the whole skeleton: the
+        one-step problems run in chunks; after each chunk from `first_check`
+        on, their satisfying particles are composed and the composed batch is
+        tested (one cost launch; the host reads one flag).  When no composed
+        particle satisfies by `max_iters`, the last composition is refined by
+        the plain optimizer with stop at first.  `first_sat_iter` counts
+        one-step iterations plus refinement iterations."""
+        gb = self.batch
+        X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
+        cost = torch.empty(n, dtype=torch.float32, device=gp.device)
+        mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t_wall = time.perf_counter()
+        start = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        gb.seed(seed)
+        adam1 = default_adam(1)
+        done = 0
+        while done < max_iters:
+            c = min(chunk, max_iters - done)
+            gb.optimize(done, c, adam1)
+            done += c
+            if done < first_check and done < max_iters:
+                continue
+            self._compose(X, M, V, n)
+            B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), None, mask.data_ptr(),
+                      stream.cuda_stream)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            if bool(mask[:n].any().item()):
+                return SolveResult(done, done, start.elapsed_time(ev) / 1e3, time.perf_counter() - t_wall,
+                                   int(mask[:n].sum().item()))
+        # refine the last composition
+        adam = default_adam(n)
+        frozen = grasp_frozen(gp.prob, gp.device)
+        flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=gp.device)
+        events = []
+        t = 0
+        while t < refine_budget:
+            c = min(refine_chunk, refine_budget - t)
+            gp.optimize(X, M, V, n, t, c, adam, frozen=frozen, cost=cost, mask=mask, first_sat=flag,
+                        stop_at_first=True)
+            t += c
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            events.append(e)
+        torch.cuda.synchronize()
+        f = int(flag.item())
+        wall = time.perf_counter() - t_wall
+        if f == INT32_MAX:
+            return SolveResult(max_iters + refine_budget, None, None, wall, int(mask.sum().item()))
+        ttf = start.elapsed_time(events[min(f // refine_chunk, len(events) - 1)]) / 1e3
+        return SolveResult(max_iters + refine_budget, max_iters + f, ttf, wall, int(mask.sum().item()))

@@ -20,6 +20,7 @@ namespace mlp {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));   // 16 bytes moved as one value
 
 // float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -80,6 +81,47 @@ constexpr int GT = 64;    // workgroup tile (M and N)
 constexpr int GK = 32;    // K per stage (one MFMA deep)
 constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 
+// Epilogue of one 16 x 16 accumulator tile: lane values are rows mb .. mb+3
+// of column n.
+template <int EPI>
+__device__ __forceinline__ void store_tile(const GemmArgs& g, int mb, int n, const f32x4_t& a, int split) {
+    if (n >= g.N) return;
+    uint16_t hv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = mb + r;
+        const float v = a[r];
+        hv[r] = 0;
+        if (m >= g.M) continue;
+        if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
+            const float z = v + g.bias[n];
+            if constexpr (EPI == EPI_HID_TRAIN) g.F[(int64_t)m * g.ldf + n] = z;
+            hv[r] = to_bf16(gelu(z));
+            g.Hb[(int64_t)m * g.ldh + n] = hv[r];
+        } else if constexpr (EPI == EPI_OUT) {
+            g.F[(int64_t)m * g.ldf + n] = v + g.bias[n];
+        } else if constexpr (EPI == EPI_BWD) {
+            hv[r] = to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n]));
+            g.Hb[(int64_t)m * g.ldh + n] = hv[r];
+        } else {
+            g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
+        }
+    }
+    if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_BWD) {
+        // four consecutive rows of one column: one 8-byte store of the transpose
+        uint16_t* dst = g.Ht + (int64_t)n * g.ldht + mb;
+        if (mb + 3 < g.M) {
+            uint2 p;
+            p.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+            p.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
+            *(uint2*)dst = p;
+        } else {
+            for (int r = 0; r < 4; ++r)
+                if (mb + r < g.M) dst[r] = hv[r];
+        }
+    }
+}
+
 // 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a 32 x 32
 // block = 2 x 2 MFMA 16x16x32 tiles.  Operand fragments: lane l holds row
 // (l % 16) and K elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and
@@ -107,20 +149,20 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
     for (int k0 = kb; k0 < ke; k0 += GK) {
-        const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-        const uint4 a = a_ok ? *(const uint4*)(pa + k0) : z4;
-        const uint4 b = b_ok ? *(const uint4*)(pb + k0) : z4;
+        const u32x4_t z4 = {0u, 0u, 0u, 0u};
+        const u32x4_t a = a_ok ? *(const u32x4_t*)(pa + k0) : z4;
+        const u32x4_t b = b_ok ? *(const u32x4_t*)(pb + k0) : z4;
         __syncthreads();   // the previous stage's fragments are read
-        *(uint4*)&As[lr][lk] = a;
-        *(uint4*)&Bs[lr][lk] = b;
+        *(u32x4_t*)&As[lr][lk] = a;
+        *(u32x4_t*)&Bs[lr][lk] = b;
         __syncthreads();
         bf16x8_t af[2], bf[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-            af[i] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+            af[i] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            bf[j] = __builtin_bit_cast(bf16x8_t, *(const uint4*)&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+            bf[j] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -129,48 +171,101 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     }
 
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int mb = m0 + wm * 32 + i * 16 + (lane >> 4) * 4;
-            const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-            if (n >= g.N) continue;
-            uint16_t hv[4];
+        for (int j = 0; j < 2; ++j)
+            store_tile<EPI>(g, m0 + wm * 32 + i * 16 + (lane >> 4) * 4, n0 + wn * 32 + j * 16 + (lane & 15),
+                            acc[i][j], split);
+}
+
+// Large row counts (the selection passes over rows x draws): 128 x 128
+// workgroup tiles, each wave a 64 x 64 block = 4 x 4 MFMA tiles (8 fragment
+// reads per 16 MFMAs), K staged through two LDS buffers so that the global
+// loads of the next 32-deep slice overlap the products of this one.  Same
+// operand layout, epilogues and bounds as gemm_nt_kernel (ksplit = 1).
+constexpr int GB = 128;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_big_kernel(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][GB][GK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GB][GK + GPAD];
+    const int tiles_n = (g.N + GB - 1) / GB;
+    const int m0 = (int)(blockIdx.x / tiles_n) * GB, n0 = (int)(blockIdx.x % tiles_n) * GB;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int lr = tid >> 2, lk = (tid & 3) * 8;   // rows lr and lr + 64
+    bool aok[2], bok[2];
+    const uint16_t* pa[2];
+    const uint16_t* pb[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = mb + r;
-                const float v = acc[i][j][r];
-                hv[r] = 0;
-                if (m >= g.M) continue;
-                if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
-                    const float z = v + g.bias[n];
-                    if constexpr (EPI == EPI_HID_TRAIN) g.F[(int64_t)m * g.ldf + n] = z;
-                    hv[r] = to_bf16(gelu(z));
-                    g.Hb[(int64_t)m * g.ldh + n] = hv[r];
-                } else if constexpr (EPI == EPI_OUT) {
-                    g.F[(int64_t)m * g.ldf + n] = v + g.bias[n];
-                } else if constexpr (EPI == EPI_BWD) {
-                    hv[r] = to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n]));
-                    g.Hb[(int64_t)m * g.ldh + n] = hv[r];
-                } else {
-                    g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
-                }
-            }
-            if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_BWD) {
-                // four consecutive rows of one column: one 8-byte store of the transpose
-                uint16_t* dst = g.Ht + (int64_t)n * g.ldht + mb;
-                if (mb + 3 < g.M) {
-                    uint2 p;
-                    p.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
-                    p.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
-                    *(uint2*)dst = p;
-                } else {
-                    for (int r = 0; r < 4; ++r)
-                        if (mb + r < g.M) dst[r] = hv[r];
-                }
+    for (int h = 0; h < 2; ++h) {
+        const int ra = m0 + lr + 64 * h, rb = n0 + lr + 64 * h;
+        aok[h] = ra < g.M;
+        bok[h] = rb < g.N;
+        pa[h] = g.A + (int64_t)(aok[h] ? ra : 0) * g.lda + lk;
+        pb[h] = g.B + (int64_t)(bok[h] ? rb : 0) * g.ldb + lk;
+    }
+    f32x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const u32x4_t z4 = {0u, 0u, 0u, 0u};
+    u32x4_t ra[2], rb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        ra[h] = aok[h] ? *(const u32x4_t*)(pa[h]) : z4;
+        rb[h] = bok[h] ? *(const u32x4_t*)(pb[h]) : z4;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        *(u32x4_t*)&As[0][lr + 64 * h][lk] = ra[h];
+        *(u32x4_t*)&Bs[0][lr + 64 * h][lk] = rb[h];
+    }
+    __syncthreads();
+    const int steps = g.K / GK;
+    for (int st = 0; st < steps; ++st) {
+        const int cur = st & 1;
+        const bool more = st + 1 < steps;
+        if (more) {
+            const int k1 = (st + 1) * GK;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                ra[h] = aok[h] ? *(const u32x4_t*)(pa[h] + k1) : z4;
+                rb[h] = bok[h] ? *(const u32x4_t*)(pb[h] + k1) : z4;
             }
         }
+        bf16x8_t af[4], bf[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            af[i] = __builtin_bit_cast(bf16x8_t,
+                                       *(const u32x4_t*)&As[cur][wm * 64 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            bf[j] = __builtin_bit_cast(bf16x8_t,
+                                       *(const u32x4_t*)&Bs[cur][wn * 64 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        if (more) {
+            // the other buffer was last read in step st - 1, which every wave
+            // finished before the barrier at the end of that step
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                *(u32x4_t*)&As[cur ^ 1][lr + 64 * h][lk] = ra[h];
+                *(u32x4_t*)&Bs[cur ^ 1][lr + 64 * h][lk] = rb[h];
+            }
+        }
+        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            store_tile<EPI>(g, m0 + wm * 64 + i * 16 + (lane >> 4) * 4, n0 + wn * 64 + j * 16 + (lane & 15),
+                            acc[i][j], 0);
 }
 
 // ---------------------------------------------------------------------------

@@ -68,7 +68,9 @@ def test_noise_matches_oracle():
     m.close()
 
 
-@pytest.mark.parametrize("name,rows", [("small", 100), ("small", 64), ("proposer", 4096), ("proposer", 200)])
+# 4096 and more rows take the 128 x 128 double-buffered kernel; 4100 leaves a ragged last tile
+@pytest.mark.parametrize("name,rows", [("small", 100), ("small", 64), ("proposer", 4096), ("proposer", 200),
+                                       ("proposer", 4100), ("small", 5000)])
 def test_forward_matches_oracle(name, rows):
     m, dims, p, feats, fr, draw = _setup(name, rows)
     Y = m.forward(_dev(feats), rows, 77, _dev(fr, torch.int32), _dev(draw, torch.int32)).cpu().numpy()
@@ -83,7 +85,7 @@ def test_forward_matches_oracle(name, rows):
     m.close()
 
 
-@pytest.mark.parametrize("name,rows", [("small", 128), ("proposer", 4096)])
+@pytest.mark.parametrize("name,rows", [("small", 128), ("proposer", 4096), ("proposer", 4160)])
 def test_backward_matches_oracle(name, rows):
     m, dims, p, feats, fr, draw = _setup(name, rows, seed=1)
     rng = np.random.default_rng(11)

@@ -137,7 +137,7 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
     held-out scenes."""
     batch, draws = 1024, 32
     t0 = time.perf_counter()
-    data = collect(None)
+    data = collect(None, 0)
     lg(f"learned/{name}: round 0: {len(data.targets)} targets ({data.weights.sum() / 21:.0f} converged steps) "
        f"in {time.perf_counter() - t0:.1f} s")
     mlp = SD.GpuMlp(d_out=d_out, max_rows=batch * draws, device=dev)
@@ -146,7 +146,7 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
     logs = [SD.train(mlp, data, stats, steps=steps, batch=batch, n_draws=draws, lr=1e-3, seed=0)]
     prop = SD.Proposer(mlp, stats)
     for r in range(1, rounds + 1):
-        data = SD.merge(data, collect(prop))
+        data = SD.merge(data, collect(prop, r))
         stats = SD.Stats.of(data)
         prop = SD.Proposer(mlp, stats)
         logs.append(SD.train(mlp, data, stats, steps=steps // 2, batch=batch, n_draws=draws, lr=1e-3, seed=r))
@@ -260,22 +260,23 @@ def learned_seeds(args, dev, n, q):
                 "first, from uniform seeds vs from the learned proposer's seeds (a learned run that finds "
                 "nothing in its budget falls back to uniform seeds); GPU time incl. initialization and seed "
                 "inference. Proposer: 152-512-512-512-out BF16 MLP trained on the GPU by IMLE (batch 1024, 32 "
-                "draws) on converged pick-place steps the method produced on training scenes 10000+; "
-                "held-out scenes 20000+.",
+                "draws) on converged pick-place steps the method produced on training scenes 10000+ (packing: "
+                "one-step skeletons first, then two rounds of runs seeded by the proposer itself); held-out scenes "
+                "20000+.",
     }
     sc1 = range(10000, 10000 + 2 * args.learned_scenes)
     out["single_pick_place"] = _learned_family(
         SD, I, torch, dev, lg, "single", SD.single_problem, 21,
-        lambda prop: SD.collect(sc1, robot_seed=rs, n=1024, iters=3000, keep=64, proposer=prop,
-                                make=SD.single_problem),
+        lambda prop, r: SD.collect(sc1, robot_seed=rs, n=1024, iters=3000, keep=64, proposer=prop,
+                                   make=SD.single_problem),
         0, args.learned_steps, 256, list(range(20000, 20000 + 2 * args.eval_scenes)), 3000, rs)
     sc2 = range(10000, 10000 + args.learned_scenes)
     out["packing"] = _learned_family(
         SD, I, torch, dev, lg, "packing", SD.packing_problem, 84,
-        lambda prop: (SD.collect_steps(sc2, robot_seed=rs, n=1024, iters=3000, keep=64) if prop is None else
-                      SD.collect(sc2, robot_seed=rs, n=1024, iters=1000, keep=64, proposer=prop,
-                                 init_seed=5000)),
-        1, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs)
+        lambda prop, r: (SD.collect_steps(sc2, robot_seed=rs, n=1024, iters=3000, keep=64) if prop is None else
+                         SD.collect(sc2, robot_seed=rs, n=1024, iters=1000, keep=64, proposer=prop,
+                                    init_seed=5000 * r)),
+        2, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs)
     return out
 
 

@@ -131,7 +131,7 @@ def cpu_baseline(prob, budget_s: float):
 
 
 def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, steps, n_eval, eval_scenes,
-                    budget, robot_seed):
+                    budget, robot_seed, extra_eval=None):
     """Train one seed proposer on the method's converged particles, then time
     to the first satisfying particle from uniform vs learned seeds on
     held-out scenes."""
@@ -202,6 +202,8 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
         "mean_converged_step_fraction_uniform": float(np.mean(cmpr.uniform_steps)),
         "mean_converged_step_fraction_learned": float(np.mean(cmpr.learned_steps)),
     }
+    if extra_eval is not None:
+        res.update(extra_eval(prop))
     lg(f"learned/{name}: coverage uniform {cov_u:.2f} vs learned {res['coverage_learned_alone']:.2f} "
        f"(with fallback {cov_l:.2f}); at rate {rate:.2f}: uniform {at_u} s vs learned {at_l} s; converged steps "
        f"{res['mean_converged_step_fraction_uniform']:.4f} vs {res['mean_converged_step_fraction_learned']:.4f}")
@@ -222,8 +224,8 @@ def compositional(args, dev, n, q):
         gp = GpuProblem(prob, dev)
         ci = CompositionalInit(prob, n_sub, dev)
         seed = 4242 + s
-        ci.solve(gp, n, seed, max_iters=200, first_check=100, refine_budget=20)   # captures the loops' graphs
-        r = ci.solve(gp, n, seed, max_iters=args.sampling_iters, first_check=200, chunk=100, refine_budget=budget)
+        ci.solve(gp, n, seed, max_iters=100, first_check=50, chunk=50, refine_budget=20)   # captures the graphs
+        r = ci.solve(gp, n, seed, max_iters=args.sampling_iters, first_check=50, chunk=50, refine_budget=budget)
         first.append(r.first_sat_iter)
         times.append(r.time_to_first_s)
         counts.append([int(c) for c in ci.count.cpu().numpy()])
@@ -235,8 +237,8 @@ def compositional(args, dev, n, q):
     return {
         "kind": "time to the first satisfying particle (Eq. 3) from compositional initialization: each pick-place "
                 "step solved alone by the plain optimizer (one-step skeletons, all steps in one persistent launch "
-                f"per iteration, {n_sub} particles each); from 200 iterations on, every 100 iterations the "
-                "satisfying one-step particles are composed into packing particles and tested; after "
+                f"per iteration, {n_sub} particles each, uniform seeds); every 50 iterations the satisfying "
+                "one-step particles are composed into packing particles and tested; after "
                 f"{args.sampling_iters} one-step iterations the composition is refined by the plain optimizer "
                 "with stop at first; GPU time from the start of initialization",
         "scenes": scenes, "particles": n, "one_step_particles": n_sub, "one_step_iters_max": args.sampling_iters,
@@ -276,8 +278,46 @@ def learned_seeds(args, dev, n, q):
         lambda prop, r: (SD.collect_steps(sc2, robot_seed=rs, n=1024, iters=3000, keep=64) if prop is None else
                          SD.collect(sc2, robot_seed=rs, n=1024, iters=1000, keep=64, proposer=prop,
                                     init_seed=5000 * r)),
-        2, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs)
+        2, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs,
+        extra_eval=lambda prop: learned_compositional(args, dev, prop, n, lg))
     return out
+
+
+def learned_compositional(args, dev, prop, n, lg):
+    """The proposer's seeds as the starting points of compositional
+    initialization's one-step problems (step k of each seed seeds one-step
+    problem k), same schedule as the uniform-seeded compositional run."""
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd.planner import GpuProblem
+    from paper_2411_11833_amd.sampling import CompositionalInit
+
+    scenes = list(range(20000, 20000 + args.eval_scenes))
+    n_sub = 8192
+    first, times = [], []
+    for s in scenes:
+        prob = I.packing(args.robot_seed, s)
+        gp = GpuProblem(prob, dev)
+        pre = prop.prepare(prob)
+        ci = CompositionalInit(prob, n_sub, dev)
+        seed = 4242 + s
+        sd = lambda X, M, V: prop.seed(pre, seed, X, M, V, n_sub)  # noqa: E731
+        ci.solve(gp, n, seed, max_iters=100, first_check=50, chunk=50, refine_budget=20, seeder=sd)
+        r = ci.solve(gp, n, seed, max_iters=args.sampling_iters, first_check=50, chunk=50,
+                     refine_budget=args.eval_budget, seeder=sd)
+        first.append(r.first_sat_iter)
+        times.append(r.time_to_first_s)
+        lg(f"learned seeds + compositional init, scene {s}: first satisfying particle after {r.first_sat_iter} "
+           f"iterations, {r.time_to_first_s} s")
+        ci.close()
+        gp.close()
+    solved = [t for t in times if t is not None]
+    return {"learned_compositional": {
+        "kind": "compositional initialization whose one-step problems start from the proposer's seeds instead of "
+                "uniform draws (seed inference timed), same schedule as compositional_init",
+        "scenes": scenes, "first_iter": first, "time_to_first_s": times,
+        "coverage": len(solved) / len(scenes),
+        "median_time_to_first_s": float(np.median(solved)) if solved else None,
+        "max_time_to_first_s": max(solved) if solved else None}}
 
 
 def main():
@@ -485,6 +525,17 @@ def main():
     learned = None
     if not args.no_learned:
         learned = learned_seeds(args, dev, n, q)
+
+    if sampling is not None and learned is not None and "learned_compositional" in learned["packing"]:
+        from paper_2411_11833_amd import seeds as SD
+        lc = learned["packing"]["learned_compositional"]
+        cu, cl, rate, tu, tl = SD.equal_rate_times(sampling["time_to_first_s"], lc["time_to_first_s"])
+        learned["packing_equal_rate_vs_uniform_seeded_compositional"] = {
+            "coverage_uniform_seeds": cu, "coverage_learned_seeds": cl, "equal_satisfaction_rate": rate,
+            "time_uniform_seeds_s": tu, "time_learned_seeds_s": tl,
+            "speedup": (tu / tl) if (tu and tl) else None}
+        log(f"[bench] packing, compositional init from uniform vs learned seeds: at satisfaction rate {rate:.2f} "
+            f"{tu} s vs {tl} s", q)
 
     out = {
         "metric": METRIC,

@@ -86,25 +86,47 @@ class CompositionalInit:
                               None if M is None else M.data_ptr(), None if V is None else V.data_ptr(),
                               X.shape[1], I.STEP_DIM * k, n, st)
 
+    def seed_from(self, Xfull):
+        """Seed the one-step problems from a whole-skeleton particle batch
+        (e.g. a learned proposer's seeds): one-step problem k takes the rows
+        of step k; moments zeroed."""
+        gb = self.batch
+        st = _stream()
+        ld = Xfull.shape[1]
+        for k in range(len(gb.gps)):
+            B.ct_gather_block(Xfull.data_ptr() + 4 * I.STEP_DIM * k * ld, ld, I.STEP_DIM, ld, None, None,
+                              gb.X[k].data_ptr(), gb.M[k].data_ptr(), gb.V[k].data_ptr(), gb.X[k].shape[1], 0,
+                              self.n_sub, st)
+        gb.first_sat.fill_(INT32_MAX)
+
     def solve(self, gp: GpuProblem, n: int, seed: int, max_iters: int = 2000, chunk: int = 100,
-              first_check: int = 300, refine_budget: int = 2000, refine_chunk: int = 10) -> SolveResult:
+              first_check: int = 300, refine_budget: int = 2000, refine_chunk: int = 10,
+              seeder=None) -> SolveResult:
         """Time to the first satisfying particle of the whole skeleton: the
         one-step problems run in chunks; after each chunk from `first_check`
         on, their satisfying particles are composed and the composed batch is
         tested (one cost launch; the host reads one flag).  When no composed
         particle satisfies by `max_iters`, the last composition is refined by
         the plain optimizer with stop at first.  `first_sat_iter` counts
-        one-step iterations plus refinement iterations."""
+        one-step iterations plus refinement iterations.  With `seeder(X, M,
+        V)`, which fills a whole-skeleton batch of n_sub particles (timed),
+        the one-step problems start from its step blocks instead of uniform
+        draws."""
         gb = self.batch
         X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
         cost = torch.empty(n, dtype=torch.float32, device=gp.device)
         mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
+        Xs = gp.empty(self.n_sub) if seeder is not None else None
         stream = torch.cuda.current_stream()
         torch.cuda.synchronize()
         t_wall = time.perf_counter()
         start = torch.cuda.Event(enable_timing=True)
         start.record(stream)
-        gb.seed(seed)
+        if seeder is None:
+            gb.seed(seed)
+        else:
+            seeder(Xs, None, None)
+            self.seed_from(Xs)
         adam1 = default_adam(1)
         done = 0
         while done < max_iters:

@@ -591,3 +591,21 @@ def test_compositional_init_solves_packing_where_uniform_does_not():
     assert ru.first_sat_iter is None
     assert rc.first_sat_iter is not None
     ci.close()
+
+
+def test_seed_from_hands_each_step_block_to_its_one_step_problem():
+    from paper_2411_11833_amd.sampling import CompositionalInit
+    prob = I.packing(0, 1)
+    ci = CompositionalInit(prob, 300)
+    gp = _gp(prob)
+    Xf = gp.from_rows(I.uniform_particles(prob, 300, seed=9))
+    for k in range(4):
+        ci.batch.M[k].fill_(5.0)
+    ci.seed_from(Xf)
+    torch.cuda.synchronize()
+    full = gp.to_rows(Xf, 300).cpu().numpy()
+    for k, g in enumerate(ci.batch.gps):
+        got = g.to_rows(ci.batch.X[k], 300).cpu().numpy()
+        np.testing.assert_array_equal(got, full[:, I.STEP_DIM * k:I.STEP_DIM * (k + 1)])
+        assert np.all(ci.batch.M[k][:, :300].cpu().numpy() == 0)
+    ci.close()

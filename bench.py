@@ -15,9 +15,13 @@ Also reported on the same JSON line:
     launch / its average launch time (HIP events on its stream);
   * the waypoint motion cost (16384 particles) and 64 skeletons of uneven
     length in one persistent launch per iteration vs one launch each;
+  * the plan-skeleton feasibility heuristic H of Eq. (5);
+  * compositional initialization (one-step problems composed, then refined)
+    on held-out packing scenes;
   * learned vs uniform seeds: a BF16 MLP proposer trained on the GPU on the
     method's converged particles, then time to the first satisfying particle
-    on held-out single pick-place and packing scenes;
+    on held-out single pick-place and packing scenes, for packing also as
+    the starting points of compositional initialization;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]

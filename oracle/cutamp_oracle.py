@@ -19,6 +19,8 @@ the oracle's own cost.  References are to the paper (Shen et al.,
 * distance from bounds, pairwise object distance ............. App. listing of example cost functions
 * weights (1, kin-rot 5, stable place 2), tolerances ........ App. "Cost Weights", "Constraint Tolerances"
 * spheres vs oriented boxes .................................. App. "Collision Representation"
+* robot self-collision (spheres of non-adjacent links) ....... Sec. IV-B "Parallelizing on GPUs",
+                                                                App. "Constraint Tolerances"
 
 Readings where the paper is silent are listed in the design notes (robot
 DH form, pose-error form, grasp box, containment, collision hinge, box sets).
@@ -44,7 +46,7 @@ __all__ = [
     "rz", "rx", "trans", "fk_frames", "box_sdf", "sphere_box_penalty", "pose_error",
     "dist_from_bounds", "pairwise_dist_sum", "grasp_tf", "place_tf", "evaluate",
     "Evaluation", "terms", "cost", "mask", "cost_and_grad", "adam_step", "margins",
-    "weights_vector", "tolerance_vector", "place_z", "feasibility",
+    "weights_vector", "tolerance_vector", "place_z", "feasibility", "self_pairs", "self_collision",
 ]
 
 
@@ -194,7 +196,7 @@ def weights_vector(prob: Problem) -> np.ndarray:
     w, K = prob.weights, prob.skeleton.n_steps
     per = [w.kin_pos, w.kin_rot, w.kin_pos, w.kin_rot, w.grasp, w.place, w.jlim, w.jlim,
            w.coll, w.coll, w.coll]
-    out = per * K + [w.motion_coll] * prob.n_motion_terms
+    out = per * K + [w.motion_coll] * prob.n_motion_terms + [w.self_coll] * prob.n_self_terms
     if prob.skeleton.goal_cost:
         out.append(w.goal)
     if prob.skeleton.waypoints > 0:
@@ -207,7 +209,8 @@ def tolerance_vector(prob: Problem) -> np.ndarray:
     e, K = prob.tolerances, prob.skeleton.n_steps
     per = [e.kin_pos, e.kin_rot, e.kin_pos, e.kin_rot, e.grasp, e.place, e.jlim, e.jlim,
            e.coll, e.coll, e.coll]
-    return np.array(per * K + [e.motion_coll] * prob.n_motion_terms, dtype=np.float64)
+    return np.array(per * K + [e.motion_coll] * prob.n_motion_terms + [e.self_coll] * prob.n_self_terms,
+                    dtype=np.float64)
 
 
 def _robot_spheres(prob: Problem, frames):
@@ -247,6 +250,33 @@ def _collision(c, rad, boxes, kinks, want_kinks):
     return total
 
 
+def self_pairs(sphere_link) -> tuple[np.ndarray, np.ndarray]:
+    """Index pairs (a, b), a < b, of robot spheres whose rigid segments are
+    neither the same nor neighbours in the chain (|link_a - link_b| >= 2;
+    segments 1..7 are the links, 8 the tool).  Neighbouring segments meet at
+    a joint, where their spheres overlap by construction."""
+    L = np.asarray(sphere_link, dtype=np.int64)
+    a, b = np.triu_indices(L.size, k=1)
+    keep = np.abs(L[a] - L[b]) >= 2
+    return a[keep], b[keep]
+
+
+def self_collision(c, rad, sphere_link, kinks=None, want_kinks=False):
+    """Self-penetration of one configuration: sum over the pairs of
+    ``self_pairs`` of max(0, r_a + r_b - |c_a - c_b|), for world centres c
+    [B, S, 3] and radii rad [S].  Returns (penalty [B], the largest hinge
+    argument [B]; minus it is how far the closest pair is from touching)."""
+    ia, ib = self_pairs(sphere_link)
+    ia, ib = torch.as_tensor(ia), torch.as_tensor(ib)
+    d = torch.linalg.vector_norm(c[:, ia] - c[:, ib], dim=-1)
+    arg = rad[ia] + rad[ib] - d
+    if want_kinks:
+        with torch.no_grad():
+            kinks.append(arg.abs().min(-1).values)
+            kinks.append(d.min(-1).values)
+    return torch.clamp(arg, min=0.0).sum(-1), arg.detach().max(-1).values
+
+
 def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evaluation:
     """All terms of Eq. (2) for particles X [B, dim] (float64).
 
@@ -262,9 +292,10 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
       8 CFreeHold at q_g: robot + held-object spheres vs the step's boxes   (lambda 1, eps 1 mm)
       9 the same at q_p                                                     (lambda 1, eps 1 mm)
       10 CFreePlace: object spheres at P(rho) vs the step's boxes          (lambda 1, eps 1 mm)
-    then, with motion, one collision term per transition, then the soft
-    costs: the goal's pairwise placed-object distance and the trajectory
-    length.
+    then, with motion, one collision term per transition, then, with
+    self-collision, one self-penetration term per key configuration (q_g of
+    step k at 2k, q_p at 2k + 1; lambda 1, eps 0), then the soft costs: the
+    goal's pairwise placed-object distance and the trajectory length.
 
     The boxes of step k are the table, the obstacles, objects the skeleton
     never moves, and every other moved object: at its placement if placed
@@ -378,6 +409,14 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
                 if want_kinks:
                     kinks.append(seg_len[-1].detach().clone())
             prev = qp
+    if sk.self_collision:
+        for k in range(K):
+            blk = X[:, STEP_DIM * k:STEP_DIM * (k + 1)]
+            for q in (blk[:, 0:7], blk[:, 7:14]):
+                c, rad = _robot_spheres(prob, fk_frames(r, q))
+                pen, top = self_collision(c, rad, r.sphere_link, kinks, want_kinks)
+                cols.append(pen)
+                flip_lo.append(-top)
     if sk.goal_cost:
         pos = torch.stack([P[k][:, :3, 3] for k in range(K)], 1)
         cols.append(pairwise_dist_sum(pos))

@@ -67,6 +67,7 @@ class Skeleton:
     goal_cost: int = 0              # 1: add the pairwise placed-object distance cost
     waypoints: int = 0              # interior waypoints per transition (0 = no motion cost)
     q0: np.ndarray = field(default_factory=lambda: np.zeros(N_JOINTS))
+    self_collision: int = 0         # 1: add the robot self-collision constraint at every key configuration
 
     @property
     def n_steps(self) -> int:
@@ -84,6 +85,7 @@ class Weights:
     goal: float = 0.25
     traj_len: float = 0.1
     motion_coll: float = 1.0
+    self_coll: float = 1.0
 
 
 @dataclass
@@ -95,6 +97,7 @@ class Tolerances:
     jlim: float = 0.0
     coll: float = 0.001
     motion_coll: float = 0.001
+    self_coll: float = 0.0          # App. "Constraint Tolerances": zero self-penetration
 
 
 @dataclass
@@ -114,8 +117,12 @@ class Problem:
         return 2 * self.skeleton.n_steps if self.skeleton.waypoints > 0 else 0
 
     @property
+    def n_self_terms(self) -> int:
+        return 2 * self.skeleton.n_steps if self.skeleton.self_collision else 0
+
+    @property
     def n_constraint_terms(self) -> int:
-        return TERMS_PER_STEP * self.skeleton.n_steps + self.n_motion_terms
+        return TERMS_PER_STEP * self.skeleton.n_steps + self.n_motion_terms + self.n_self_terms
 
     @property
     def n_terms(self) -> int:
@@ -125,6 +132,7 @@ class Problem:
     def term_names(self) -> list[str]:
         names = [f"s{k}.{n}" for k in range(self.skeleton.n_steps) for n in TERM_NAMES]
         names += [f"motion{m}.coll" for m in range(self.n_motion_terms)]
+        names += [f"self{m}" for m in range(self.n_self_terms)]
         if self.skeleton.goal_cost:
             names.append("goal")
         if self.skeleton.waypoints > 0:

@@ -288,7 +288,8 @@ def collect_steps(scene_seeds, robot_seed: int = 0, n: int = 1024, iters: int = 
 def _tolerances(prob: I.Problem) -> list[float]:
     t = prob.tolerances
     per = [t.kin_pos, t.kin_rot, t.kin_pos, t.kin_rot, t.grasp, t.place, t.jlim, t.jlim, t.coll, t.coll, t.coll]
-    return per * prob.skeleton.n_steps + [t.motion_coll] * prob.n_motion_terms
+    return (per * prob.skeleton.n_steps + [t.motion_coll] * prob.n_motion_terms +
+            [t.self_coll] * prob.n_self_terms)
 
 
 def merge(a: Dataset, b: Dataset) -> Dataset:

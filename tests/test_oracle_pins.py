@@ -325,17 +325,27 @@ def test_cost_is_weighted_sum_and_particle_permutation():
     np.testing.assert_array_equal(O.terms(prob, X[perm]), T[perm])
 
 
-@pytest.mark.parametrize("which", ["single", "packing", "motion"])
+@pytest.mark.parametrize("which", ["single", "packing", "motion", "self"])
 def test_gradient_matches_central_differences(which):
     if which == "single":
         prob = I.single_pick_place(0, 1)
     elif which == "packing":
         prob = _small_packing()
+    elif which == "self":
+        prob = _small_packing()
+        prob.skeleton.self_collision = 1
     else:
         prob = I.packing(robot_seed=1, scene_seed=2, n_objects=2, n_obstacles=2, waypoints=4)
-    X = I.uniform_particles(prob, 24, seed=5).astype(np.float64)
+    X = I.uniform_particles(prob, 48 if which == "self" else 24, seed=5).astype(np.float64)
     _, kink = O.margins(prob, X)
-    X = X[kink >= 1e-4][:8]
+    X = X[kink >= 1e-4]
+    if which == "self":
+        # particles with some self-penetration first
+        ns = prob.n_self_terms
+        pen = O.terms(prob, X)[:, prob.n_constraint_terms - ns:prob.n_constraint_terms].sum(1)
+        X = X[np.argsort(-pen, kind="stable")]
+        assert np.sum(pen > 0) >= 3
+    X = X[:8]
     assert len(X) >= 4
     J, G = O.cost_and_grad(prob, X)
     h = 1e-6
@@ -397,3 +407,98 @@ def test_feasibility_heuristic_brute_force_and_special_cases():
     Z[:, 7] = 1.0          # joint-limit term of step 0 (tolerance 0) never satisfied
     c1, h1 = O.feasibility(prob, Z, -1000.0)
     assert c1[7] == 0 and h1 == pytest.approx(((nc - 1) * N - 1000.0) / nc)
+
+
+# ----------------------------------------------------------------------------- self-collision
+
+
+def test_self_pairs_count_and_rule():
+    """The pair set is every pair of spheres whose segments differ by two or
+    more: C(S, 2) minus the pairs inside one segment and between neighbouring
+    segments; checked by brute-force enumeration."""
+    import itertools
+    r = I.make_robot(0, n_spheres=60)
+    L = r.sphere_link
+    n = np.bincount(L, minlength=10)
+    want = math.comb(L.size, 2) - sum(math.comb(int(c), 2) for c in n) - sum(int(n[i] * n[i + 1]) for i in range(9))
+    a, b = O.self_pairs(L)
+    assert a.size == want
+    brute = {(i, j) for i, j in itertools.combinations(range(L.size), 2) if abs(int(L[i]) - int(L[j])) >= 2}
+    assert set(zip(a.tolist(), b.tolist())) == brute
+
+
+def _planar_robot(a, spheres, links):
+    """Seven revolute joints about parallel z-axes (alpha = 0, d = 0): frame i
+    sits at the end of a chain of segments of lengths a_1..a_i in the plane,
+    heading q_1 + ... + q_i."""
+    dh = np.zeros((7, 4))
+    dh[:, 0] = a
+    return I.Robot(dh=dh, q_lo=np.full(7, -4.0), q_hi=np.full(7, 4.0), tool_d=0.05,
+                   spheres=np.asarray(spheres, dtype=np.float64), sphere_link=np.asarray(links, dtype=np.int32))
+
+
+def _self_term(robot, q):
+    q = torch.as_tensor(np.atleast_2d(q), dtype=DT)
+    fr = O.fk_frames(robot, q)
+    S = robot.spheres
+    c = torch.stack([fr[int(L)][:, :3, :3] @ torch.as_tensor(S[s, :3]) + fr[int(L)][:, :3, 3]
+                     for s, L in enumerate(robot.sphere_link)], 1)
+    pen, _ = O.self_collision(c, torch.as_tensor(S[:, 3]), robot.sphere_link)
+    return pen.numpy()
+
+
+def test_self_collision_planar_fold_closed_form():
+    """Planar arm folded back at joint 3 (q_3 = pi): frame 1 is at (a_1, 0) and
+    frame 3 at (a_1 + a_2 - a_3, 0), so spheres at those origins are
+    |a_2 - a_3| apart and penetrate by r_1 + r_3 - |a_2 - a_3|.  The sphere at
+    frame 2's origin touches both but is their neighbour and never counts; a
+    rigid turn of the whole arm (q_1) changes nothing."""
+    a = np.array([0.2, 0.3, 0.25, 0.2, 0.2, 0.2, 0.2])
+    spheres = [[0, 0, 0, 0.04], [0, 0, 0, 0.06], [0, 0, 0, 0.035], [0, 0, 0, 0.03]]
+    links = [1, 2, 3, 7]
+    rob = _planar_robot(a, spheres, links)
+    q = np.array([0.0, 0.0, math.pi, 0.0, 0.0, 0.0, 0.0])
+    want = 0.04 + 0.035 - abs(a[1] - a[2])
+    np.testing.assert_allclose(_self_term(rob, q), [want], rtol=0, atol=1e-14)
+    q2 = q.copy()
+    q2[0] = 0.7
+    np.testing.assert_allclose(_self_term(rob, q2), [want], rtol=0, atol=1e-14)
+    # unfolded: the chain is straight and nothing non-adjacent touches
+    np.testing.assert_allclose(_self_term(rob, np.zeros(7)), [0.0], atol=0)
+    # the far segment folded onto frame 1 as well: link 7's frame at
+    # (a1 + a2 - a3 + a4 - a5 + a6 - a7, 0) = (a1 + a2 - a3, 0) with these lengths
+    q3 = np.array([0.0, 0.0, math.pi, math.pi, math.pi, math.pi, math.pi])
+    x7 = a[0] + a[1] - a[2] + a[3] - a[4] + a[5] - a[6]
+    x3 = a[0] + a[1] - a[2]
+    want3 = want + max(0.0, 0.04 + 0.03 - abs(x7 - a[0])) + max(0.0, 0.035 + 0.03 - abs(x7 - x3)) \
+        + max(0.0, 0.06 + 0.03 - abs(x7 - a[0] - a[1]))
+    np.testing.assert_allclose(_self_term(rob, q3), [want3], rtol=0, atol=1e-13)
+
+
+def test_self_terms_layout_and_mask():
+    """Self terms follow the step (and motion) terms, one per key
+    configuration, enter the mask with tolerance 0 and the cost with their
+    weight; turning the option off removes exactly them."""
+    base = _small_packing()
+    prob = _small_packing()
+    prob.skeleton.self_collision = 1
+    K = prob.skeleton.n_steps
+    assert prob.n_constraint_terms == base.n_constraint_terms + 2 * K
+    assert prob.term_names()[11 * K:11 * K + 2 * K] == [f"self{m}" for m in range(2 * K)]
+    X = I.uniform_particles(prob, 64, seed=8).astype(np.float64)
+    T, Tb = O.terms(prob, X), O.terms(base, X)
+    nc = base.n_constraint_terms
+    np.testing.assert_array_equal(T[:, :nc], Tb[:, :nc])
+    np.testing.assert_array_equal(T[:, nc + 2 * K:], Tb[:, nc:])
+    S = T[:, nc:nc + 2 * K]
+    assert np.all(S >= 0) and np.any(S > 0)
+    # slot m of step k is q_grasp (m even) / q_place (m odd) alone
+    rob = prob.robot
+    for m in range(2 * K):
+        k, off = m // 2, 7 * (m % 2)
+        np.testing.assert_allclose(S[:, m], _self_term(rob, X[:, 21 * k + off:21 * k + off + 7]), rtol=1e-14,
+                                   atol=1e-15)
+    np.testing.assert_allclose(O.cost(prob, X) - O.cost(base, X), S.sum(1) * prob.weights.self_coll, rtol=1e-12,
+                               atol=1e-12)
+    m = O.mask(prob, T)
+    assert np.array_equal(m, O.mask(base, Tb) & np.all(S <= 0.0, axis=1))

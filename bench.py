@@ -16,6 +16,7 @@ Also reported on the same JSON line:
   * the waypoint motion cost (16384 particles) and 64 skeletons of uneven
     length in one persistent launch per iteration vs one launch each;
   * the plan-skeleton feasibility heuristic H of Eq. (5);
+  * the packing step with the robot self-collision constraint switched on;
   * compositional initialization (one-step problems composed, then refined)
     on held-out packing scenes;
   * learned vs uniform seeds: a BF16 MLP proposer trained on the GPU on the
@@ -85,6 +86,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-motion", action="store_true", help="skip the waypoint motion-cost measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
+    ap.add_argument("--no-self", action="store_true", help="skip the self-collision measurement")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
@@ -482,6 +484,53 @@ def main():
         log(f"[bench] motion: fwd+bwd {nm / fb_s:.4g} particle-iters/s, fused step {st_s * 1e3:.2f} ms "
             f"({mwk.flops * nm / st_s / 1e12:.1f} TFLOP/s model)", q)
 
+    # ---- the robot self-collision constraint on: same workload, step kernel
+    # time and what the optimizer does with the constraint
+    self_coll = None
+    if not args.no_self:
+        sprob = I.packing(robot_seed=args.robot_seed, scene_seed=args.scene_seed)
+        sprob.skeleton.self_collision = 1
+        sg = GpuProblem(sprob, dev)
+        Xs, Ms, Vs = sg.empty(n), sg.empty(n), sg.empty(n)
+        sg.seed_uniform(7, Xs, Ms, Vs, n)
+        ssplit = sg.autotune(Xs, n)
+        sfz = grasp_frozen(sprob, dev)
+        for t in range(1, 11):
+            sg.step(Xs, Ms, Vs, n, t, adam, frozen=sfz)
+        e0.record(stream)
+        for t in range(11, 11 + reps):
+            sg.step(Xs, Ms, Vs, n, t, adam, frozen=sfz)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s_kernel = e0.elapsed_time(e1) / 1e3 / reps
+        nc, ns = sg.n_constraint, sprob.n_self_terms
+
+        def penetrating():
+            _, Ts, _ = sg.cost(Xs, n, terms=True)
+            return float((Ts[nc - ns:nc, :n] > 0).any(0).float().mean().item())
+
+        sg.seed_uniform(1234, Xs, Ms, Vs, n)
+        before = penetrating()
+        sg.optimize(Xs, Ms, Vs, n, 0, iters, adam, frozen=sfz)
+        after = penetrating()
+        swk = workmodel.per_particle_iteration(sprob)
+        self_coll = {
+            "workload": f"4-object packing, {n} particles, robot self-collision constraint at the 8 key "
+                        f"configurations ({workmodel.self_pair_count(sprob.robot.sphere_link)} sphere pairs each)",
+            "split": ssplit,
+            "step_kernel_us": s_kernel * 1e6,
+            "step_particle_iters_per_s": n / s_kernel,
+            "overhead_vs_without": s_kernel / kernel_s - 1.0,
+            "flop_per_particle_iter": swk.flops,
+            "step_tflops_model": swk.flops * n / s_kernel / 1e12,
+            "penetrating_fraction_uniform_seeds": before,
+            f"penetrating_fraction_after_{iters}_iters": after,
+        }
+        log(f"[bench] self-collision on: step kernel {s_kernel * 1e6:.1f} us "
+            f"({100 * (s_kernel / kernel_s - 1):+.1f}% vs off); particles with self-penetration "
+            f"{before:.3f} -> {after:.3f} after {iters} iterations", q)
+        sg.close()
+
     # ---- many skeletons: one persistent launch per iteration vs one per skeleton
     batch = None
     if not args.no_batch:
@@ -571,6 +620,7 @@ def main():
         "satisfied_after_full_run": sat_end,
         "feasibility": feas,
         "motion": motion,
+        "self_collision": self_coll,
         "batch": batch,
         "compositional_init": sampling,
         "learned_seeds": learned,

@@ -112,7 +112,12 @@ typedef struct ct_scene {
  * waypoints > 0 adds, for each of the 2K transitions q0 -> q_g^1 -> q_p^1 ->
  * q_g^2 ... , a collision term over `waypoints` interior linearly
  * interpolated configurations and the soft TrajLength cost (MoveFree /
- * MoveHold, Listing 1).
+ * MoveHold, Listing 1).  self_collision = 1 adds the robot self-collision
+ * constraint (Sec. IV-B "Parallelizing on GPUs"; tolerance in App.
+ * "Constraint Tolerances") at each of the 2K key configurations: the sum over
+ * pairs of robot spheres whose links differ by two or more (1..7 = links,
+ * 8 = tool; a link and its neighbours meet at a joint and never count) of
+ * max(0, r_a + r_b - |c_a - c_b|).
  */
 typedef struct ct_skeleton {
     int32_t n_steps;               /* K, 1 .. CT_MAX_STEPS                          */
@@ -122,16 +127,17 @@ typedef struct ct_skeleton {
     int32_t goal_cost;             /* 0 or 1                                         */
     int32_t waypoints;             /* 0 .. CT_MAX_WAYPOINTS                          */
     const double *q0;              /* [7] start configuration; used if waypoints > 0 */
+    int32_t self_collision;        /* 0 or 1                                         */
 } ct_skeleton;
 
 /* Weights lambda of Eq. (2) (App. "Cost Weights"). */
 typedef struct ct_weights {
-    double kin_pos, kin_rot, grasp, place, jlim, coll, goal, traj_len, motion_coll;
+    double kin_pos, kin_rot, grasp, place, jlim, coll, goal, traj_len, motion_coll, self_coll;
 } ct_weights;
 
 /* Tolerances eps of Eq. (3) (App. "Constraint Tolerances"); all >= 0. */
 typedef struct ct_tolerances {
-    double kin_pos, kin_rot, grasp, place, jlim, coll, motion_coll;
+    double kin_pos, kin_rot, grasp, place, jlim, coll, motion_coll, self_coll;
 } ct_tolerances;
 
 /* Adam hyper-parameters (Sec. IV-B).  grad_scale multiplies dJ/dx before the
@@ -165,8 +171,10 @@ int ct_problem_destroy(ct_problem *problem);
  * the mask).  Term order: per step k the 11 terms
  *   kin_pick_pos, kin_pick_rot, kin_place_pos, kin_place_rot, grasp, place,
  *   jlim_grasp, jlim_place, coll_grasp, coll_place_conf, coll_placed_obj,
- * then (with waypoints) one collision term per transition, then the goal
- * cost (if enabled), then TrajLength (if waypoints > 0).
+ * then (with waypoints) one collision term per transition, then (with
+ * self_collision) one self-collision term per key configuration (q_grasp of
+ * step k at 2k, q_place at 2k + 1), then the goal cost (if enabled), then
+ * TrajLength (if waypoints > 0).
  * Any output pointer may be NULL.
  */
 int ct_problem_info(const ct_problem *problem, int32_t *dim, int32_t *n_terms,

@@ -36,17 +36,17 @@ class CtScene(C.Structure):
 
 class CtSkeleton(C.Structure):
     _fields_ = [("n_steps", C.c_int32), ("object_of_step", _ip), ("grasp_lo", _dp), ("grasp_hi", _dp),
-                ("goal_cost", C.c_int32), ("waypoints", C.c_int32), ("q0", _dp)]
+                ("goal_cost", C.c_int32), ("waypoints", C.c_int32), ("q0", _dp), ("self_collision", C.c_int32)]
 
 
 class CtWeights(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("kin_pos", "kin_rot", "grasp", "place", "jlim", "coll", "goal",
-                                          "traj_len", "motion_coll")]
+                                          "traj_len", "motion_coll", "self_coll")]
 
 
 class CtTolerances(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("kin_pos", "kin_rot", "grasp", "place", "jlim", "coll",
-                                          "motion_coll")]
+                                          "motion_coll", "self_coll")]
 
 
 class CtAdam(C.Structure):
@@ -159,10 +159,10 @@ def ct_problem_create(prob: I.Problem) -> int:
     glo = np.array([prob.grasp_bounds(k)[0] for k in range(K)])
     ghi = np.array([prob.grasp_bounds(k)[1] for k in range(K)])
     skel = CtSkeleton(K, ip(sk.object_of_step), dp(glo), dp(ghi), int(sk.goal_cost), int(sk.waypoints),
-                      dp(sk.q0))
+                      dp(sk.q0), int(sk.self_collision))
     weights = CtWeights(w.kin_pos, w.kin_rot, w.grasp, w.place, w.jlim, w.coll, w.goal, w.traj_len,
-                        w.motion_coll)
-    tols = CtTolerances(e.kin_pos, e.kin_rot, e.grasp, e.place, e.jlim, e.coll, e.motion_coll)
+                        w.motion_coll, w.self_coll)
+    tols = CtTolerances(e.kin_pos, e.kin_rot, e.grasp, e.place, e.jlim, e.coll, e.motion_coll, e.self_coll)
     h = C.c_void_p()
     _chk(LIB.ct_problem_create(C.byref(robot), C.byref(scene), C.byref(skel), C.byref(weights),
                                C.byref(tols), C.byref(h)), "ct_problem_create")

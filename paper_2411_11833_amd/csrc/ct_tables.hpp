@@ -32,9 +32,9 @@ struct SBox {
 };
 
 // weight slots
-enum { W_KPOS, W_KROT, W_GRASP, W_PLACE, W_JLIM, W_COLL, W_GOAL, W_TRAJ, W_MCOLL, W_N };
+enum { W_KPOS, W_KROT, W_GRASP, W_PLACE, W_JLIM, W_COLL, W_GOAL, W_TRAJ, W_MCOLL, W_SELF, W_N };
 // tolerance slots
-enum { E_KPOS, E_KROT, E_GRASP, E_PLACE, E_JLIM, E_COLL, E_MCOLL, E_N };
+enum { E_KPOS, E_KROT, E_GRASP, E_PLACE, E_JLIM, E_COLL, E_MCOLL, E_SELF, E_N };
 
 // term index of each kind inside one step's block of CT_TERMS_PER_STEP
 enum {
@@ -53,6 +53,8 @@ struct Tables {
     int W;             // interior waypoints per transition (0 = no motion cost)
     int goal_term;     // index of the goal term (or -1)
     int traj_term;     // index of the TrajLength term (or -1)
+    int self_on;       // robot self-collision constraint at the key configurations on/off
+    int self_term;     // index of the first self-collision term (slot s adds s), or -1
     int link_start[10];  // robot spheres of link L (1..8) are rs[link_start[L] .. link_start[L+1])
     float ca[CT_N_JOINTS], sa[CT_N_JOINTS], a[CT_N_JOINTS], d[CT_N_JOINTS], th0[CT_N_JOINTS];
     float q_lo[CT_N_JOINTS], q_hi[CT_N_JOINTS];

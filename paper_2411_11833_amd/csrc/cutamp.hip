@@ -141,24 +141,26 @@ bool valid_adam(const ct_adam* a) {
 }
 
 // ---------------------------------------------------------------------------
-// particle kernel dispatch: split in {1, 2, 4} (one object file per split),
-// skeleton length K = 1..6, three modes; the many-skeleton kernel reads K
-// from each skeleton's tables at run time
+// particle kernel dispatch: split in {1, 2, 4}, with or without the
+// self-collision pass (one object file per combination), skeleton length
+// K = 1..6, three modes; the many-skeleton kernel reads K from each
+// skeleton's tables at run time.  Problems without self-collision run
+// kernels that do not contain the pass (it would cost them registers).
 
-PkFn pick_kernel(int split, int K, int mode) {
+PkFn pick_kernel(int split, int K, int mode, bool self) {
     switch (split) {
-        case 1: return ct_pick_s1(K, mode);
-        case 2: return ct_pick_s2(K, mode);
-        case 4: return ct_pick_s4(K, mode);
+        case 1: return self ? ct_pick_s1_self(K, mode) : ct_pick_s1(K, mode);
+        case 2: return self ? ct_pick_s2_self(K, mode) : ct_pick_s2(K, mode);
+        case 4: return self ? ct_pick_s4_self(K, mode) : ct_pick_s4(K, mode);
         default: return nullptr;
     }
 }
 
-BatchFn pick_batch(int split) {
+BatchFn pick_batch(int split, bool self) {
     switch (split) {
-        case 1: return ct_batch_s1();
-        case 2: return ct_batch_s2();
-        case 4: return ct_batch_s4();
+        case 1: return self ? ct_batch_s1_self() : ct_batch_s1();
+        case 2: return self ? ct_batch_s2_self() : ct_batch_s2();
+        case 4: return self ? ct_batch_s4_self() : ct_batch_s4();
         default: return nullptr;
     }
 }
@@ -167,7 +169,7 @@ int effective_split(const ct_problem* P, int64_t n) { return P->split ? P->split
 
 int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0) {
     if (a.n == 0) return CT_OK;
-    PkFn f = pick_kernel(split ? split : effective_split(P, a.n), P->K, mode);
+    PkFn f = pick_kernel(split ? split : effective_split(P, a.n), P->K, mode, P->h.self_on != 0);
     if (!f) return CT_ERR_UNSUPPORTED;
     return err_of(f(P->d, a, st));
 }
@@ -244,6 +246,7 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
     if (K > CT_MAX_STEPS) return CT_ERR_UNSUPPORTED;
     if (!sk->object_of_step || !sk->grasp_lo || !sk->grasp_hi) return CT_ERR_INVALID_ARG;
     if (sk->goal_cost != 0 && sk->goal_cost != 1) return CT_ERR_INVALID_ARG;
+    if (sk->self_collision != 0 && sk->self_collision != 1) return CT_ERR_INVALID_ARG;
     if (sk->waypoints < 0) return CT_ERR_INVALID_ARG;
     if (sk->waypoints > CT_MAX_WAYPOINTS) return CT_ERR_UNSUPPORTED;
     if (sk->waypoints > 0) {
@@ -264,11 +267,12 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
     const int n_unmoved = scene->n_objects - K;
     if (1 + scene->n_obstacles + n_unmoved > CT_MAX_STATIC_BOXES) return CT_ERR_UNSUPPORTED;
     // ---- weights and tolerances
-    const double ws[9] = {w->kin_pos, w->kin_rot, w->grasp, w->place, w->jlim, w->coll, w->goal, w->traj_len,
-                          w->motion_coll};
+    const double ws[ct::W_N] = {w->kin_pos, w->kin_rot, w->grasp,       w->place,       w->jlim,
+                                w->coll,    w->goal,    w->traj_len,    w->motion_coll, w->self_coll};
     for (double v : ws)
         if (!is_fin(v) || v < 0) return CT_ERR_INVALID_ARG;
-    const double es[7] = {e->kin_pos, e->kin_rot, e->grasp, e->place, e->jlim, e->coll, e->motion_coll};
+    const double es[ct::E_N] = {e->kin_pos, e->kin_rot, e->grasp,       e->place,
+                                e->jlim,    e->coll,    e->motion_coll, e->self_coll};
     for (double v : es)
         if (!is_fin(v) || v < 0) return CT_ERR_INVALID_ARG;
 
@@ -279,7 +283,9 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
     T.K = K;
     T.D = CT_STEP_DIM * K;
     T.W = sk->waypoints;
-    T.n_constraint = CT_TERMS_PER_STEP * K + (T.W > 0 ? 2 * K : 0);
+    T.self_on = sk->self_collision;
+    T.self_term = T.self_on ? CT_TERMS_PER_STEP * K + (T.W > 0 ? 2 * K : 0) : -1;
+    T.n_constraint = CT_TERMS_PER_STEP * K + (T.W > 0 ? 2 * K : 0) + (T.self_on ? 2 * K : 0);
     T.goal = sk->goal_cost;
     T.goal_term = T.goal ? T.n_constraint : -1;
     T.traj_term = T.W > 0 ? T.n_constraint + T.goal : -1;
@@ -699,7 +705,9 @@ int batch_launch(ct_batch* B, const ct_adam* adam, int32_t t, const int32_t* t_i
     AdamArgs a = adam_args(adam);
     if (B->persistent) {
         if (B->n_items == 0) return CT_OK;
-        BatchFn f = pick_batch(batch_split(B));
+        bool self = false;
+        for (const ct_problem* P : B->probs) self = self || P->h.self_on;
+        BatchFn f = pick_batch(batch_split(B), self);
         if (!f) return CT_ERR_UNSUPPORTED;
         BatchArgs g{};
         g.skels = B->d_skels;

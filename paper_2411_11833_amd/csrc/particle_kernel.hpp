@@ -259,6 +259,23 @@ __device__ __forceinline__ void cross3(const float a[3], const float b[3], float
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// One standard-DH joint: (R, t) <- (R, t) Rz(theta_i) Tz(d_i) Tx(a_i) Rx(alpha_i)
+// for joint i (0-based) with the sine and cosine of theta_i = q_i + theta0_i.
+__device__ __forceinline__ void joint_advance(const Tables* __restrict__ T, int i, float sn, float cs, float R[9],
+                                              float t[3]) {
+    const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
+    const float lx = a * cs, ly = a * sn;
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr) {
+        const float r0 = R[3 * rr], r1 = R[3 * rr + 1], r2 = R[3 * rr + 2];
+        t[rr] += r0 * lx + r1 * ly + r2 * d;
+        const float w = r1 * cs - r0 * sn;
+        R[3 * rr] = r0 * cs + r1 * sn;
+        R[3 * rr + 1] = ca * w + r2 * sa;
+        R[3 * rr + 2] = r2 * ca - sa * w;
+    }
+}
+
 // NB consecutive robot spheres of one lane on a link with frame (R, t):
 // lane si of a slot takes table entries s0 + si + SPLIT j, j = j0 .. j0+NB-1
 // (entries past the link's end get radius 0, which never penetrates).
@@ -414,6 +431,145 @@ __device__ __forceinline__ float bounds_dist(const float v[N], const float* lo, 
     return dist;
 }
 
+// Robot self-collision of one configuration: pairs of robot spheres on links
+// La < Lb with Lb >= La + 2, penalty max(0, r_a + r_b - |c_a - c_b|).  The
+// work is done in the frame of La: the frame of every later link relative to
+// it is a product of joint transforms (the stored joint sines and cosines),
+// so no world frame is formed and nothing is staged.
+//
+// Gradient: a pair pushes its b sphere with g_b = lam (c_a - c_b) / |c_a - c_b|
+// and its a sphere with -g_b along the same line, so a joint that moves both
+// spheres (joints up to La) feels nothing; joint j in La+1 .. Lb (0-based
+// index La .. Lb-1) feels the wrench (g_b, c_b x g_b) through its axis S_j.
+// Per La, the b-side wrenches are summed by link and folded onto the axes as
+// in the world pass: dJ/dq_j = <S_j, W_total> - <S_j, W of links <= j>.
+
+// NB consecutive spheres of link Lb of one lane (entries b0 + si + SPLIT j,
+// j = j0 .. j0+NB-1, in a frame (Q, o) relative to link La's frame) against
+// every sphere of La (in La's own frame; uniform loads, one per NB pairs).
+// Skipped when no lane's run meets La's bounding sphere (it would add zeros).
+template <int SPLIT, int NB, bool GRAD>
+__device__ __forceinline__ void self_run(const Tables* __restrict__ T, int a0, int a1, float4 ba, int b0, int b1,
+                                         int j0, int si, const float Q[9], const float o[3], float lam, float& pen,
+                                         float F[3], float Mo[3]) {
+    float cx[NB], cy[NB], cz[NB], rb[NB];
+    bool valid[NB];
+    bool near = false;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const int base = b0 + SPLIT * (j0 + m);   // uniform
+        float4 sb = T->rs[min(base, b1 - 1)];
+        if (SPLIT > 1) {
+#pragma unroll
+            for (int u = 1; u < SPLIT; ++u) {
+                const float4 alt = T->rs[min(base + u, b1 - 1)];
+                if (si == u) sb = alt;
+            }
+        }
+        valid[m] = base + si < b1;
+        rb[m] = sb.w;
+        cx[m] = Q[0] * sb.x + Q[1] * sb.y + Q[2] * sb.z + o[0];
+        cy[m] = Q[3] * sb.x + Q[4] * sb.y + Q[5] * sb.z + o[1];
+        cz[m] = Q[6] * sb.x + Q[7] * sb.y + Q[8] * sb.z + o[2];
+        const float ux = cx[m] - ba.x, uy = cy[m] - ba.y, uz = cz[m] - ba.z, ur = ba.w + sb.w;
+        near |= valid[m] && ux * ux + uy * uy + uz * uz < ur * ur;
+    }
+    if (!__ballot(near)) return;   // wave-uniform
+    float p[NB], gx[NB], gy[NB], gz[NB];
+#pragma unroll
+    for (int m = 0; m < NB; ++m) p[m] = gx[m] = gy[m] = gz[m] = 0.f;
+    for (int a = a0; a < a1; ++a) {
+        const float4 sa = T->rs[a];
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const float dx = sa.x - cx[m], dy = sa.y - cy[m], dz = sa.z - cz[m];
+            const float d2 = dx * dx + dy * dy + dz * dz;
+            const float rsum = sa.w + rb[m];
+            if (valid[m] && d2 < rsum * rsum) {
+                const float dist = sqrtf(d2);
+                p[m] += rsum - dist;
+                if (GRAD && dist > 0.f) {
+                    const float sc = lam / dist;
+                    gx[m] += dx * sc; gy[m] += dy * sc; gz[m] += dz * sc;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        pen += p[m];
+        if (GRAD) {
+            F[0] += gx[m]; F[1] += gy[m]; F[2] += gz[m];
+            Mo[0] += cy[m] * gz[m] - cz[m] * gy[m];
+            Mo[1] += cz[m] * gx[m] - cx[m] * gz[m];
+            Mo[2] += cx[m] * gy[m] - cy[m] * gx[m];
+        }
+    }
+}
+
+// All sphere pairs of links La and Lb (frame (Q, o) of Lb relative to La):
+// runs of 2, then 1 over the entries each lane of the slot takes;
+// skipped as a whole when no lane's bounding spheres of the two links meet.
+template <int SPLIT, bool GRAD>
+__device__ __forceinline__ void self_block(const Tables* __restrict__ T, int La, int Lb, int si, const float Q[9],
+                                           const float o[3], float lam, float& pen, float F[3], float Mo[3]) {
+    const int a0 = T->link_start[La], a1 = T->link_start[La + 1];
+    const int b0 = T->link_start[Lb], b1 = T->link_start[Lb + 1];
+    if (b0 == b1) return;
+    const float4 ba = T->lbs[La], bb = T->lbs[Lb];
+    const float ex = Q[0] * bb.x + Q[1] * bb.y + Q[2] * bb.z + o[0] - ba.x;
+    const float ey = Q[3] * bb.x + Q[4] * bb.y + Q[5] * bb.z + o[1] - ba.y;
+    const float ez = Q[6] * bb.x + Q[7] * bb.y + Q[8] * bb.z + o[2] - ba.z;
+    const float rs = ba.w + bb.w;
+    if (!__ballot(ex * ex + ey * ey + ez * ez < rs * rs)) return;   // wave-uniform
+    const int per_lane = (b1 - b0 + SPLIT - 1) / SPLIT;
+    int j = 0;
+    for (; j + 2 <= per_lane; j += 2)
+        self_run<SPLIT, 2, GRAD>(T, a0, a1, ba, b0, b1, j, si, Q, o, lam, pen, F, Mo);
+    if (j < per_lane) self_run<SPLIT, 1, GRAD>(T, a0, a1, ba, b0, b1, j, si, Q, o, lam, pen, F, Mo);
+}
+
+// <S_j, (F, Mo)> for the axis of a frame (R, t): z . Mo + (t x z) . F
+__device__ __forceinline__ float axis_dot(const float R[9], const float t[3], const float F[3], const float Mo[3]) {
+    const float z[3] = {R[2], R[5], R[8]};
+    float mz[3];
+    cross3(t, z, mz);
+    return z[0] * Mo[0] + z[1] * Mo[1] + z[2] * Mo[2] + mz[0] * F[0] + mz[1] * F[1] + mz[2] * F[2];
+}
+
+template <int SPLIT, bool GRAD>
+__device__ __forceinline__ void self_pass(const Tables* __restrict__ T, int si, const float jsn[CT_N_JOINTS],
+                                          const float jcs[CT_N_JOINTS], float lam, float& pen,
+                                          float gq[CT_N_JOINTS]) {
+#pragma unroll 1
+    for (int La = 1; La <= 6; ++La) {   // wave-uniform
+        if (T->link_start[La] == T->link_start[La + 1]) continue;
+        float Q[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+        float o[3] = {0.f, 0.f, 0.f};
+        float F[3] = {0.f, 0.f, 0.f}, Mo[3] = {0.f, 0.f, 0.f};   // b-side wrench, La's frame and origin
+#pragma unroll
+        for (int j = 1; j < CT_N_JOINTS; ++j) {   // (Q, o) is frame j: joint j's axis (0-based)
+            if (j < La) continue;                  // wave-uniform
+            if (GRAD && j > La) gq[j] -= axis_dot(Q, o, F, Mo);
+            joint_advance(T, j, jsn[j], jcs[j], Q, o);
+            if (j + 1 >= La + 2) self_block<SPLIT, GRAD>(T, La, j + 1, si, Q, o, lam, pen, F, Mo);
+        }
+        // the tool: frame 7 moved along its z-axis
+        const float ot[3] = {o[0] + Q[2] * T->tool_d, o[1] + Q[5] * T->tool_d, o[2] + Q[8] * T->tool_d};
+        self_block<SPLIT, GRAD>(T, La, 8, si, Q, ot, lam, pen, F, Mo);
+        if (GRAD) {
+            float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+            float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 1; j < CT_N_JOINTS; ++j) {
+                if (j < La) continue;
+                gq[j] += axis_dot(R, t, F, Mo);
+                if (j + 1 < CT_N_JOINTS) joint_advance(T, j, jsn[j], jcs[j], R, t);
+            }
+        }
+    }
+}
+
 struct LaneOut {
     float cost;   // weighted sum of this slot's terms
     float traj;   // this slot's transition length (TrajLength share), 0 without motion
@@ -432,7 +588,8 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                                             float lam, const MoveCtx<KT>& mc, float gx, float gy, float gz,
                                             float g_c, float g_s, float rho_x, float rho_y, float rho_c,
                                             float rho_s, float& coll, float gq[CT_N_JOINTS], float gg[4],
-                                            float* __restrict__ gr, float& kin_pos, float& kin_rot) {
+                                            float* __restrict__ gr, float& kin_pos, float& kin_rot, bool self,
+                                            float& self_pen) {
     const int k = mc.k;
     // Joint axis S_j = (z_j, o_j x z_j) of joint j+1 (z of frame j through its
     // origin).  dJ/dq_j = <S_j, wrench of links j+1..8>
@@ -458,17 +615,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
         sincosf(q[i] + T->th0[i], &sn, &cs);
         jsn[i] = sn;
         jcs[i] = cs;
-        const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
-        const float lx = a * cs, ly = a * sn;
-#pragma unroll
-        for (int rr = 0; rr < 3; ++rr) {
-            const float r0 = R[3 * rr], r1 = R[3 * rr + 1], r2 = R[3 * rr + 2];
-            t[rr] += r0 * lx + r1 * ly + r2 * d;
-            const float w = r1 * cs - r0 * sn;
-            R[3 * rr] = r0 * cs + r1 * sn;
-            R[3 * rr + 1] = ca * w + r2 * sa;
-            R[3 * rr + 2] = r2 * ca - sa * w;
-        }
+        joint_advance(T, i, sn, cs, R, t);
         link_spheres<KT, SPLIT, GRAD>(T, i + 1, si, R, t, mc, lam, coll, f, tq, gr);
     }
     // ---- tool frame: tool spheres, the held object, the kinematic constraint
@@ -567,22 +714,10 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
             float m[3];
             cross3(o, z, m);
             gq[i] += z[0] * tq[0] + z[1] * tq[1] + z[2] * tq[2] + m[0] * f[0] + m[1] * f[1] + m[2] * f[2] - cj[i];
-            if (i + 1 < CT_N_JOINTS) {
-                const float sn = jsn[i], cs = jcs[i];
-                const float ca = T->ca[i], sa = T->sa[i], a = T->a[i], d = T->d[i];
-                const float lx = a * cs, ly = a * sn;
-#pragma unroll
-                for (int rr = 0; rr < 3; ++rr) {
-                    const float r0 = Q[3 * rr], r1 = Q[3 * rr + 1], r2 = Q[3 * rr + 2];
-                    o[rr] += r0 * lx + r1 * ly + r2 * d;
-                    const float w = r1 * cs - r0 * sn;
-                    Q[3 * rr] = r0 * cs + r1 * sn;
-                    Q[3 * rr + 1] = ca * w + r2 * sa;
-                    Q[3 * rr + 2] = r2 * ca - sa * w;
-                }
-            }
+            if (i + 1 < CT_N_JOINTS) joint_advance(T, i, jsn[i], jcs[i], Q, o);
         }
     }
+    if (self) self_pass<SPLIT, GRAD>(T, si, jsn, jcs, T->w[W_SELF], self_pen, gq);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,7 +736,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
 // Every lane writes its own gradient partials (no cross-lane reduction) to
 // part[0 .. 18+3K): [0,7) own q, [7,11) grasp, [11, 11+3K) placements
 // (accumulated in place), [11+3K, 18+3K) foreign q.
-template <int KT, int SPLIT, int MODE>
+template <int KT, int SPLIT, int MODE, bool SELF>
 __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
                                              int xs_stride, const float4* __restrict__ plc,
                                              const float4* __restrict__ osl, int K_rt, int slot, int si,
@@ -609,6 +744,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
                                              int64_t term_ld, int64_t i_glob, bool write_terms) {
     constexpr bool GRAD = MODE != MODE_COST;
     const int K = KT ? KT : K_rt;
+    const bool self_on = SELF && T->self_on;   // wave-uniform; compiled out without SELF
     const int k = slot >> 1;
     const bool placing = slot & 1;
     auto X = [&](int d) { return xs[d * xs_stride]; };
@@ -652,7 +788,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
 #pragma unroll
     for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = gqa[j] = 0.f;
     float gg[4] = {0.f, 0.f, 0.f, 0.f};
-    float coll = 0.f, coll_m = 0.f, kin_pos = 0.f, kin_rot = 0.f;
+    float coll = 0.f, coll_m = 0.f, kin_pos = 0.f, kin_rot = 0.f, selfc = 0.f;
     const float4* osl_k = osl + k * CT_MAX_OBJ_SPHERES;
 
     // waypoints w = 1..W of the transition, then the configuration itself
@@ -672,7 +808,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const bool held = key || placing;
         const float lam = key ? T->w[W_COLL] : T->w[W_MCOLL];
         config_pass<KT, SPLIT, GRAD>(T, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
-                                 rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot);
+                                     rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, key && self_on, selfc);
         if (key) coll += cw; else coll_m += cw;
         if (GRAD) {
 #pragma unroll
@@ -775,6 +911,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     coll = split_sum<SPLIT>(coll);
     coll_m = split_sum<SPLIT>(coll_m);
     coll_obj = split_sum<SPLIT>(coll_obj);
+    if (self_on) selfc = split_sum<SPLIT>(selfc);
 
     LaneOut out;
     const float* w = T->w;
@@ -791,10 +928,14 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
         for (int j = 0; j < 3 * K; ++j) gsum += gr[j];
     }
-    const float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll +
+    float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll +
                      w[W_MCOLL] * coll_m + w[W_TRAJ] * traj;
     bool ok = kin_pos <= e[E_KPOS] && kin_rot <= e[E_KROT] && jlim <= e[E_JLIM] && coll <= e[E_COLL] &&
               coll_m <= e[E_MCOLL];
+    if (self_on) {
+        kw += w[W_SELF] * selfc;
+        ok = ok && selfc <= e[E_SELF];
+    }
     if (!placing) {
         out.cost = kw + w[W_GRASP] * grasp + w[W_COLL] * coll_obj;
         ok = ok && grasp <= e[E_GRASP] && coll_obj <= e[E_COLL];
@@ -827,6 +968,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             if (slot == 1 && T->goal) put(T->goal_term, goal);
         }
         if (W > 0) put(CT_TERMS_PER_STEP * K + slot, coll_m);
+        if (self_on) put(T->self_term + slot, selfc);
     }
     return out;
 }
@@ -865,7 +1007,7 @@ struct TileIO {
 };
 
 
-template <int KT, int SPLIT, int MODE>
+template <int KT, int SPLIT, int MODE, bool SELF>
 __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<SPLIT>& sm, float lr, float b1,
                                          float b2, float eps, int32_t t) {
     const Tables* __restrict__ T = io.T;
@@ -909,7 +1051,7 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
         if (slot < SLOTS) {
             const int64_t i = p0 + p;
             const bool wt = (MODE == MODE_COST) && io.terms != nullptr && i < n;
-            const LaneOut o = lane_slot<KT, SPLIT, MODE>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
+            const LaneOut o = lane_slot<KT, SPLIT, MODE, SELF>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
                                                      sm.part + (size_t)((p * SLOTS + slot) * SPLIT + si) * NP,
                                                      io.terms, ld, i, wt);
             if (si == 0) {
@@ -994,7 +1136,7 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
 
 // ---------------------------------------------------------------------------
 // One skeleton of KT steps: one workgroup per tile (XCD-aware tile order).
-template <int SPLIT, int MODE, int KT>
+template <int SPLIT, int MODE, int KT, bool SELF>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void particle_kernel(
     const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
     float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
@@ -1016,7 +1158,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
     // that share cache lines of X, M and V then share one L2
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale};
-    run_tile<KT, SPLIT, MODE>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
+    run_tile<KT, SPLIT, MODE, SELF>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
 }
 
 
@@ -1024,7 +1166,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
 // a fixed number of workgroups pull (skeleton, tile) items from a device
 // queue (items ordered by cost, largest first) until it is empty; the last
 // workgroup to leave resets the queue for the next launch.
-template <int SPLIT>
+template <int SPLIT, bool SELF>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(const BatchSkel* __restrict__ skels,
                                                    const int2* __restrict__ items, int32_t n_items,
                                                    int32_t* __restrict__ queue, float lr, float b1, float b2,
@@ -1046,7 +1188,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void ba
         const BatchSkel& b = skels[w.x];
         const TileIO io{b.T, b.X, b.M, b.V, nullptr, b.cost, nullptr, b.mask, b.first_sat, b.frozen, nullptr,
                         b.n, b.ld, b.gscale};
-        run_tile<0, SPLIT, MODE_STEP>(io, (int64_t)w.y * tile_particles(b.T->K, SPLIT), sm, lr, b1, b2, eps, t);
+        run_tile<0, SPLIT, MODE_STEP, SELF>(io, (int64_t)w.y * tile_particles(b.T->K, SPLIT), sm, lr, b1, b2, eps, t);
         __syncthreads();
     }
     if (threadIdx.x == 0) {

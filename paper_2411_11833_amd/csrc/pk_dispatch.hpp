@@ -42,9 +42,16 @@ struct BatchArgs {
 using BatchFn = hipError_t (*)(const BatchArgs&, hipStream_t);
 
 // defined in pk_instances.hip, compiled once per split (-DCT_SPLIT=1, 2, 4)
+// without (-DCT_SELF=0) and with (_self, -DCT_SELF=1) the self-collision pass
 PkFn ct_pick_s1(int K, int mode);
 PkFn ct_pick_s2(int K, int mode);
 PkFn ct_pick_s4(int K, int mode);
+PkFn ct_pick_s1_self(int K, int mode);
+PkFn ct_pick_s2_self(int K, int mode);
+PkFn ct_pick_s4_self(int K, int mode);
 BatchFn ct_batch_s1();
 BatchFn ct_batch_s2();
 BatchFn ct_batch_s4();
+BatchFn ct_batch_s1_self();
+BatchFn ct_batch_s2_self();
+BatchFn ct_batch_s4_self();

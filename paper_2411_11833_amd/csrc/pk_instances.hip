@@ -1,10 +1,14 @@
-// Instantiations of the fused particle kernels for one lane split (compiled
-// once per split with -DCT_SPLIT=<1|2|4>, so the objects build in parallel).
+// Instantiations of the fused particle kernels for one lane split, with or
+// without the robot self-collision pass (compiled once per combination with
+// -DCT_SPLIT=<1|2|4> -DCT_SELF=<0|1>, so the objects build in parallel).
 #include "particle_kernel.hpp"
 #include "pk_dispatch.hpp"
 
 #ifndef CT_SPLIT
 #error "compile with -DCT_SPLIT=<lanes per configuration>"
+#endif
+#ifndef CT_SELF
+#error "compile with -DCT_SELF=<0|1> (self-collision pass compiled in)"
 #endif
 
 namespace {
@@ -13,7 +17,7 @@ template <int S, int MODE, int K>
 hipError_t launch_pk(const ct::Tables* T, const PkArgs& g, hipStream_t st) {
     constexpr int P = ct::tile_particles(K, S);
     const dim3 grid((unsigned)((g.n + P - 1) / P));
-    hipLaunchKernelGGL((ct::particle_kernel<S, MODE, K>), grid, dim3(ct::WG), 0, st, T, g.X, g.M, g.V, g.G, g.cost,
+    hipLaunchKernelGGL((ct::particle_kernel<S, MODE, K, CT_SELF != 0>), grid, dim3(ct::WG), 0, st, T, g.X, g.M, g.V, g.G, g.cost,
                        g.terms, g.mask, g.first_sat, g.frozen, g.n, g.ld, g.a.lr, g.a.b1, g.a.b2, g.a.eps, g.a.gs,
                        g.t, g.t_in, g.t_out, g.stop_at_first, g.gw);
     return hipGetLastError();
@@ -21,7 +25,7 @@ hipError_t launch_pk(const ct::Tables* T, const PkArgs& g, hipStream_t st) {
 
 template <int S>
 hipError_t launch_batch(const BatchArgs& g, hipStream_t st) {
-    hipLaunchKernelGGL((ct::batch_kernel<S>), dim3((unsigned)g.n_workgroups), dim3(ct::WG), 0, st,
+    hipLaunchKernelGGL((ct::batch_kernel<S, CT_SELF != 0>), dim3((unsigned)g.n_workgroups), dim3(ct::WG), 0, st,
                        static_cast<const ct::BatchSkel*>(g.skels), g.items, g.n_items, g.queue, g.a.lr, g.a.b1,
                        g.a.b2, g.a.eps, g.t, g.t_in, g.t_out);
     return hipGetLastError();
@@ -51,5 +55,10 @@ PkFn pick(int K, int mode) {
 
 #define CT_CAT2(a, b) a##b
 #define CT_CAT(a, b) CT_CAT2(a, b)
-PkFn CT_CAT(ct_pick_s, CT_SPLIT)(int K, int mode) { return pick<CT_SPLIT>(K, mode); }
-BatchFn CT_CAT(ct_batch_s, CT_SPLIT)() { return launch_batch<CT_SPLIT>; }
+#if CT_SELF
+#define CT_SUFFIX _self
+#else
+#define CT_SUFFIX
+#endif
+PkFn CT_CAT(CT_CAT(ct_pick_s, CT_SPLIT), CT_SUFFIX)(int K, int mode) { return pick<CT_SPLIT>(K, mode); }
+BatchFn CT_CAT(CT_CAT(ct_batch_s, CT_SPLIT), CT_SUFFIX)() { return launch_batch<CT_SPLIT>; }

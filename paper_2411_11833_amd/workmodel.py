@@ -9,7 +9,9 @@ sin / cos / sqrt / rsq / atan2 counted apart and not as flops):
     tape-based autodiff of the same cost would spend on every pair;
   * forward kinematics: 90 flops per joint and configuration;
   * one sphere transform to world: 18 flops;
-  * Adam: 15 flops per coordinate.
+  * Adam: 15 flops per coordinate;
+  * one robot self-collision sphere pair (with the constraint on): 11 flops
+    forward (difference, squared norm, radius sum, hinge) + 8 adjoint.
 HBM bytes: X, M and V read and written once per coordinate (24 B) plus the
 per-particle cost (4 B) and mask (1 B).
 """
@@ -23,6 +25,15 @@ PAIR_FWD, PAIR_BWD = 27, 25
 FK_PER_JOINT = 90
 SPHERE_TF = 18
 ADAM_PER_COORD = 15
+SELF_FWD, SELF_BWD = 11, 8
+
+
+def self_pair_count(sphere_link) -> int:
+    """Robot sphere pairs on links two or more apart (per configuration)."""
+    n = [0] * 10
+    for L in sphere_link:
+        n[int(L)] += 1
+    return sum(n[a] * n[b] for a in range(10) for b in range(a + 2, 10))
 
 
 @dataclass
@@ -51,5 +62,7 @@ def per_particle_iteration(prob: I.Problem) -> Work:
     pairs = inst * n_boxes
     flops = (pairs * (PAIR_FWD + PAIR_BWD) + configs * 7 * FK_PER_JOINT + inst * SPHERE_TF
              + prob.dim * ADAM_PER_COORD)
+    if prob.skeleton.self_collision:
+        flops += 2 * K * self_pair_count(prob.robot.sphere_link) * (SELF_FWD + SELF_BWD)
     nbytes = 24 * prob.dim + 5
     return Work(pairs=pairs, sphere_instances=inst, configs=configs, flops=flops, bytes=nbytes)

@@ -60,9 +60,10 @@ def _descriptors(prob, **over):
     oos = over.get("object_of_step", sk.object_of_step)
     glo = np.array([prob.grasp_bounds(0)[0]] * max(K, 1))
     ghi = np.array([prob.grasp_bounds(0)[1]] * max(K, 1))
-    skel = B.CtSkeleton(K, ip(oos), dp(glo), dp(ghi), over.get("goal", 0), over.get("waypoints", 0), dp(sk.q0))
-    w = B.CtWeights(1, 5, 1, 2, 1, over.get("w_coll", 1.0), 0.25, 0.1, 1)
-    e = B.CtTolerances(0.005, 0.05, 0, 0.001, 0, 0.001, 0.001)
+    skel = B.CtSkeleton(K, ip(oos), dp(glo), dp(ghi), over.get("goal", 0), over.get("waypoints", 0), dp(sk.q0),
+                        over.get("self_collision", 0))
+    w = B.CtWeights(1, 5, 1, 2, 1, over.get("w_coll", 1.0), 0.25, 0.1, 1, over.get("w_self", 1.0))
+    e = B.CtTolerances(0.005, 0.05, 0, 0.001, 0, 0.001, 0.001, over.get("e_self", 0.0))
     return keep, robot, scene, skel, w, e
 
 
@@ -86,6 +87,9 @@ def _create(prob, **over):
     ({"w_coll": -1.0}, B.CT_ERR_INVALID_ARG),
     ({"goal": 3}, B.CT_ERR_INVALID_ARG),
     ({"waypoints": -1}, B.CT_ERR_INVALID_ARG),
+    ({"self_collision": 2}, B.CT_ERR_INVALID_ARG),
+    ({"self_collision": 1, "w_self": -1.0}, B.CT_ERR_INVALID_ARG),
+    ({"self_collision": 1, "e_self": float("nan")}, B.CT_ERR_INVALID_ARG),
 ])
 def test_create_rejects_bad_descriptors(over, want):
     rc, h = _create(I.single_pick_place(0, 0), **over)

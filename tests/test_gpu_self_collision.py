@@ -1,0 +1,139 @@
+"""GPU parity of the robot self-collision constraint (sphere pairs on links
+two or more apart, one term per key configuration, tolerance 0) with the FP64
+oracle, through the C ABI, at the tolerances of the other parity tests:
+terms and costs 1e-4 relative + 2e-6, gradients 1e-3 relative (particles with
+kink margin >= 1e-5), one Adam update 1e-5 absolute, masks bit-exact outside
+the 1e-4 flip band; many-skeleton launches bit-exact with per-skeleton ones.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2411_11833_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_parity import _adam, _check_cost_terms_mask, _check_grad, _close, _gp  # noqa: E402
+
+
+def _with_self(prob):
+    prob.skeleton.self_collision = 1
+    return prob
+
+
+CASES = {
+    "single": lambda: _with_self(I.single_pick_place(0, 0)),
+    "packing": lambda: _with_self(I.packing(0, 0)),
+    "six_steps": lambda: _with_self(I.packing(2, 3, n_objects=6, n_obstacles=4)),
+    "motion": lambda: _with_self(I.packing(robot_seed=1, scene_seed=2, n_objects=2, n_obstacles=2, waypoints=4)),
+}
+
+
+def _self_block(prob, T):
+    nc = prob.n_constraint_terms
+    return T[:, nc - prob.n_self_terms:nc]
+
+
+@pytest.mark.parametrize("case,n", [("single", 256), ("packing", 200), ("six_steps", 45), ("motion", 40)])
+def test_self_terms_cost_mask(case, n):
+    prob = CASES[case]()
+    gp = _gp(prob)
+    X = I.uniform_particles(prob, n, seed=31)
+    _, T, _ = _check_cost_terms_mask(prob, gp, X)
+    # the case exercises the term: some configurations penetrate, some do not
+    # (robot seed 1 of the motion case has 0.12 m links between links whose
+    # end spheres overlap in every configuration: it always penetrates)
+    S = _self_block(prob, T)
+    assert np.any(S > 0)
+    if case != "motion":
+        assert np.any(S == 0)
+
+
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_self_terms_every_split(split):
+    prob = CASES["packing"]()
+    X = I.uniform_particles(prob, 77, seed=32)
+    _check_cost_terms_mask(prob, _gp(prob), X, split=split)
+
+
+@pytest.mark.parametrize("case,n,split", [("single", 192, None), ("packing", 150, None), ("packing", 64, 2),
+                                          ("packing", 64, 4), ("six_steps", 40, None), ("motion", 32, None)])
+def test_self_gradient(case, n, split):
+    prob = CASES[case]()
+    gp = _gp(prob)
+    if split is not None:
+        gp.set_split(split)
+    X = I.uniform_particles(prob, n, seed=33)
+    G, Go, ok = _check_grad(prob, gp, X)
+    # the self-collision part of the gradient is really present: compare with
+    # the same particles without the constraint
+    base = CASES[case]()
+    base.skeleton.self_collision = 0
+    _, Gb = O.cost_and_grad(base, X.astype(np.float64))
+    assert np.any(np.abs(Go - Gb).max(1) > 1e-3)
+
+
+def test_self_fused_step():
+    prob = CASES["packing"]()
+    n = 128
+    gp = _gp(prob)
+    X = I.uniform_particles(prob, n, seed=34)
+    Xd = gp.from_rows(X)
+    Md, Vd = torch.zeros_like(Xd), torch.zeros_like(Xd)
+    cost = torch.empty(n, device="cuda")
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    gp.step(Xd, Md, Vd, n, 1, _adam(n), cost=cost, mask=mask)
+    torch.cuda.synchronize()
+    X64 = X.astype(np.float64)
+    Jo, Go = O.cost_and_grad(prob, X64)
+    assert not _close(cost.cpu().numpy(), Jo).any()
+    _, kink = O.margins(prob, X64)
+    ok = kink >= 1e-5
+    xo, _, _ = O.adam_step(X, np.zeros_like(X), np.zeros_like(X), Go, 1, grad_scale=1.0 / n)
+    err = np.abs(gp.to_rows(Xd, n).cpu().numpy() - xo).max(1)
+    assert np.all(err[ok] <= 1e-5), err[ok].max()
+
+
+def test_self_full_size_sampled():
+    """Packing at 8192 particles with the constraint on, in the launch shape
+    of the throughput measurement: sampled particles against the oracle."""
+    prob = CASES["packing"]()
+    n = 8192
+    gp = _gp(prob)
+    X = I.uniform_particles(prob, n, seed=35)
+    Xd = gp.from_rows(X)
+    c, T, m = gp.cost(Xd, n, terms=True)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(3).choice(n, 96, replace=False)
+    T = gp.to_rows(T, n).cpu().numpy()[idx]
+    To = O.terms(prob, X[idx].astype(np.float64))
+    assert not _close(T, To).any()
+    assert not _close(c.cpu().numpy()[idx], To @ O.weights_vector(prob)).any()
+
+
+def test_self_batch_matches_per_skeleton_steps():
+    """Skeletons with and without the constraint in one persistent launch give
+    the per-skeleton results bit for bit."""
+    from paper_2411_11833_amd.planner import GpuBatch
+    robot = I.make_robot(0, n_spheres=60)
+    probs = [I.random_skeleton_problem(s, robot) for s in (1, 2, 3, 4)]
+    for p in probs[::2]:
+        p.skeleton.self_collision = 1
+    sizes = [131, 64, 200, 77]
+    b = GpuBatch(probs, sizes)
+    b.set_tuning(split=2, workgroups=37)
+    b.seed(8)
+    ref = [(x.clone(), m.clone(), v.clone()) for x, m, v in zip(b.X, b.M, b.V)]
+    for t in (1, 2):
+        b.step(t, _adam(1))
+    for s, (g, n) in enumerate(zip(b.gps, sizes)):
+        X, M, V = ref[s]
+        g.set_split(2)
+        c = torch.empty(n, device="cuda")
+        for t in (1, 2):
+            g.step(X, M, V, n, t, _adam(n), frozen=b.frozen[s], cost=c)
+        torch.cuda.synchronize()
+        assert torch.equal(X, b.X[s]) and torch.equal(M, b.M[s]) and torch.equal(V, b.V[s]), s
+        assert torch.equal(c, b.cost[s]), s

@@ -15,6 +15,9 @@ the oracle's own cost.  References are to the paper (Shen et al.,
 * batch objective (mean over the N_b particles) ............. Eq. (4)
 * plan-skeleton feasibility heuristic H ...................... Eq. (5)
 * Adam on that objective ..................................... Sec. IV-B
+* per-particle (augmented-Lagrangian) term weights and the
+  method-of-multipliers update ............................... Sec. IV-B (optimizers the method
+                                                                admits), Sec. "Limitations"
 * Kin(q,o,g,p): FK(q) = p * g, pose error .................... Sec. III, App. listing of example cost functions
 * distance from bounds, pairwise object distance ............. App. listing of example cost functions
 * weights (1, kin-rot 5, stable place 2), tolerances ........ App. "Cost Weights", "Constraint Tolerances"
@@ -47,6 +50,7 @@ __all__ = [
     "dist_from_bounds", "pairwise_dist_sum", "grasp_tf", "place_tf", "evaluate",
     "Evaluation", "terms", "cost", "mask", "cost_and_grad", "adam_step", "margins",
     "weights_vector", "tolerance_vector", "place_z", "feasibility", "self_pairs", "self_collision",
+    "weighted_cost_and_grad", "al_update",
 ]
 
 
@@ -490,6 +494,41 @@ def cost_and_grad(prob: Problem, X, chunk: int = 128):
     if not Js:
         return np.zeros(0), np.zeros((0, prob.dim))
     return torch.cat(Js).numpy(), torch.cat(Gs).numpy()
+
+
+def weighted_cost_and_grad(prob: Problem, X, W, chunk: int = 128):
+    """Eq. (2) with per-particle weights in place of lambda: J_i = sum_c
+    W[i, c] J_c(x_i), W [N, n_terms]; returns (J [N], dJ/dx [N, dim]) by
+    reverse-mode autodiff of that sum."""
+    X = torch.as_tensor(np.asarray(X, dtype=np.float64))
+    Wt = torch.as_tensor(np.array(W, dtype=np.float64))
+    Js, Gs = [], []
+    for a, b in _chunks(X.shape[0], chunk):
+        x = X[a:b].clone().requires_grad_(True)
+        J = (evaluate(prob, x).terms * Wt[a:b]).sum(1)
+        (g,) = torch.autograd.grad(J.sum(), x)
+        Js.append(J.detach())
+        Gs.append(g)
+    if not Js:
+        return np.zeros(0), np.zeros((0, prob.dim))
+    return torch.cat(Js).numpy(), torch.cat(Gs).numpy()
+
+
+def al_update(prob: Problem, T, mu, rho: float):
+    """One method-of-multipliers step on the constraint weights: each
+    constraint J_c <= eps_c is the inequality g_c = J_c - eps_c <= 0, whose
+    multiplier moves to max(0, mu_c + rho g_c) (a non-finite J_c leaves it);
+    the term's weight becomes lambda_c + mu_c.  Soft costs keep lambda_c and
+    their multipliers.  T, mu: [N, n_terms]; returns (mu, W)."""
+    T = np.asarray(T, dtype=np.float64)
+    mu = np.array(mu, dtype=np.float64, copy=True)
+    nc = prob.n_constraint_terms
+    g = T[:, :nc] - tolerance_vector(prob)[None]
+    fin = np.isfinite(T[:, :nc])
+    mu[:, :nc] = np.where(fin, np.maximum(0.0, mu[:, :nc] + rho * np.where(fin, g, 0.0)), mu[:, :nc])
+    W = np.broadcast_to(weights_vector(prob), T.shape).copy()
+    W[:, :nc] += mu[:, :nc]
+    return mu, W
 
 
 def adam_step(x, m, v, g, t: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,

@@ -502,3 +502,59 @@ def test_self_terms_layout_and_mask():
                                atol=1e-12)
     m = O.mask(prob, T)
     assert np.array_equal(m, O.mask(base, Tb) & np.all(S <= 0.0, axis=1))
+
+
+# ----------------------------------------------------------------------------- augmented-Lagrangian weights
+
+
+def test_weighted_cost_reduces_to_eq2_and_matches_finite_differences():
+    """With every particle's weights equal to lambda the weighted cost is
+    Eq. (2); with random weights its gradient matches central differences
+    of sum_c W_c J_c."""
+    prob = _small_packing()
+    X = I.uniform_particles(prob, 24, seed=12).astype(np.float64)
+    lam = np.broadcast_to(O.weights_vector(prob), (24, prob.n_terms))
+    J, G = O.weighted_cost_and_grad(prob, X, lam)
+    J0, G0 = O.cost_and_grad(prob, X)
+    np.testing.assert_allclose(J, J0, rtol=1e-13)
+    np.testing.assert_allclose(G, G0, rtol=1e-12, atol=1e-13)
+    _, kink = O.margins(prob, X)
+    X = X[kink >= 1e-4][:4]
+    W = np.random.default_rng(3).uniform(0.1, 5.0, (len(X), prob.n_terms))
+    J, G = O.weighted_cost_and_grad(prob, X, W)
+    h = 1e-6
+    for i in range(prob.dim):
+        xp, xm = X.copy(), X.copy()
+        xp[:, i] += h
+        xm[:, i] -= h
+        fd = ((O.terms(prob, xp) * W).sum(1) - (O.terms(prob, xm) * W).sum(1)) / (2 * h)
+        assert np.all(np.abs(G[:, i] - fd) <= 1e-5 * np.abs(fd) + 1e-6 * (1 + np.abs(J))), i
+
+
+def test_al_update_special_cases():
+    """rho = 0 keeps the multipliers; a violated constraint raises its
+    multiplier by rho times the violation, a satisfied one lowers it, never
+    below 0; NaN terms keep theirs; soft costs keep lambda."""
+    prob = _small_packing()
+    prob.skeleton.goal_cost = 1
+    nc, nt = prob.n_constraint_terms, prob.n_terms
+    eps = O.tolerance_vector(prob)
+    lam = O.weights_vector(prob)
+    T = np.zeros((3, nt))
+    T[0, :nc] = eps + 0.5          # violated by 0.5 everywhere
+    T[1, :nc] = eps * 0.5          # satisfied (0 for eps = 0 terms)
+    T[2, :nc] = np.nan
+    T[:, nc:] = 7.0
+    mu0 = np.full((3, nt), 0.25)
+    mu, W = O.al_update(prob, T, mu0, 0.0)
+    np.testing.assert_array_equal(mu, mu0)
+    mu, W = O.al_update(prob, T, mu0, 2.0)
+    np.testing.assert_allclose(mu[0, :nc], 0.25 + 2.0 * 0.5)
+    np.testing.assert_allclose(mu[1, :nc], np.maximum(0.0, 0.25 - 2.0 * (eps - eps * 0.5)))
+    np.testing.assert_array_equal(mu[2], mu0[2])
+    np.testing.assert_array_equal(mu[:, nc:], mu0[:, nc:])
+    np.testing.assert_allclose(W[:, :nc], lam[None, :nc] + mu[:, :nc])
+    np.testing.assert_array_equal(W[:, nc:], np.broadcast_to(lam[nc:], (3, nt - nc)))
+    # a long-satisfied constraint's multiplier decays to exactly 0
+    mu, _ = O.al_update(prob, np.zeros((1, nt)) + np.r_[eps - 0.1, np.zeros(nt - nc)][None], np.ones((1, nt)), 100)
+    assert np.all(mu[0, :nc][eps > 0] == 0)

@@ -17,6 +17,8 @@ Also reported on the same JSON line:
     length in one persistent launch per iteration vs one launch each;
   * the plan-skeleton feasibility heuristic H of Eq. (5);
   * the packing step with the robot self-collision constraint switched on;
+  * augmented-Lagrangian constraint weights: the weighted step kernel and the
+    plain method's time to first with per-particle multipliers;
   * compositional initialization (one-step problems composed, then refined)
     on held-out packing scenes;
   * learned vs uniform seeds: a BF16 MLP proposer trained on the GPU on the
@@ -87,6 +89,9 @@ def parse():
     ap.add_argument("--no-motion", action="store_true", help="skip the waypoint motion-cost measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-skeleton measurement")
     ap.add_argument("--no-self", action="store_true", help="skip the self-collision measurement")
+    ap.add_argument("--no-al", action="store_true", help="skip the augmented-Lagrangian measurement")
+    ap.add_argument("--al-rho", type=float, default=10.0, help="multiplier step of the augmented-Lagrangian mode")
+    ap.add_argument("--al-outer", type=int, default=50, help="iterations between multiplier updates")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
@@ -439,6 +444,39 @@ def main():
         log(f"[bench] single pick-place (256 particles) time-to-first seed {seed}: {r.time_to_first_s} s "
             f"at iteration {r.first_sat_iter}", q)
 
+    # ---- augmented-Lagrangian constraint weights: the weighted step kernel,
+    # and time to first with the same seeds as the fixed-lambda runs above
+    al = None
+    if not args.no_al:
+        from paper_2411_11833_amd.planner import al_solve
+        Wt = gp.empty(n, rows=gp.n_terms)
+        _, Tb, _ = gp.cost(X, n, terms=True)
+        gp.al_update(Tb, n, 0.0, torch.zeros_like(Wt), Wt)      # W = lambda: same cost, weighted kernel
+        gp.set_term_weights(Wt)
+        gp.seed_uniform(7, X, M, V, n)
+        for t in range(1, 11):
+            gp.step(X, M, V, n, t, adam, frozen=frozen)
+        e0.record(stream)
+        for t in range(11, 11 + reps):
+            gp.step(X, M, V, n, t, adam, frozen=frozen)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        w_kernel = e0.elapsed_time(e1) / 1e3 / reps
+        gp.set_term_weights(None)
+        runs = {"packing_8192": [], "single_pick_place_256": []}
+        for seed in (4242, 4243, 4244):
+            for key, g, nn in (("packing_8192", gp, n), ("single_pick_place_256", gs, 256)):
+                r = al_solve(g, nn, args.ttf_budget, seed=seed, rho=args.al_rho, outer=args.al_outer)
+                runs[key].append({"seed": seed, "first_sat_iter": r.first_sat_iter,
+                                  "time_to_first_s": r.time_to_first_s, "satisfied_at_end": r.n_satisfied})
+                log(f"[bench] augmented Lagrangian {key} seed {seed}: {r.time_to_first_s} s at iteration "
+                    f"{r.first_sat_iter}", q)
+        al = {"rho": args.al_rho, "outer_iters": args.al_outer,
+              "weighted_step_kernel_us": w_kernel * 1e6, "fixed_lambda_step_kernel_us": kernel_s * 1e6,
+              "time_to_first": runs,
+              "note": "plain method with per-particle multiplier-adjusted weights (mu <- max(0, mu + rho (J - eps)) "
+                      "every outer_iters iterations, W = lambda + mu); same seeds and budget as time_to_first"}
+
     # ---- motion cost: 16 interpolated waypoints per transition, 16384 particles
     motion = None
     if not args.no_motion:
@@ -621,6 +659,7 @@ def main():
         "feasibility": feas,
         "motion": motion,
         "self_collision": self_coll,
+        "augmented_lagrangian": al,
         "batch": batch,
         "compositional_init": sampling,
         "learned_seeds": learned,

@@ -282,6 +282,32 @@ int ct_feasibility(const ct_problem *problem, const float *terms, int64_t n, int
                    int32_t *counts, float *H, void *stream);
 
 /*
+ * Augmented-Lagrangian constraint weights (Sec. IV-B names augmented
+ * Lagrangians as an optimizer the method admits; Sec. "Limitations" proposes
+ * them to scale the costs dynamically instead of fixing lambda).
+ *
+ * ct_set_term_weights makes every later ct_cost / ct_cost_grad / ct_step /
+ * ct_optimize call on the handle use per-particle weights: particle i's cost
+ * is sum_c W[c][i] J_c (device W [n_terms][ld], read at each launch; the
+ * caller keeps it alive and may rewrite it between calls) instead of the
+ * fixed lambda_c of Eq. (2).  The call's ld must equal this ld
+ * (CT_ERR_INVALID_ARG otherwise).  Terms, masks and first_sat stay
+ * unweighted.  W = NULL restores lambda.  A change drops the captured loop of
+ * ct_optimize.  The many-skeleton calls (ct_batch_*) always use lambda.
+ *
+ * ct_al_update is the method-of-multipliers step between inner solves: with
+ * terms [n_terms][ld] as written by ct_cost and multipliers mu [n_terms][ld]
+ * (device, caller-owned, start at 0), for i < n and constraint c:
+ *   mu[c][i] = max(0, mu[c][i] + rho (J_c - eps_c))   (kept if J_c is NaN/inf)
+ *   W[c][i]  = lambda_c + mu[c][i]
+ * and W[c][i] = lambda_c for the soft costs (their mu rows are not touched).
+ * Requires rho >= 0 and finite.
+ */
+int ct_set_term_weights(ct_problem *problem, const float *W, int64_t ld);
+int ct_al_update(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, float rho, float *mu,
+                 float *W, void *stream);
+
+/*
  * Compositional initialization (Sec. V): the particles of a skeleton are
  * assembled from the solutions of smaller problems, one block of rows at a
  * time.  ct_compact writes the indices i < n with mask[i] != 0, in index

@@ -88,6 +88,8 @@ def _load() -> C.CDLL:
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
         "ct_feasibility": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
+        "ct_set_term_weights": (C.c_int, [vp, vp, i64]),
+        "ct_al_update": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
         "ct_compact": (C.c_int, [vp, i64, vp, vp, vp]),
         "ct_gather_block": (C.c_int, [vp, i64, i32, i64, vp, vp, vp, vp, vp, i64, i32, i64, vp]),
         "ct_batch_create": (C.c_int, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
@@ -227,6 +229,14 @@ def ct_autotune(h, X, n, ld, stream=0) -> int:
 
 def ct_feasibility(h, terms, n, ld, penalty, counts=None, H=None, stream=0):
     _chk(LIB.ct_feasibility(h, terms, n, ld, penalty, counts, H, stream), "ct_feasibility")
+
+
+def ct_set_term_weights(h, W, ld):
+    _chk(LIB.ct_set_term_weights(h, W, ld), "ct_set_term_weights")
+
+
+def ct_al_update(h, terms, n, ld, rho, mu, W, stream=0):
+    _chk(LIB.ct_al_update(h, terms, n, ld, rho, mu, W, stream), "ct_al_update")
 
 
 def ct_compact(mask, n, idx, count, stream=0):

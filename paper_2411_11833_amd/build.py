@@ -1,8 +1,9 @@
 """Build libcutamp.so (the C ABI of include/cutamp.h) for gfx950 with hipcc.
 
-The fused particle kernels are instantiated per lane split, with and without
-the self-collision pass, each in its own object (pk_instances.hip with
--DCT_SPLIT=s -DCT_SELF=0|1) so the objects compile in parallel;
+The fused particle kernels are instantiated per lane split, plain and
+extended (self-collision pass and per-particle term weights), each in its own
+object (pk_instances.hip with -DCT_SPLIT=s -DCT_EXT=0|1) so the objects
+compile in parallel;
 the host side (cutamp.hip) holds the C ABI and the small elementwise kernels,
 mlp.hip the seed proposer's matrix-core kernels and their C ABI.
 
@@ -59,10 +60,10 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     units = [(os.path.join(CSRC, "cutamp.hip"), os.path.join(obj_dir, "cutamp.o"), []),
              (os.path.join(CSRC, "mlp.hip"), os.path.join(obj_dir, "mlp.o"), [])]
     for split in SPLITS:
-        for self_coll in (0, 1):
+        for ext in (0, 1):
             units.append((os.path.join(CSRC, "pk_instances.hip"),
-                          os.path.join(obj_dir, f"pk_s{split}{'_self' if self_coll else ''}.o"),
-                          [f"-DCT_SPLIT={split}", f"-DCT_SELF={self_coll}"]))
+                          os.path.join(obj_dir, f"pk_s{split}{'_ext' if ext else ''}.o"),
+                          [f"-DCT_SPLIT={split}", f"-DCT_EXT={ext}"]))
     cmds = [[hipcc(), *HIPCC_FLAGS, *(extra or []), *inc, *defs, "-c", src, "-o", obj]
             for src, obj, defs in units]
     jobs = jobs or min(len(cmds), max(1, min(16, os.cpu_count() or 1)))

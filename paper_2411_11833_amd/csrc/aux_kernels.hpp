@@ -69,8 +69,10 @@ __global__ void counter_set_kernel(int32_t* c, int32_t v) { *c = v; }
 
 // Tolerance of constraint term c (per step: Kin position / rotation at the
 // pick and at the place, grasp box, placement, two joint-limit terms, three
-// collision terms; then the motion-collision terms).
+// collision terms; then the motion-collision terms, then the self-collision
+// terms).
 __device__ __forceinline__ float term_eps(const Tables* __restrict__ T, int c) {
+    if (T->self_term >= 0 && c >= T->self_term) return T->eps[E_SELF];
     if (c >= CT_TERMS_PER_STEP * T->K) return T->eps[E_MCOLL];
     switch (c % CT_TERMS_PER_STEP) {
         case T_PICK_POS: case T_PLACE_POS: return T->eps[E_KPOS];
@@ -79,6 +81,48 @@ __device__ __forceinline__ float term_eps(const Tables* __restrict__ T, int c) {
         case T_PLACE: return T->eps[E_PLACE];
         case T_JLIM_G: case T_JLIM_P: return T->eps[E_JLIM];
         default: return T->eps[E_COLL];
+    }
+}
+
+// Weight lambda of term c of Eq. (2), in the term order of term_eps followed
+// by the soft costs (goal, TrajLength).
+__device__ __forceinline__ float term_weight(const Tables* __restrict__ T, int c) {
+    if (c == T->goal_term) return T->w[W_GOAL];
+    if (c == T->traj_term) return T->w[W_TRAJ];
+    if (T->self_term >= 0 && c >= T->self_term) return T->w[W_SELF];
+    if (c >= CT_TERMS_PER_STEP * T->K) return T->w[W_MCOLL];
+    switch (c % CT_TERMS_PER_STEP) {
+        case T_PICK_POS: case T_PLACE_POS: return T->w[W_KPOS];
+        case T_PICK_ROT: case T_PLACE_ROT: return T->w[W_KROT];
+        case T_GRASP: return T->w[W_GRASP];
+        case T_PLACE: return T->w[W_PLACE];
+        case T_JLIM_G: case T_JLIM_P: return T->w[W_JLIM];
+        default: return T->w[W_COLL];
+    }
+}
+
+// Multiplier update of the augmented-Lagrangian mode for every particle i < n
+// and term c, arrays [n_terms][ld]: a constraint J_c <= eps_c is the
+// inequality g_c = J_c - eps_c <= 0, so mu_c <- max(0, mu_c + rho g_c) (kept
+// when J_c is not finite) and the term's weight becomes W_c = lambda_c + mu_c;
+// a soft cost keeps W_c = lambda_c.
+__global__ __launch_bounds__(256) void al_update_kernel(const Tables* __restrict__ T, const float* __restrict__ terms,
+                                                        int64_t n, int64_t ld, float rho, float* __restrict__ mu,
+                                                        float* __restrict__ W) {
+    const int64_t total = (int64_t)T->n_terms * n;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int c = (int)(idx / n);
+        const int64_t a = (int64_t)c * ld + (idx - (int64_t)c * n);
+        const float lam = term_weight(T, c);
+        if (c < T->n_constraint) {
+            const float J = terms[a];
+            float m = mu[a];
+            if (__builtin_isfinite(J)) m = fmaxf(0.f, fmaf(rho, J - term_eps(T, c), m));
+            mu[a] = m;
+            W[a] = lam + m;
+        } else {
+            W[a] = lam;
+        }
     }
 }
 

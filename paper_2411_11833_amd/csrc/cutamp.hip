@@ -22,12 +22,13 @@ struct GraphKey {
     uint8_t* mask = nullptr;
     int32_t* first_sat = nullptr;
     const uint8_t* frozen = nullptr;
+    const float* wts = nullptr;
     int64_t n = -1, ld = -1;
     int32_t iters = -1, split = -1, stop = -1;
     float lr = 0, b1 = 0, b2 = 0, eps = 0, gs = 0;
     bool operator==(const GraphKey& o) const {
         return X == o.X && M == o.M && V == o.V && cost == o.cost && mask == o.mask &&
-               first_sat == o.first_sat && frozen == o.frozen && n == o.n && ld == o.ld &&
+               first_sat == o.first_sat && frozen == o.frozen && wts == o.wts && n == o.n && ld == o.ld &&
                iters == o.iters && split == o.split && stop == o.stop && lr == o.lr && b1 == o.b1 && b2 == o.b2 &&
                eps == o.eps && gs == o.gs;
     }
@@ -46,6 +47,8 @@ struct ct_problem {
     int32_t* t_dev = nullptr;   // two-slot device counter of applied updates for captured loops,
                                 // followed by n_constraint per-constraint counts (feasibility)
     GraphKey key;
+    const float* wts = nullptr;  // per-particle term weights (ct_set_term_weights), or null
+    int64_t wts_ld = 0;
 };
 
 namespace {
@@ -149,29 +152,35 @@ bool valid_adam(const ct_adam* a) {
 
 PkFn pick_kernel(int split, int K, int mode, bool self) {
     switch (split) {
-        case 1: return self ? ct_pick_s1_self(K, mode) : ct_pick_s1(K, mode);
-        case 2: return self ? ct_pick_s2_self(K, mode) : ct_pick_s2(K, mode);
-        case 4: return self ? ct_pick_s4_self(K, mode) : ct_pick_s4(K, mode);
+        case 1: return self ? ct_pick_s1_ext(K, mode) : ct_pick_s1(K, mode);
+        case 2: return self ? ct_pick_s2_ext(K, mode) : ct_pick_s2(K, mode);
+        case 4: return self ? ct_pick_s4_ext(K, mode) : ct_pick_s4(K, mode);
         default: return nullptr;
     }
 }
 
 BatchFn pick_batch(int split, bool self) {
     switch (split) {
-        case 1: return self ? ct_batch_s1_self() : ct_batch_s1();
-        case 2: return self ? ct_batch_s2_self() : ct_batch_s2();
-        case 4: return self ? ct_batch_s4_self() : ct_batch_s4();
+        case 1: return self ? ct_batch_s1_ext() : ct_batch_s1();
+        case 2: return self ? ct_batch_s2_ext() : ct_batch_s2();
+        case 4: return self ? ct_batch_s4_ext() : ct_batch_s4();
         default: return nullptr;
     }
 }
 
 int effective_split(const ct_problem* P, int64_t n) { return P->split ? P->split : default_split(P->K, n); }
 
-int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0) {
+// One launch of the particle kernel for problem P.  `weighted`: apply the
+// problem's per-particle term weights if it has any (their ld must be the
+// call's); the many-skeleton reference launches pass false.
+int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int split = 0, bool weighted = true) {
     if (a.n == 0) return CT_OK;
-    PkFn f = pick_kernel(split ? split : effective_split(P, a.n), P->K, mode, P->h.self_on != 0);
+    PkArgs b = a;
+    b.wts = weighted ? P->wts : nullptr;
+    if (b.wts && P->wts_ld != a.ld) return CT_ERR_INVALID_ARG;
+    PkFn f = pick_kernel(split ? split : effective_split(P, a.n), P->K, mode, P->h.self_on || b.wts);
     if (!f) return CT_ERR_UNSUPPORTED;
-    return err_of(f(P->d, a, st));
+    return err_of(f(P->d, b, st));
 }
 
 void drop_graph(ct_problem* P) {
@@ -399,6 +408,28 @@ extern "C" int ct_problem_destroy(ct_problem* P) {
     return CT_OK;
 }
 
+extern "C" int ct_set_term_weights(ct_problem* P, const float* W, int64_t ld) {
+    if (!P) return CT_ERR_INVALID_ARG;
+    if (W && (ld <= 0 || !good_layout(W, 1, ld))) return CT_ERR_INVALID_ARG;
+    if (W != P->wts || (W && ld != P->wts_ld)) drop_graph(P);   // a captured loop holds the old pointer
+    P->wts = W;
+    P->wts_ld = W ? ld : 0;
+    return CT_OK;
+}
+
+extern "C" int ct_al_update(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float rho, float* mu,
+                            float* W, void* stream) {
+    if (empty_ok(P, n, ld) && std::isfinite(rho) && rho >= 0) return CT_OK;
+    if (!P || !terms || !mu || !W || !std::isfinite(rho) || rho < 0) return CT_ERR_INVALID_ARG;
+    if (!good_layout(terms, n, ld) || !good_layout(mu, n, ld) || !good_layout(W, n, ld)) return CT_ERR_INVALID_ARG;
+    if (n == 0) return CT_OK;
+    const int64_t total = (int64_t)P->n_terms * n;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(ct::al_update_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, P->d, terms, n, ld,
+                       rho, mu, W);
+    return err_of(hipGetLastError());
+}
+
 extern "C" int ct_feasibility(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float penalty,
                               int32_t* counts, float* H, void* stream) {
     if (!P || !std::isfinite(penalty)) return CT_ERR_INVALID_ARG;
@@ -539,7 +570,7 @@ extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t 
     if (n == 0 || iters == 0) return CT_OK;
     GraphKey key;
     key.X = X; key.M = M; key.V = V; key.cost = cost; key.mask = mask; key.first_sat = first_sat;
-    key.frozen = frozen; key.n = n; key.ld = ld; key.iters = iters;
+    key.frozen = frozen; key.wts = P->wts; key.n = n; key.ld = ld; key.iters = iters;
     key.split = effective_split(P, n);
     key.stop = stop_at_first ? 1 : 0;
     key.lr = adam->lr; key.b1 = adam->beta1; key.b2 = adam->beta2; key.eps = adam->eps;
@@ -730,7 +761,7 @@ int batch_launch(ct_batch* B, const ct_adam* adam, int32_t t, const int32_t* t_i
         p.X = k.X; p.M = k.M; p.V = k.V; p.cost = k.cost; p.mask = k.mask; p.first_sat = k.first_sat;
         p.frozen = k.frozen; p.n = k.n; p.ld = k.ld; p.a = a; p.a.gs = k.gscale; p.t = t; p.t_in = t_in;
         p.t_out = (s + 1 == B->probs.size()) ? t_out : nullptr;
-        const int rc = run_pk(B->probs[s], ct::MODE_STEP, p, st, batch_split(B));
+        const int rc = run_pk(B->probs[s], ct::MODE_STEP, p, st, batch_split(B), false);
         if (rc != CT_OK) return rc;
     }
     return CT_OK;

@@ -570,6 +570,43 @@ __device__ __forceinline__ void self_pass(const Tables* __restrict__ T, int si, 
     }
 }
 
+// Weights of the terms one slot evaluates: the problem's lambda of Eq. (2)
+// (uniform), or the particle's own row of a per-particle weight table
+// [n_terms][ld] (the multiplier-adjusted weights of the augmented-Lagrangian
+// mode; extended kernels only).  Fields a slot kind does not own stay unused.
+struct SlotW {
+    float kpos, krot, jlim, coll, mcoll, self, grasp, cobj, place, goal, traj;
+};
+
+__device__ __forceinline__ SlotW slot_weights(const Tables* __restrict__ T, const float* __restrict__ wts,
+                                              int64_t ld, int64_t i, int K, int slot, bool self_on) {
+    const float* w = T->w;
+    SlotW sw{w[W_KPOS], w[W_KROT], w[W_JLIM], w[W_COLL], w[W_MCOLL], w[W_SELF],
+             w[W_GRASP], w[W_COLL], w[W_PLACE], w[W_GOAL], w[W_TRAJ]};
+    if (wts) {
+        const int tb = CT_TERMS_PER_STEP * (slot >> 1);
+        const bool placing = slot & 1;
+        auto at = [&](int c) { return wts[(int64_t)c * ld + i]; };
+        sw.kpos = at(tb + (placing ? T_PLACE_POS : T_PICK_POS));
+        sw.krot = at(tb + (placing ? T_PLACE_ROT : T_PICK_ROT));
+        sw.jlim = at(tb + (placing ? T_JLIM_P : T_JLIM_G));
+        sw.coll = at(tb + (placing ? T_COLL_P : T_COLL_G));
+        if (!placing) {
+            sw.grasp = at(tb + T_GRASP);
+            sw.cobj = at(tb + T_COLL_OBJ);
+        } else {
+            sw.place = at(tb + T_PLACE);
+        }
+        if (T->W > 0) {
+            sw.mcoll = at(CT_TERMS_PER_STEP * K + slot);
+            sw.traj = at(T->traj_term);
+        }
+        if (self_on) sw.self = at(T->self_term + slot);
+        if (T->goal) sw.goal = at(T->goal_term);
+    }
+    return sw;
+}
+
 struct LaneOut {
     float cost;   // weighted sum of this slot's terms
     float traj;   // this slot's transition length (TrajLength share), 0 without motion
@@ -588,8 +625,8 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                                             float lam, const MoveCtx<KT>& mc, float gx, float gy, float gz,
                                             float g_c, float g_s, float rho_x, float rho_y, float rho_c,
                                             float rho_s, float& coll, float gq[CT_N_JOINTS], float gg[4],
-                                            float* __restrict__ gr, float& kin_pos, float& kin_rot, bool self,
-                                            float& self_pen) {
+                                            float* __restrict__ gr, float& kin_pos, float& kin_rot,
+                                            const SlotW* slw, bool self, float& self_pen) {
     const int k = mc.k;
     // Joint axis S_j = (z_j, o_j x z_j) of joint j+1 (z of frame j through its
     // origin).  dJ/dq_j = <S_j, wrench of links j+1..8>
@@ -672,7 +709,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
         const float sw = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
         kin_rot = atan2f(sw, 0.5f * (E00 + E11 + E22 - 1.f));
         if (GRAD) {
-            const float lp = T->w[W_KPOS], lr = T->w[W_KROT];
+            const float lp = slw ? slw->kpos : T->w[W_KPOS], lr = slw ? slw->krot : T->w[W_KROT];
             if (kin_pos > 0.f) {
                 const float sc = lp / kin_pos;
                 const float nx = ex * sc, ny = ey * sc, nz = ez * sc;
@@ -717,7 +754,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
             if (i + 1 < CT_N_JOINTS) joint_advance(T, i, jsn[i], jcs[i], Q, o);
         }
     }
-    if (self) self_pass<SPLIT, GRAD>(T, si, jsn, jcs, T->w[W_SELF], self_pen, gq);
+    if (self) self_pass<SPLIT, GRAD>(T, si, jsn, jcs, slw ? slw->self : T->w[W_SELF], self_pen, gq);
 }
 
 // ---------------------------------------------------------------------------
@@ -736,15 +773,21 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
 // Every lane writes its own gradient partials (no cross-lane reduction) to
 // part[0 .. 18+3K): [0,7) own q, [7,11) grasp, [11, 11+3K) placements
 // (accumulated in place), [11+3K, 18+3K) foreign q.
-template <int KT, int SPLIT, int MODE, bool SELF>
+template <int KT, int SPLIT, int MODE, bool EXT>
 __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
                                              int xs_stride, const float4* __restrict__ plc,
                                              const float4* __restrict__ osl, int K_rt, int slot, int si,
                                              float* __restrict__ part, float* __restrict__ terms,
-                                             int64_t term_ld, int64_t i_glob, bool write_terms) {
+                                             int64_t term_ld, int64_t i_glob, bool write_terms,
+                                             const float* __restrict__ wts) {
     constexpr bool GRAD = MODE != MODE_COST;
     const int K = KT ? KT : K_rt;
-    const bool self_on = SELF && T->self_on;   // wave-uniform; compiled out without SELF
+    const bool self_on = EXT && T->self_on;   // wave-uniform; compiled out without EXT
+    // per-particle weights only in extended kernels; plain kernels read lambda
+    // from the tables where each term needs it
+    SlotW swv;
+    if (EXT) swv = slot_weights(T, wts, term_ld, i_glob, K, slot, self_on);
+    const SlotW* sw = EXT ? &swv : nullptr;
     const int k = slot >> 1;
     const bool placing = slot & 1;
     auto X = [&](int d) { return xs[d * xs_stride]; };
@@ -806,9 +849,9 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         // the object is in the hand at both configurations of its step and
         // along the holding transition
         const bool held = key || placing;
-        const float lam = key ? T->w[W_COLL] : T->w[W_MCOLL];
+        const float lam = key ? (sw ? sw->coll : T->w[W_COLL]) : (sw ? sw->mcoll : T->w[W_MCOLL]);
         config_pass<KT, SPLIT, GRAD>(T, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
-                                     rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, key && self_on, selfc);
+                                     rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, sw, key && self_on, selfc);
         if (key) coll += cw; else coll_m += cw;
         if (GRAD) {
 #pragma unroll
@@ -829,7 +872,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         float gj[CT_N_JOINTS], qk[CT_N_JOINTS];
 #pragma unroll
         for (int j = 0; j < CT_N_JOINTS; ++j) qk[j] = qb(j);
-        jlim = bounds_dist<CT_N_JOINTS>(qk, T->q_lo, T->q_hi, T->w[W_JLIM], gj);
+        jlim = bounds_dist<CT_N_JOINTS>(qk, T->q_lo, T->q_hi, sw ? sw->jlim : T->w[W_JLIM], gj);
         if (GRAD) {
 #pragma unroll
             for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] += gj[j];
@@ -840,7 +883,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
             for (int j = 0; j < CT_N_JOINTS; ++j) ss += (qb(j) - qa(j)) * (qb(j) - qa(j));
             traj = sqrtf(ss);
             if (GRAD && traj > 0.f) {
-                const float sc = T->w[W_TRAJ] / traj;
+                const float sc = (sw ? sw->traj : T->w[W_TRAJ]) / traj;
 #pragma unroll
                 for (int j = 0; j < CT_N_JOINTS; ++j) {
                     gq[j] += sc * (qb(j) - qa(j));
@@ -851,12 +894,12 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     }
 
     float grasp = 0.f, coll_obj = 0.f, place = 0.f, goal = 0.f;
-    const float lc = T->w[W_COLL];
+    const float lc = sw ? sw->cobj : T->w[W_COLL];
     if (!placing) {
         if (si == 0) {
             const float gv[3] = {gx, gy, gz};
             float gb[3];
-            grasp = bounds_dist<3>(gv, T->grasp_lo[k], T->grasp_hi[k], T->w[W_GRASP], gb);
+            grasp = bounds_dist<3>(gv, T->grasp_lo[k], T->grasp_hi[k], sw ? sw->grasp : T->w[W_GRASP], gb);
             if (GRAD) { gg[0] += gb[0]; gg[1] += gb[1]; gg[2] += gb[2]; }
         }
         // CFreePlace: the object's spheres at its placement P(rho_k); the
@@ -874,7 +917,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         }
     } else if (si == 0) {
         // StablePlace containment: footprint corners inside the region
-        const float hx = T->obj0[k].hx, hy = T->obj0[k].hy, lpl = T->w[W_PLACE];
+        const float hx = T->obj0[k].hx, hy = T->obj0[k].hy, lpl = sw ? sw->place : T->w[W_PLACE];
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const float sx = (cc & 1) ? hx : -hx, sy = (cc & 2) ? hy : -hy;
@@ -890,7 +933,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         }
         if (slot == 1 && T->goal) {
             // MinimizeObjDist: sum of pairwise distances of the placements
-            const float lg = T->w[W_GOAL];
+            const float lg = sw ? sw->goal : T->w[W_GOAL];
             for (int a = 0; a < K; ++a)
                 for (int b = a + 1; b < K; ++b) {
                     const float dx = plc[a * xs_stride].x - plc[b * xs_stride].x;
@@ -914,7 +957,6 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     if (self_on) selfc = split_sum<SPLIT>(selfc);
 
     LaneOut out;
-    const float* w = T->w;
     const float* e = T->eps;
     float gsum = 0.f;
     if (GRAD) {
@@ -928,19 +970,22 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         for (int j = 0; j < 4; ++j) { part[7 + j] = gg[j]; gsum += gg[j]; }
         for (int j = 0; j < 3 * K; ++j) gsum += gr[j];
     }
-    float kw = w[W_KPOS] * kin_pos + w[W_KROT] * kin_rot + w[W_JLIM] * jlim + w[W_COLL] * coll +
-                     w[W_MCOLL] * coll_m + w[W_TRAJ] * traj;
+    const SlotW swc = sw ? *sw : SlotW{T->w[W_KPOS], T->w[W_KROT], T->w[W_JLIM], T->w[W_COLL], T->w[W_MCOLL],
+                                       T->w[W_SELF], T->w[W_GRASP], T->w[W_COLL], T->w[W_PLACE], T->w[W_GOAL],
+                                       T->w[W_TRAJ]};
+    float kw = swc.kpos * kin_pos + swc.krot * kin_rot + swc.jlim * jlim + swc.coll * coll + swc.mcoll * coll_m +
+               swc.traj * traj;
     bool ok = kin_pos <= e[E_KPOS] && kin_rot <= e[E_KROT] && jlim <= e[E_JLIM] && coll <= e[E_COLL] &&
               coll_m <= e[E_MCOLL];
     if (self_on) {
-        kw += w[W_SELF] * selfc;
+        kw += swc.self * selfc;
         ok = ok && selfc <= e[E_SELF];
     }
     if (!placing) {
-        out.cost = kw + w[W_GRASP] * grasp + w[W_COLL] * coll_obj;
+        out.cost = kw + swc.grasp * grasp + swc.cobj * coll_obj;
         ok = ok && grasp <= e[E_GRASP] && coll_obj <= e[E_COLL];
     } else {
-        out.cost = kw + w[W_PLACE] * place + w[W_GOAL] * goal;
+        out.cost = kw + swc.place * place + swc.goal * goal;
         ok = ok && place <= e[E_PLACE];
     }
     out.traj = traj;
@@ -1004,10 +1049,11 @@ struct TileIO {
     const float* gw;
     int64_t n, ld;
     float gscale;
+    const float* wts;   // per-particle term weights [n_terms][ld] (extended kernels), or null
 };
 
 
-template <int KT, int SPLIT, int MODE, bool SELF>
+template <int KT, int SPLIT, int MODE, bool EXT>
 __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<SPLIT>& sm, float lr, float b1,
                                          float b2, float eps, int32_t t) {
     const Tables* __restrict__ T = io.T;
@@ -1051,9 +1097,9 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
         if (slot < SLOTS) {
             const int64_t i = p0 + p;
             const bool wt = (MODE == MODE_COST) && io.terms != nullptr && i < n;
-            const LaneOut o = lane_slot<KT, SPLIT, MODE, SELF>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
+            const LaneOut o = lane_slot<KT, SPLIT, MODE, EXT>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
                                                      sm.part + (size_t)((p * SLOTS + slot) * SPLIT + si) * NP,
-                                                     io.terms, ld, i, wt);
+                                                     io.terms, ld, i, wt, i < n ? io.wts : nullptr);
             if (si == 0) {
                 sm.cpart[p * SLOTS + slot] = o.cost;
                 sm.tpart[p * SLOTS + slot] = o.traj;
@@ -1136,13 +1182,14 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
 
 // ---------------------------------------------------------------------------
 // One skeleton of KT steps: one workgroup per tile (XCD-aware tile order).
-template <int SPLIT, int MODE, int KT, bool SELF>
+template <int SPLIT, int MODE, int KT, bool EXT>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void particle_kernel(
     const Tables* __restrict__ T, float* __restrict__ X, float* __restrict__ M, float* __restrict__ V,
     float* __restrict__ G, float* __restrict__ cost, float* __restrict__ terms, uint8_t* __restrict__ mask,
     int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
     float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
-    int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw) {
+    int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw,
+    const float* __restrict__ wts) {
     __shared__ TileSmem<SPLIT> sm;
     // update number t: explicit, or one past the device counter of applied
     // updates; a captured loop alternates two counter slots (read t_in,
@@ -1157,8 +1204,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
     // 8 XCDs, so give each XCD a contiguous range of particle tiles; tiles
     // that share cache lines of X, M and V then share one L2
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale};
-    run_tile<KT, SPLIT, MODE, SELF>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
+    const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale, EXT ? wts : nullptr};
+    run_tile<KT, SPLIT, MODE, EXT>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
 }
 
 
@@ -1166,7 +1213,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
 // a fixed number of workgroups pull (skeleton, tile) items from a device
 // queue (items ordered by cost, largest first) until it is empty; the last
 // workgroup to leave resets the queue for the next launch.
-template <int SPLIT, bool SELF>
+template <int SPLIT, bool EXT>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void batch_kernel(const BatchSkel* __restrict__ skels,
                                                    const int2* __restrict__ items, int32_t n_items,
                                                    int32_t* __restrict__ queue, float lr, float b1, float b2,
@@ -1188,7 +1235,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void ba
         const BatchSkel& b = skels[w.x];
         const TileIO io{b.T, b.X, b.M, b.V, nullptr, b.cost, nullptr, b.mask, b.first_sat, b.frozen, nullptr,
                         b.n, b.ld, b.gscale};
-        run_tile<0, SPLIT, MODE_STEP, SELF>(io, (int64_t)w.y * tile_particles(b.T->K, SPLIT), sm, lr, b1, b2, eps, t);
+        run_tile<0, SPLIT, MODE_STEP, EXT>(io, (int64_t)w.y * tile_particles(b.T->K, SPLIT), sm, lr, b1, b2, eps, t);
         __syncthreads();
     }
     if (threadIdx.x == 0) {

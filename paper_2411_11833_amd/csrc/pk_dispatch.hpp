@@ -22,6 +22,7 @@ struct PkArgs {
     int32_t* t_out;          // receives t (the other counter slot), or null
     int32_t stop_at_first;   // skip the step if an earlier iteration satisfied
     const float* gw;         // per-particle gradient weights (gradient mode), or null
+    const float* wts;        // per-particle term weights [n_terms][ld] (extended kernels), or null
 };
 
 // one skeleton of a given length (each length has its own kernels)
@@ -42,16 +43,17 @@ struct BatchArgs {
 using BatchFn = hipError_t (*)(const BatchArgs&, hipStream_t);
 
 // defined in pk_instances.hip, compiled once per split (-DCT_SPLIT=1, 2, 4)
-// without (-DCT_SELF=0) and with (_self, -DCT_SELF=1) the self-collision pass
+// plain (-DCT_EXT=0) and extended (_ext, -DCT_EXT=1: the self-collision pass
+// and per-particle term weights compiled in)
 PkFn ct_pick_s1(int K, int mode);
 PkFn ct_pick_s2(int K, int mode);
 PkFn ct_pick_s4(int K, int mode);
-PkFn ct_pick_s1_self(int K, int mode);
-PkFn ct_pick_s2_self(int K, int mode);
-PkFn ct_pick_s4_self(int K, int mode);
+PkFn ct_pick_s1_ext(int K, int mode);
+PkFn ct_pick_s2_ext(int K, int mode);
+PkFn ct_pick_s4_ext(int K, int mode);
 BatchFn ct_batch_s1();
 BatchFn ct_batch_s2();
 BatchFn ct_batch_s4();
-BatchFn ct_batch_s1_self();
-BatchFn ct_batch_s2_self();
-BatchFn ct_batch_s4_self();
+BatchFn ct_batch_s1_ext();
+BatchFn ct_batch_s2_ext();
+BatchFn ct_batch_s4_ext();

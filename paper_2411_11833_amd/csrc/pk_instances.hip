@@ -1,14 +1,15 @@
-// Instantiations of the fused particle kernels for one lane split, with or
-// without the robot self-collision pass (compiled once per combination with
-// -DCT_SPLIT=<1|2|4> -DCT_SELF=<0|1>, so the objects build in parallel).
+// Instantiations of the fused particle kernels for one lane split, plain or
+// extended (the robot self-collision pass and per-particle term weights
+// compiled in), once per combination with -DCT_SPLIT=<1|2|4> -DCT_EXT=<0|1>,
+// so the objects build in parallel.
 #include "particle_kernel.hpp"
 #include "pk_dispatch.hpp"
 
 #ifndef CT_SPLIT
 #error "compile with -DCT_SPLIT=<lanes per configuration>"
 #endif
-#ifndef CT_SELF
-#error "compile with -DCT_SELF=<0|1> (self-collision pass compiled in)"
+#ifndef CT_EXT
+#error "compile with -DCT_EXT=<0|1> (extended kernels)"
 #endif
 
 namespace {
@@ -17,15 +18,15 @@ template <int S, int MODE, int K>
 hipError_t launch_pk(const ct::Tables* T, const PkArgs& g, hipStream_t st) {
     constexpr int P = ct::tile_particles(K, S);
     const dim3 grid((unsigned)((g.n + P - 1) / P));
-    hipLaunchKernelGGL((ct::particle_kernel<S, MODE, K, CT_SELF != 0>), grid, dim3(ct::WG), 0, st, T, g.X, g.M, g.V, g.G, g.cost,
+    hipLaunchKernelGGL((ct::particle_kernel<S, MODE, K, CT_EXT != 0>), grid, dim3(ct::WG), 0, st, T, g.X, g.M, g.V, g.G, g.cost,
                        g.terms, g.mask, g.first_sat, g.frozen, g.n, g.ld, g.a.lr, g.a.b1, g.a.b2, g.a.eps, g.a.gs,
-                       g.t, g.t_in, g.t_out, g.stop_at_first, g.gw);
+                       g.t, g.t_in, g.t_out, g.stop_at_first, g.gw, g.wts);
     return hipGetLastError();
 }
 
 template <int S>
 hipError_t launch_batch(const BatchArgs& g, hipStream_t st) {
-    hipLaunchKernelGGL((ct::batch_kernel<S, CT_SELF != 0>), dim3((unsigned)g.n_workgroups), dim3(ct::WG), 0, st,
+    hipLaunchKernelGGL((ct::batch_kernel<S, CT_EXT != 0>), dim3((unsigned)g.n_workgroups), dim3(ct::WG), 0, st,
                        static_cast<const ct::BatchSkel*>(g.skels), g.items, g.n_items, g.queue, g.a.lr, g.a.b1,
                        g.a.b2, g.a.eps, g.t, g.t_in, g.t_out);
     return hipGetLastError();
@@ -55,8 +56,8 @@ PkFn pick(int K, int mode) {
 
 #define CT_CAT2(a, b) a##b
 #define CT_CAT(a, b) CT_CAT2(a, b)
-#if CT_SELF
-#define CT_SUFFIX _self
+#if CT_EXT
+#define CT_SUFFIX _ext
 #else
 #define CT_SUFFIX
 #endif

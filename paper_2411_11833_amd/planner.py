@@ -86,6 +86,18 @@ class GpuProblem:
                          counts.data_ptr(), H.data_ptr(), _stream())
         return counts, H
 
+    def set_term_weights(self, W):
+        """Per-particle term weights [n_terms][ld] (device, kept alive by the
+        caller) for every later cost / gradient / step call, or None for the
+        fixed lambda of Eq. (2)."""
+        self._wts = W
+        B.ct_set_term_weights(self.handle, None if W is None else W.data_ptr(), 0 if W is None else W.shape[1])
+
+    def al_update(self, terms, n: int, rho: float, mu, W):
+        """Method-of-multipliers step on the constraint weights (device)."""
+        B.ct_al_update(self.handle, terms.data_ptr(), n, terms.shape[1], float(rho), mu.data_ptr(), W.data_ptr(),
+                       _stream())
+
     def cost_grad(self, X, n: int, weights=None):
         c = torch.empty(n, dtype=torch.float32, device=self.device)
         G = self.empty(n)
@@ -272,6 +284,59 @@ def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, 
         e.record(stream)
         events.append(e)
     torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    f = int(flag.item())
+    if f == INT32_MAX:
+        return SolveResult(iters, None, None, wall, int(mask.sum().item()))
+    ttf = start.elapsed_time(events[min(f // chunk, len(events) - 1)]) / 1e3
+    return SolveResult(iters, f, ttf, wall, int(mask.sum().item()))
+
+
+def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, outer: int = 50, chunk: int = 10,
+             adam: B.CtAdam | None = None, fixed_grasps: bool = True) -> SolveResult:
+    """The plain method with augmented-Lagrangian constraint weights: Adam on
+    sum_c W_c J_c per particle, where every `outer` iterations the
+    multipliers take one method-of-multipliers step from the particles'
+    current terms (mu <- max(0, mu + rho (J - eps)), W = lambda + mu).
+    Stops at the first satisfying particle (unweighted Eq. (3)) like
+    plain_solve; the weights start at lambda."""
+    adam = adam or default_adam(n)
+    frozen = grasp_frozen(gp.prob, gp.device) if fixed_grasps else None
+    X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
+    terms = gp.empty(n, rows=gp.n_terms)
+    mu = torch.zeros_like(terms)
+    W = torch.empty_like(terms)
+    cost = torch.empty(n, dtype=torch.float32, device=gp.device)
+    mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
+    flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=gp.device)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    gp.seed_uniform(seed, X, M, V, n)
+    gp.set_term_weights(None)
+    B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), terms.data_ptr(), None, _stream())
+    gp.al_update(terms, n, 0.0, mu, W)            # W = lambda
+    gp.set_term_weights(W)
+    events = []
+    done = 0
+    try:
+        while done < iters:
+            c = min(chunk, iters - done)
+            gp.optimize(X, M, V, n, done, c, adam, frozen=frozen, cost=cost, mask=mask, first_sat=flag,
+                        stop_at_first=True)
+            done += c
+            e = torch.cuda.Event(enable_timing=True)
+            e.record(stream)
+            events.append(e)
+            if done % outer == 0 and done < iters:
+                B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), terms.data_ptr(), None,
+                          _stream())
+                gp.al_update(terms, n, rho, mu, W)
+        torch.cuda.synchronize()
+    finally:
+        gp.set_term_weights(None)
     wall = time.perf_counter() - t_wall
     f = int(flag.item())
     if f == INT32_MAX:

@@ -147,3 +147,8 @@ def test_mlp_null_handles_rejected():
 
 def test_feasibility_rejects_bad_arguments():
     assert B.LIB.ct_feasibility(None, None, 0, 64, -1.0, None, None, None) == B.CT_ERR_INVALID_ARG
+
+
+def test_term_weight_calls_reject_bad_arguments():
+    assert B.LIB.ct_set_term_weights(None, None, 0) == B.CT_ERR_INVALID_ARG
+    assert B.LIB.ct_al_update(None, None, 0, 64, C.c_float(1.0), None, None, None) == B.CT_ERR_INVALID_ARG

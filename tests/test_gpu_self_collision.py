@@ -137,3 +137,24 @@ def test_self_batch_matches_per_skeleton_steps():
         torch.cuda.synchronize()
         assert torch.equal(X, b.X[s]) and torch.equal(M, b.M[s]) and torch.equal(V, b.V[s]), s
         assert torch.equal(c, b.cost[s]), s
+
+
+def test_self_feasibility_counts_use_the_self_tolerance():
+    """Eq. (5) counts with the self terms in the constraint set use the self
+    tolerance (0), not the motion terms' (1 mm) that precede them: a terms
+    table whose self rows hold 0 or 0.5 mm is counted like the oracle does."""
+    prob = I.packing(0, 0, n_objects=2, n_obstacles=2, waypoints=4)
+    prob.skeleton.self_collision = 1
+    gp = _gp(prob)
+    n = 256
+    rng = np.random.default_rng(37)
+    Th = rng.uniform(0.0, 0.002, (n, prob.n_terms)).astype(np.float32)
+    nc, ns = prob.n_constraint_terms, prob.n_self_terms
+    Th[:, nc - ns:nc] = np.where(rng.random((n, ns)) < 0.5, 0.0, 0.0005).astype(np.float32)
+    T = gp.empty(n, rows=prob.n_terms)
+    T[:, :n] = torch.from_numpy(np.ascontiguousarray(Th.T)).cuda()
+    counts, _ = gp.feasibility(T, n)
+    torch.cuda.synchronize()
+    co, _ = O.feasibility(prob, Th.astype(np.float64), -n)
+    np.testing.assert_array_equal(counts.cpu().numpy(), co)
+    np.testing.assert_array_equal(co[-ns:], (Th[:, nc - ns:nc] == 0).sum(0))

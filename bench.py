@@ -52,7 +52,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
 # dispatch, each scaled by what the same counter read for a 256 MiB device copy
 # in the same run (FETCH_SIZE reads half the bytes: factor 2.0; WRITE_SIZE 1.0).
 # Valid only for the kernel sources it was measured on (hash below).
-STEP_TRAFFIC = {"sources": "9692c4037280db0c", "fetch_kib": 4078.0, "fetch_factor": 2.0,
+STEP_TRAFFIC = {"sources": "8231cc2726c91000", "fetch_kib": 4084.8, "fetch_factor": 2.0,
                 "write_kib": 6539.0, "write_factor": 1.0}
 STEP_SOURCES = ("paper_2411_11833_amd/csrc/particle_kernel.hpp", "paper_2411_11833_amd/csrc/ct_tables.hpp",
                 "paper_2411_11833_amd/csrc/pk_instances.hip")

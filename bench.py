@@ -290,8 +290,42 @@ def learned_seeds(args, dev, n, q):
                          SD.collect(sc2, robot_seed=rs, n=1024, iters=1000, keep=64, proposer=prop,
                                     init_seed=5000 * r)),
         2, args.learned_steps, n, list(range(20000, 20000 + args.eval_scenes)), args.eval_budget, rs,
-        extra_eval=lambda prop: learned_compositional(args, dev, prop, n, lg))
+        extra_eval=lambda prop: {**learned_compositional(args, dev, prop, n, lg),
+                                 **({} if args.no_al else
+                                    {"learned_augmented_lagrangian": al_heldout(args, dev, n, lg, prop)})})
     return out
+
+
+def al_heldout(args, dev, n, lg, prop=None):
+    """The augmented-Lagrangian plain method on the held-out packing scenes
+    (budget --eval-budget), from uniform seeds or from the proposer's seeds
+    (seed inference timed)."""
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd.planner import GpuProblem, al_solve
+
+    scenes = list(range(20000, 20000 + args.eval_scenes))
+    first, times = [], []
+    for s in scenes:
+        prob = I.packing(args.robot_seed, s)
+        gp = GpuProblem(prob, dev)
+        seed = 4242 + s
+        init = None
+        if prop is not None:
+            pre = prop.prepare(prob)
+            init = lambda X, M, V: prop.seed(pre, seed, X, M, V, n)  # noqa: E731
+        al_solve(gp, n, 20, seed, rho=args.al_rho, outer=args.al_outer, init=init)    # captures the graphs
+        r = al_solve(gp, n, args.eval_budget, seed, rho=args.al_rho, outer=args.al_outer, init=init)
+        first.append(r.first_sat_iter)
+        times.append(r.time_to_first_s)
+        lg(f"augmented Lagrangian ({'learned' if prop else 'uniform'} seeds), scene {s}: first satisfying "
+           f"particle after {r.first_sat_iter} iterations, {r.time_to_first_s} s")
+        gp.close()
+    solved = [t for t in times if t is not None]
+    return {"seeds": "learned" if prop is not None else "uniform", "scenes": scenes, "particles": n,
+            "budget": args.eval_budget, "first_iter": first, "time_to_first_s": times,
+            "coverage": len(solved) / len(scenes),
+            "median_time_to_first_s": float(np.median(solved)) if solved else None,
+            "max_time_to_first_s": max(solved) if solved else None}
 
 
 def learned_compositional(args, dev, prop, n, lg):
@@ -471,7 +505,8 @@ def main():
                                   "time_to_first_s": r.time_to_first_s, "satisfied_at_end": r.n_satisfied})
                 log(f"[bench] augmented Lagrangian {key} seed {seed}: {r.time_to_first_s} s at iteration "
                     f"{r.first_sat_iter}", q)
-        al = {"rho": args.al_rho, "outer_iters": args.al_outer,
+        heldout = al_heldout(args, dev, n, lambda m: log("[bench] " + m, q))
+        al = {"rho": args.al_rho, "outer_iters": args.al_outer, "heldout_packing": heldout,
               "weighted_step_kernel_us": w_kernel * 1e6, "fixed_lambda_step_kernel_us": kernel_s * 1e6,
               "time_to_first": runs,
               "note": "plain method with per-particle multiplier-adjusted weights (mu <- max(0, mu + rho (J - eps)) "
@@ -627,6 +662,23 @@ def main():
             "speedup": (tu / tl) if (tu and tl) else None}
         log(f"[bench] packing, compositional init from uniform vs learned seeds: at satisfaction rate {rate:.2f} "
             f"{tu} s vs {tl} s", q)
+    if al is not None:
+        from paper_2411_11833_amd import seeds as SD
+        cmp = {}
+        pairs = [("compositional_uniform_seeds", sampling["time_to_first_s"] if sampling else None)]
+        if learned is not None and "learned_augmented_lagrangian" in learned["packing"]:
+            pairs.append(("augmented_lagrangian_learned_seeds",
+                          learned["packing"]["learned_augmented_lagrangian"]["time_to_first_s"]))
+        for name, other in pairs:
+            if other is None:
+                continue
+            cu, cl, rate, tu, tl = SD.equal_rate_times(al["heldout_packing"]["time_to_first_s"], other)
+            cmp[name] = {"coverage_augmented_lagrangian_uniform": cu, "coverage_other": cl,
+                         "equal_satisfaction_rate": rate, "time_augmented_lagrangian_uniform_s": tu,
+                         "time_other_s": tl}
+            log(f"[bench] packing, augmented Lagrangian (uniform seeds) vs {name}: at satisfaction rate {rate:.2f} "
+                f"{tu} s vs {tl} s", q)
+        al["heldout_equal_rate"] = cmp
 
     out = {
         "metric": METRIC,

@@ -293,13 +293,14 @@ def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, 
 
 
 def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, outer: int = 50, chunk: int = 10,
-             adam: B.CtAdam | None = None, fixed_grasps: bool = True) -> SolveResult:
+             adam: B.CtAdam | None = None, fixed_grasps: bool = True, init=None) -> SolveResult:
     """The plain method with augmented-Lagrangian constraint weights: Adam on
     sum_c W_c J_c per particle, where every `outer` iterations the
     multipliers take one method-of-multipliers step from the particles'
     current terms (mu <- max(0, mu + rho (J - eps)), W = lambda + mu).
     Stops at the first satisfying particle (unweighted Eq. (3)) like
-    plain_solve; the weights start at lambda."""
+    plain_solve; the weights start at lambda.  Uniform seeds, or
+    `init(X, M, V)` (timed with the solve)."""
     adam = adam or default_adam(n)
     frozen = grasp_frozen(gp.prob, gp.device) if fixed_grasps else None
     X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
@@ -314,7 +315,10 @@ def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, o
     t_wall = time.perf_counter()
     start = torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    gp.seed_uniform(seed, X, M, V, n)
+    if init is None:
+        gp.seed_uniform(seed, X, M, V, n)
+    else:
+        init(X, M, V)
     gp.set_term_weights(None)
     B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), terms.data_ptr(), None, _stream())
     gp.al_update(terms, n, 0.0, mu, W)            # W = lambda

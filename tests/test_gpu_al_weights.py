@@ -164,3 +164,33 @@ def test_al_weights_reach_a_satisfying_particle_sooner_than_fixed_weights():
         print(f"seed {seed}: fixed lambda {r_fixed.first_sat_iter}, multipliers {r_al.first_sat_iter}")
         assert r_al.first_sat_iter is not None
         assert r_fixed.first_sat_iter is None or r_al.first_sat_iter < r_fixed.first_sat_iter
+
+
+def test_many_skeleton_calls_use_lambda_even_with_weights_set():
+    """A weight table set on a problem does not reach the many-skeleton
+    launches (persistent or one launch per skeleton): results are bit-equal
+    to the same batch without it."""
+    from paper_2411_11833_amd.planner import GpuBatch
+    robot = I.make_robot(0, n_spheres=60)
+    probs = [I.random_skeleton_problem(s, robot) for s in (1, 2)]
+    sizes = [131, 64]
+    outs = []
+    for weighted in (False, True):
+        for persistent in (True, False):
+            b = GpuBatch(probs, sizes)
+            keep = []
+            if weighted:
+                for g, n in zip(b.gps, sizes):
+                    W = g.empty(n, rows=g.n_terms).fill_(3.0)
+                    keep.append(W)
+                    g.set_term_weights(W)
+            b.set_tuning(split=1, workgroups=0, persistent=persistent)
+            b.seed(9)
+            b.optimize(0, 6, _adam(1))
+            torch.cuda.synchronize()
+            outs.append([x.clone() for x in b.X])
+            for g in b.gps:
+                g.set_term_weights(None)
+    for o in outs[1:]:
+        for u, v in zip(outs[0], o):
+            assert torch.equal(u, v)

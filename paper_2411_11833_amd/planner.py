@@ -300,7 +300,10 @@ def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, o
     current terms (mu <- max(0, mu + rho (J - eps)), W = lambda + mu).
     Stops at the first satisfying particle (unweighted Eq. (3)) like
     plain_solve; the weights start at lambda.  Uniform seeds, or
-    `init(X, M, V)` (timed with the solve)."""
+    `init(X, M, V)` (timed with the solve).  `outer` must be a multiple of
+    `chunk` (the multipliers move between captured chunks)."""
+    if outer <= 0 or chunk <= 0 or outer % chunk:
+        raise ValueError(f"outer ({outer}) must be a positive multiple of chunk ({chunk})")
     adam = adam or default_adam(n)
     frozen = grasp_frozen(gp.prob, gp.device) if fixed_grasps else None
     X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)

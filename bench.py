@@ -725,7 +725,7 @@ def main():
             "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
             "traffic": step_traffic_bytes() if (split == 2 and n == 8192) else None,
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": f"ct::particle_kernel<{split},MODE_STEP,4>",
+            "kernel": f"ct::particle_kernel<{split},MODE_STEP,4,false>",
             "kernel_us": kernel_s * 1e6,
             "flop_per_particle_iter": wk.flops,
             "algorithmic_bytes_per_launch": wk.bytes * n,

@@ -25,6 +25,10 @@ Also reported on the same JSON line:
     method's converged particles, then time to the first satisfying particle
     on held-out single pick-place and packing scenes, for packing also as
     the starting points of compositional initialization;
+  * the time-to-satisfy half of the metric in one place
+    (`time_to_satisfy_learned_vs_uniform`): learned vs uniform seeds at their
+    common satisfaction rate, single pick-place with fixed weights and
+    packing with augmented-Lagrangian weights;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -680,6 +684,22 @@ def main():
                 f"{tu} s vs {tl} s", q)
         al["heldout_equal_rate"] = cmp
 
+    # the time-to-satisfy half of the metric in one place: learned vs uniform
+    # seeds at their common satisfaction rate on the held-out scenes
+    tts = {}
+    if learned is not None:
+        sp = learned["single_pick_place"]
+        tts["single_pick_place_fixed_lambda"] = {
+            "rate": sp["equal_satisfaction_rate"], "uniform_s": sp["time_at_equal_rate_uniform_s"],
+            "learned_s": sp["time_at_equal_rate_learned_s"]}
+        if al is not None and "augmented_lagrangian_learned_seeds" in al.get("heldout_equal_rate", {}):
+            c = al["heldout_equal_rate"]["augmented_lagrangian_learned_seeds"]
+            tts["packing_augmented_lagrangian"] = {
+                "rate": c["equal_satisfaction_rate"], "uniform_s": c["time_augmented_lagrangian_uniform_s"],
+                "learned_s": c["time_other_s"]}
+        for v in tts.values():
+            v["speedup"] = (v["uniform_s"] / v["learned_s"]) if (v["uniform_s"] and v["learned_s"]) else None
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -715,6 +735,7 @@ def main():
         "batch": batch,
         "compositional_init": sampling,
         "learned_seeds": learned,
+        "time_to_satisfy_learned_vs_uniform": tts or None,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,

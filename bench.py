@@ -300,17 +300,20 @@ def learned_seeds(args, dev, n, q):
     return out
 
 
-def al_heldout(args, dev, n, lg, prop=None):
+def al_heldout(args, dev, n, lg, prop=None, self_collision=False, budget=None):
     """The augmented-Lagrangian plain method on the held-out packing scenes
-    (budget --eval-budget), from uniform seeds or from the proposer's seeds
-    (seed inference timed)."""
+    (budget --eval-budget unless given), from uniform seeds or from the
+    proposer's seeds (seed inference timed), optionally with the robot
+    self-collision constraint on."""
     from paper_2411_11833_amd import inputs as I
     from paper_2411_11833_amd.planner import GpuProblem, al_solve
 
     scenes = list(range(20000, 20000 + args.eval_scenes))
     first, times = [], []
+    budget = budget or args.eval_budget
     for s in scenes:
         prob = I.packing(args.robot_seed, s)
+        prob.skeleton.self_collision = int(self_collision)
         gp = GpuProblem(prob, dev)
         seed = 4242 + s
         init = None
@@ -318,15 +321,16 @@ def al_heldout(args, dev, n, lg, prop=None):
             pre = prop.prepare(prob)
             init = lambda X, M, V: prop.seed(pre, seed, X, M, V, n)  # noqa: E731
         al_solve(gp, n, 20, seed, rho=args.al_rho, outer=args.al_outer, init=init)    # captures the graphs
-        r = al_solve(gp, n, args.eval_budget, seed, rho=args.al_rho, outer=args.al_outer, init=init)
+        r = al_solve(gp, n, budget, seed, rho=args.al_rho, outer=args.al_outer, init=init)
         first.append(r.first_sat_iter)
         times.append(r.time_to_first_s)
-        lg(f"augmented Lagrangian ({'learned' if prop else 'uniform'} seeds), scene {s}: first satisfying "
+        lg(f"augmented Lagrangian ({'learned' if prop else 'uniform'} seeds"
+           f"{', self-collision on' if self_collision else ''}), scene {s}: first satisfying "
            f"particle after {r.first_sat_iter} iterations, {r.time_to_first_s} s")
         gp.close()
     solved = [t for t in times if t is not None]
-    return {"seeds": "learned" if prop is not None else "uniform", "scenes": scenes, "particles": n,
-            "budget": args.eval_budget, "first_iter": first, "time_to_first_s": times,
+    return {"seeds": "learned" if prop is not None else "uniform", "self_collision": bool(self_collision),
+            "scenes": scenes, "particles": n, "budget": budget, "first_iter": first, "time_to_first_s": times,
             "coverage": len(solved) / len(scenes),
             "median_time_to_first_s": float(np.median(solved)) if solved else None,
             "max_time_to_first_s": max(solved) if solved else None}
@@ -603,6 +607,10 @@ def main():
             "penetrating_fraction_uniform_seeds": before,
             f"penetrating_fraction_after_{iters}_iters": after,
         }
+        if not args.no_al:
+            self_coll["augmented_lagrangian_heldout"] = al_heldout(
+                args, dev, n, lambda m: log("[bench] " + m, q), self_collision=True,
+                budget=max(args.eval_budget, 3000))
         log(f"[bench] self-collision on: step kernel {s_kernel * 1e6:.1f} us "
             f"({100 * (s_kernel / kernel_s - 1):+.1f}% vs off); particles with self-penetration "
             f"{before:.3f} -> {after:.3f} after {iters} iterations", q)

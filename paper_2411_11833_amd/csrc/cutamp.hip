@@ -44,6 +44,7 @@ struct ct_problem {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipEvent_t replayed = nullptr;   // recorded after every replay of gexec on the caller's stream
     int32_t* t_dev = nullptr;   // two-slot device counter of applied updates for captured loops,
                                 // followed by n_constraint per-constraint counts (feasibility)
     GraphKey key;
@@ -183,7 +184,13 @@ int run_pk(const ct_problem* P, int mode, const PkArgs& a, hipStream_t st, int s
     return err_of(f(P->d, b, st));
 }
 
+// A graph exec must not be destroyed while a replay of it is still queued or
+// running: its kernel-argument storage is released with it, and the queued
+// dispatches (and a profiler's completion handler reading them) would then
+// touch freed memory.  Every replay records `replayed` on the caller's
+// stream; dropping the graph first waits for that event.
 void drop_graph(ct_problem* P) {
+    if (P->gexec && P->replayed) hipEventSynchronize(P->replayed);
     if (P->gexec) hipGraphExecDestroy(P->gexec);
     if (P->graph) hipGraphDestroy(P->graph);
     P->gexec = nullptr;
@@ -400,7 +407,10 @@ extern "C" int ct_problem_create(const ct_robot* robot, const ct_scene* scene, c
 
 extern "C" int ct_problem_destroy(ct_problem* P) {
     if (!P) return CT_OK;
+    // eager launches on any stream may still read the tables and counters
+    hipDeviceSynchronize();
     drop_graph(P);
+    if (P->replayed) hipEventDestroy(P->replayed);
     if (P->capture_stream) hipStreamDestroy(P->capture_stream);
     if (P->d) hipFree(P->d);
     if (P->t_dev) hipFree(P->t_dev);
@@ -603,10 +613,16 @@ extern "C" int ct_optimize(ct_problem* P, float* X, float* M, float* V, int64_t 
         P->gexec = ge;
         P->key = key;
     }
+    if (!P->replayed && hipEventCreateWithFlags(&P->replayed, hipEventDisableTiming) != hipSuccess) {
+        P->replayed = nullptr;
+        return CT_ERR_DEVICE;
+    }
     hipLaunchKernelGGL(ct::counter_set_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, P->t_dev, (int32_t)t0);
-    const int rc = err_of(hipGetLastError());
+    int rc = err_of(hipGetLastError());
     if (rc != CT_OK) return rc;
-    return err_of(hipGraphLaunch(P->gexec, (hipStream_t)stream));
+    rc = err_of(hipGraphLaunch(P->gexec, (hipStream_t)stream));
+    if (rc != CT_OK) return rc;
+    return err_of(hipEventRecord(P->replayed, (hipStream_t)stream));
 }
 
 extern "C" int ct_set_split(ct_problem* P, int32_t split) {
@@ -690,6 +706,7 @@ struct ct_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipEvent_t replayed = nullptr;   // recorded after every replay of gexec (see drop_graph)
     int32_t g_iters = -1, g_split = -1, g_wg = -1, g_pers = -1;
     float g_lr = 0, g_b1 = 0, g_b2 = 0, g_eps = 0;
 };
@@ -697,6 +714,7 @@ struct ct_batch {
 namespace {
 
 void batch_drop_graph(ct_batch* B) {
+    if (B->gexec && B->replayed) hipEventSynchronize(B->replayed);
     if (B->gexec) hipGraphExecDestroy(B->gexec);
     if (B->graph) hipGraphDestroy(B->graph);
     B->gexec = nullptr;
@@ -822,7 +840,9 @@ extern "C" int ct_batch_create(int32_t count, ct_problem* const* problems, float
 
 extern "C" int ct_batch_destroy(ct_batch* B) {
     if (!B) return CT_OK;
+    hipDeviceSynchronize();   // eager launches may still read the work list and queue
     batch_drop_graph(B);
+    if (B->replayed) hipEventDestroy(B->replayed);
     if (B->capture_stream) hipStreamDestroy(B->capture_stream);
     if (B->d_skels) hipFree(B->d_skels);
     if (B->d_items) hipFree(B->d_items);
@@ -881,10 +901,16 @@ extern "C" int ct_batch_optimize(ct_batch* B, int64_t t0, int32_t iters, const c
         B->g_pers = B->persistent;
         B->g_lr = adam->lr; B->g_b1 = adam->beta1; B->g_b2 = adam->beta2; B->g_eps = adam->eps;
     }
+    if (!B->replayed && hipEventCreateWithFlags(&B->replayed, hipEventDisableTiming) != hipSuccess) {
+        B->replayed = nullptr;
+        return CT_ERR_DEVICE;
+    }
     hipLaunchKernelGGL(ct::counter_set_kernel, dim3(1), dim3(1), 0, (hipStream_t)stream, B->t_dev, (int32_t)t0);
-    const int rc = err_of(hipGetLastError());
+    int rc = err_of(hipGetLastError());
     if (rc != CT_OK) return rc;
-    return err_of(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+    rc = err_of(hipGraphLaunch(B->gexec, (hipStream_t)stream));
+    if (rc != CT_OK) return rc;
+    return err_of(hipEventRecord(B->replayed, (hipStream_t)stream));
 }
 
 extern "C" int ct_batch_autotune(ct_batch* B, int32_t* chosen, void* stream) {

@@ -297,6 +297,7 @@ int ct_mlp_create(const ct_mlp_shape* shape, ct_mlp** out) {
 
 int ct_mlp_destroy(ct_mlp* mlp) {
     if (!mlp) return CT_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();   // launches on any stream may still use the buffers
     delete mlp;
     return CT_OK;
 }

@@ -162,7 +162,9 @@ int ct_problem_create(const ct_robot *robot, const ct_scene *scene, const ct_ske
                       const ct_weights *weights, const ct_tolerances *tolerances,
                       ct_problem **out);
 
-/* Release a handle and its device tables (NULL is accepted). */
+/* Release a handle and its device tables (NULL is accepted).  Waits for the
+ * device to finish (launches on any stream may still read the tables) and
+ * for every replay of the handle's captured loop before releasing it. */
 int ct_problem_destroy(ct_problem *problem);
 
 /*
@@ -247,7 +249,10 @@ int ct_step(const ct_problem *problem, float *X, float *M, float *V, int64_t n, 
  * stop_at_first != 0 (first_sat required), a step whose predecessors already
  * produced a satisfying particle does nothing, so a whole iteration budget
  * can be enqueued at once and still stops at the first solution
- * (Sec. IV-B, stopping criterion).
+ * (Sec. IV-B, stopping criterion); in that mode a particle the step finds
+ * satisfying is not updated, so after the stop the rows of X whose mask is 1
+ * are exactly the satisfying iterates (the other rows took that step's
+ * update).
  */
 int ct_optimize(ct_problem *problem, float *X, float *M, float *V, int64_t n, int64_t ld,
                 int64_t t0, int32_t iters, const ct_adam *adam, const uint8_t *frozen,
@@ -343,6 +348,8 @@ int ct_batch_create(int32_t count, ct_problem *const *problems, float *const *X,
                     float *const *V, const int64_t *n, const int64_t *ld, float *const *cost,
                     uint8_t *const *mask, int32_t *const *first_sat, const uint8_t *const *frozen,
                     ct_batch **out);
+/* Release a batch (NULL is accepted); waits for the device first, like
+ * ct_problem_destroy.  The problems it was built from stay valid. */
 int ct_batch_destroy(ct_batch *batch);
 
 /*
@@ -407,6 +414,7 @@ typedef struct ct_mlp_shape {
 
 /* Allocate a handle (weights zero until ct_mlp_set_params). */
 int ct_mlp_create(const ct_mlp_shape *shape, ct_mlp **out);
+/* Release the handle and its buffers; waits for the device first. */
 int ct_mlp_destroy(ct_mlp *mlp);
 int ct_mlp_info(const ct_mlp *mlp, int64_t *n_params);
 

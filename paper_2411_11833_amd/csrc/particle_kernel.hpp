@@ -1050,6 +1050,7 @@ struct TileIO {
     int64_t n, ld;
     float gscale;
     const float* wts;   // per-particle term weights [n_terms][ld] (extended kernels), or null
+    int keep_sat = 0;   // stop-at-first: a satisfying particle is not updated, so X keeps it
 };
 
 
@@ -1121,7 +1122,9 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
         }
         ok &= __builtin_isfinite(J) ? 1 : 0;
         m &= __builtin_isfinite(J) ? 1 : 0;
-        sm.okp[tid] = ok;
+        // the solution returned on stop is the satisfying iterate itself
+        // (the pre-update x the mask describes), so it keeps its value
+        sm.okp[tid] = ok & (io.keep_sat ? 1 - m : 1);
         if (i < n) {
             if (MODE == MODE_COST && io.terms && T->traj_term >= 0) {
                 float tl = 0.f;
@@ -1204,7 +1207,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
     // 8 XCDs, so give each XCD a contiguous range of particle tiles; tiles
     // that share cache lines of X, M and V then share one L2
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale, EXT ? wts : nullptr};
+    const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale, EXT ? wts : nullptr,
+                    stop_at_first ? 1 : 0};
     run_tile<KT, SPLIT, MODE, EXT>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
 }
 

@@ -12,6 +12,8 @@ from __future__ import annotations
 import time
 from dataclasses import dataclass
 
+import numpy as np
+
 import torch
 
 from . import binding as B
@@ -243,6 +245,8 @@ class SolveResult:
                                     # chunk of iterations that produced the first satisfying particle
     wall_s: float                   # host wall clock of the whole call
     n_satisfied: int                # satisfying particles at the last executed iterate
+    solution: np.ndarray | None = None   # [n_satisfied, D] the satisfying particles (rows of X whose
+                                         # mask is 1 after a stop at the first satisfying iterate)
 
 
 INT32_MAX = 2 ** 31 - 1
@@ -285,11 +289,16 @@ def plain_solve(gp: GpuProblem, n: int, iters: int, seed: int, chunk: int = 10, 
         events.append(e)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
+    return _result(gp, X, mask, n, flag, iters, wall, start, events, chunk, stop_at_first)
+
+
+def _result(gp, X, mask, n, flag, iters, wall, start, events, chunk, stopped) -> SolveResult:
     f = int(flag.item())
     if f == INT32_MAX:
         return SolveResult(iters, None, None, wall, int(mask.sum().item()))
     ttf = start.elapsed_time(events[min(f // chunk, len(events) - 1)]) / 1e3
-    return SolveResult(iters, f, ttf, wall, int(mask.sum().item()))
+    sol = gp.to_rows(X, n)[mask[:n].bool()].cpu().numpy() if stopped else None
+    return SolveResult(iters, f, ttf, wall, int(mask.sum().item()), sol)
 
 
 def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, outer: int = 50, chunk: int = 10,
@@ -345,8 +354,4 @@ def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, o
     finally:
         gp.set_term_weights(None)
     wall = time.perf_counter() - t_wall
-    f = int(flag.item())
-    if f == INT32_MAX:
-        return SolveResult(iters, None, None, wall, int(mask.sum().item()))
-    ttf = start.elapsed_time(events[min(f // chunk, len(events) - 1)]) / 1e3
-    return SolveResult(iters, f, ttf, wall, int(mask.sum().item()))
+    return _result(gp, X, mask, n, flag, iters, wall, start, events, chunk, True)

@@ -141,8 +141,9 @@ class CompositionalInit:
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(stream)
             if bool(mask[:n].any().item()):
-                return SolveResult(done, done, start.elapsed_time(ev) / 1e3, time.perf_counter() - t_wall,
-                                   int(mask[:n].sum().item()))
+                wall = time.perf_counter() - t_wall
+                sol = gp.to_rows(X, n)[mask[:n].bool()].cpu().numpy()
+                return SolveResult(done, done, start.elapsed_time(ev) / 1e3, wall, int(mask[:n].sum().item()), sol)
         # refine the last composition
         adam = default_adam(n)
         frozen = grasp_frozen(gp.prob, gp.device)
@@ -163,4 +164,5 @@ class CompositionalInit:
         if f == INT32_MAX:
             return SolveResult(max_iters + refine_budget, None, None, wall, int(mask.sum().item()))
         ttf = start.elapsed_time(events[min(f // refine_chunk, len(events) - 1)]) / 1e3
-        return SolveResult(max_iters + refine_budget, max_iters + f, ttf, wall, int(mask.sum().item()))
+        sol = gp.to_rows(X, n)[mask[:n].bool()].cpu().numpy()
+        return SolveResult(max_iters + refine_budget, max_iters + f, ttf, wall, int(mask.sum().item()), sol)

@@ -76,6 +76,25 @@ def _check_cost_terms_mask(prob, gp, X, split=None):
     return c, T, m
 
 
+def _check_solution(prob, sol):
+    """Eq. (3) on particles the GPU reported satisfying, evaluated by the
+    oracle: a particle outside the mask band satisfies every constraint
+    exactly; one inside it (a term within 1e-4 of its tolerance, which a
+    particle that has just crossed one often is) satisfies every constraint
+    up to the term parity tolerance."""
+    assert sol is not None and sol.shape[0] > 0
+    X64 = sol.astype(np.float64)
+    To = O.terms(prob, X64)
+    eps = O.tolerance_vector(prob)
+    nc = len(eps)
+    slack = 1e-4 * np.abs(To[:, :nc]) + 2e-6
+    assert np.all(To[:, :nc] <= eps + slack), "a reported solution violates a constraint beyond the term tolerance"
+    flip, _ = O.margins(prob, X64)
+    outside = flip.min(1) > 1e-4
+    assert np.all(O.mask(prob, To)[outside]), "a reported solution outside the mask band fails Eq. (3)"
+    return int(outside.sum())
+
+
 @pytest.mark.parametrize("case,n", [("single", 256), ("packing", 200), ("packing3", 131), ("six_steps", 45)])
 def test_cost_terms_mask(case, n):
     prob = CASES[case]()
@@ -315,7 +334,10 @@ def test_first_satisfying_iteration_matches_masks():
 
 def test_stop_at_first_freezes_the_batch():
     """With stop_at_first the steps after the first satisfying iteration do
-    nothing: the state equals an eager run stopped right after that step."""
+    nothing, and that iteration's step leaves its satisfying particles as they
+    were: the state equals an eager run stopped right after that step, except
+    that the rows its mask marks keep their values (x, m and v) from before
+    it."""
     from paper_2411_11833_amd.planner import grasp_frozen
     prob = CASES["single"]()
     gp = _gp(prob)
@@ -331,10 +353,17 @@ def test_stop_at_first_freezes_the_batch():
     f = int(flag.item())
     assert f < 3000, "no satisfying particle within the budget"
     Xe, Me, Ve = X0.clone(), M0.clone(), V0.clone()
-    for t in range(1, f + 2):
+    for t in range(1, f + 1):
         gp.step(Xe, Me, Ve, n, t, _adam(n), frozen=fz)
+    before = (Xe.clone(), Me.clone(), Ve.clone())
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda")
+    gp.step(Xe, Me, Ve, n, f + 1, _adam(n), frozen=fz, mask=mask)
     torch.cuda.synchronize()
-    assert torch.equal(X, Xe) and torch.equal(M, Me) and torch.equal(V, Ve)
+    sat = torch.cat([mask.bool(), torch.zeros(Xe.shape[1] - n, dtype=torch.bool, device="cuda")])
+    assert bool(sat.any())
+    for got, after, prev in zip((X, M, V), (Xe, Me, Ve), before):
+        want = torch.where(sat[None, :], prev, after)
+        assert torch.equal(got, want)
 
 
 # ----------------------------------------------------------------------------- motion cost
@@ -590,7 +619,29 @@ def test_compositional_init_solves_packing_where_uniform_does_not():
     print("uniform", ru.first_sat_iter, "composed", rc.first_sat_iter, rc.time_to_first_s)
     assert ru.first_sat_iter is None
     assert rc.first_sat_iter is not None
+    assert rc.solution.shape[0] == rc.n_satisfied
+    print("composed solutions outside the mask band:", _check_solution(prob, rc.solution), "of", rc.n_satisfied)
     ci.close()
+
+
+@pytest.mark.parametrize("solver", ["plain", "weighted"])
+def test_stop_at_first_returns_the_satisfying_iterate(solver):
+    """Sec. IV-B stops at the first satisfying particle: with stop-at-first
+    the step that finds it leaves it un-updated, so the rows of X whose mask
+    is 1 after the solve are the iterates the mask certified; the oracle's
+    Eq. (3) agrees on them."""
+    from paper_2411_11833_amd.planner import al_solve, default_adam, plain_solve
+    prob = I.single_pick_place(0, 0)
+    gp = _gp(prob)
+    n = 256
+    if solver == "plain":
+        r = plain_solve(gp, n, 3000, seed=4242, adam=default_adam(n))
+    else:
+        r = al_solve(gp, n, 3000, seed=4242, adam=default_adam(n))
+    assert r.first_sat_iter is not None
+    assert r.solution.shape == (r.n_satisfied, I.STEP_DIM)
+    k = _check_solution(prob, r.solution)
+    print(solver, "first satisfying iteration", r.first_sat_iter, "solutions", r.n_satisfied, "outside band", k)
 
 
 def test_seed_from_hands_each_step_block_to_its_one_step_problem():

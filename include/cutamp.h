@@ -287,6 +287,25 @@ int ct_feasibility(const ct_problem *problem, const float *terms, int64_t n, int
                    int32_t *counts, float *H, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * heuristic as ct_feasibility (same kernels, identical H), with the
+ * per-constraint counts kept in a static device array of CT_FEAS_SCRATCH_MAX
+ * int32 per GPU instead of a caller buffer or the handle.  The call never
+ * allocates or frees memory; the first call on a device looks the array's
+ * address up once.  H (device float) is required; the counts stay internal.
+ * Every call on one GPU shares that array, which keeps the last call's
+ * counts: calls that overlap on one GPU (different streams or threads
+ * without ordering) race and may return a wrong H.
+ * Errors: CT_ERR_INVALID_ARG as ct_feasibility (and H == NULL);
+ * CT_ERR_UNSUPPORTED when the problem has more than CT_FEAS_SCRATCH_MAX
+ * constraint terms (at most 90 for the skeletons this library builds).
+ */
+#define CT_FEAS_SCRATCH_MAX 128
+int ct_feasibility_noalloc(const ct_problem *problem, const float *terms, int64_t n, int64_t ld,
+                           float penalty, float *H, void *stream);
+
+/*
  * Augmented-Lagrangian constraint weights (Sec. IV-B names augmented
  * Lagrangians as an optimizer the method admits; Sec. "Limitations" proposes
  * them to scale the costs dynamically instead of fixing lambda).

@@ -88,6 +88,7 @@ def _load() -> C.CDLL:
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
         "ct_feasibility": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
+        "ct_feasibility_noalloc": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp]),
         "ct_set_term_weights": (C.c_int, [vp, vp, i64]),
         "ct_al_update": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
         "ct_compact": (C.c_int, [vp, i64, vp, vp, vp]),
@@ -229,6 +230,10 @@ def ct_autotune(h, X, n, ld, stream=0) -> int:
 
 def ct_feasibility(h, terms, n, ld, penalty, counts=None, H=None, stream=0):
     _chk(LIB.ct_feasibility(h, terms, n, ld, penalty, counts, H, stream), "ct_feasibility")
+
+
+def ct_feasibility_noalloc(h, terms, n, ld, penalty, H, stream=0):
+    _chk(LIB.ct_feasibility_noalloc(h, terms, n, ld, penalty, H, stream), "ct_feasibility_noalloc")
 
 
 def ct_set_term_weights(h, W, ld):

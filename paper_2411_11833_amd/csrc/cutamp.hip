@@ -7,6 +7,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -449,6 +450,53 @@ extern "C" int ct_feasibility(const ct_problem* P, const float* terms, int64_t n
     int32_t* cnt = counts ? counts : P->t_dev + 2;
     hipLaunchKernelGGL(ct::feas_count_kernel, dim3(P->nc), dim3(256), 0, st, P->d, terms, n, ld, cnt);
     if (H) hipLaunchKernelGGL(ct::feas_h_kernel, dim3(1), dim3(64), 0, st, cnt, P->nc, penalty, H);
+    return err_of(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free feasibility: the per-constraint counts live in one
+// file-scope device array per GPU (held until the process ends) instead of
+// the handle's buffer.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is a stand-in, not a device address): the address
+// comes from hipGetSymbolAddress, taken once per device with that device
+// current, and is kept per device.
+
+static __device__ __align__(256) int32_t scratch[CT_FEAS_SCRATCH_MAX];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_ptr[kMaxDevices] = {};
+
+int device_scratch(int32_t** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CT_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return CT_ERR_DEVICE;
+        g_scratch_ptr[dev] = (int32_t*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CT_OK;
+}
+
+}  // namespace
+
+extern "C" int ct_feasibility_noalloc(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float penalty,
+                                      float* H, void* stream) {
+    if (!P || !H || !std::isfinite(penalty)) return CT_ERR_INVALID_ARG;
+    if (n < 0 || ld < n || ld % 64 != 0 || (n > 0 && !terms)) return CT_ERR_INVALID_ARG;
+    if (terms && ((uintptr_t)terms % 256)) return CT_ERR_INVALID_ARG;
+    if (P->nc > CT_FEAS_SCRATCH_MAX) return CT_ERR_UNSUPPORTED;
+    int32_t* cnt = nullptr;
+    const int rc = device_scratch(&cnt);
+    if (rc != CT_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // every count is written (not accumulated), so nothing needs clearing
+    hipLaunchKernelGGL(ct::feas_count_kernel, dim3(P->nc), dim3(256), 0, st, P->d, terms, n, ld, cnt);
+    hipLaunchKernelGGL(ct::feas_h_kernel, dim3(1), dim3(64), 0, st, cnt, P->nc, penalty, H);
     return err_of(hipGetLastError());
 }
 

@@ -127,19 +127,29 @@ struct MoveCtx<0> {
 // skip a box only when no lane of the wave needs it.  The bound holds every
 // sphere of the set with a margin, so a skipped box touches none of them and
 // every penetration sum is unchanged.
-template <int KT>
-__device__ __forceinline__ void touched_boxes(const Tables* __restrict__ T, const MoveCtx<KT>& mc, float wx,
-                                              float wy, float wz, float rb, uint32_t& smask, uint32_t& omask) {
+// The SPLIT lanes of a slot hold the same bounding sphere, so they share the
+// static boxes out: lane si tests boxes si, si + SPLIT, ... (from the
+// workgroup's LDS copy sbl), and the ballot bits of the lanes with a given si
+// (every SPLIT-th lane of the wave) tell whether some slot touches that box.
+template <int KT, int SPLIT>
+__device__ __forceinline__ void touched_boxes(const Tables* __restrict__ T, const SBox* __restrict__ sbl, int si,
+                                              const MoveCtx<KT>& mc, float wx, float wy, float wz, float rb,
+                                              uint32_t& smask, uint32_t& omask) {
     const float r2 = rb * rb;
     smask = 0u;
     omask = 0u;
     const int nsb = T->n_static;
-    for (int b = 0; b < nsb; ++b) {
-        const SBox B = T->sbox[b];
+    constexpr uint64_t LANES = SPLIT == 1 ? ~0ull : SPLIT == 2 ? 0x5555555555555555ull : 0x1111111111111111ull;
+    for (int b0 = 0; b0 < nsb; b0 += SPLIT) {
+        const int b = b0 + si;
+        const SBox B = sbl[min(b, nsb - 1)];
         const float px = fmaf(B.c, wx, fmaf(B.s, wy, B.u0));
         const float py = fmaf(B.c, wy, fmaf(-B.s, wx, B.u1));
         const float pz = wz - B.tz;
-        if (__ballot(box_d2(px, py, pz, B.hx, B.hy, B.hz) < r2)) smask |= 1u << b;
+        const uint64_t hit = __ballot(b < nsb && box_d2(px, py, pz, B.hx, B.hy, B.hz) < r2);
+#pragma unroll
+        for (int u = 0; u < SPLIT; ++u)
+            if (hit & (LANES << u)) smask |= 1u << (b0 + u);
     }
 #pragma unroll
     for (int j = 0; j < mc.count(); ++j) {
@@ -280,24 +290,19 @@ __device__ __forceinline__ void joint_advance(const Tables* __restrict__ T, int 
 // lane si of a slot takes table entries s0 + si + SPLIT j, j = j0 .. j0+NB-1
 // (entries past the link's end get radius 0, which never penetrates).
 // Accumulates the link's wrench (force f, moment tq about the world origin).
+// The sphere table is the workgroup's LDS copy (rsl), read at each lane's
+// own entry.
 template <int KT, int SPLIT, int NB, bool GRAD>
-__device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, int s1, int j0, int si,
-                                          const float R[9], const float t[3], const MoveCtx<KT>& mc, uint32_t smask,
-                                          uint32_t omask, float lam, float& coll, float f[3], float tq[3],
-                                          float* __restrict__ gr) {
+__device__ __forceinline__ void robot_run(const Tables* __restrict__ T, const float4* __restrict__ rsl, int s0,
+                                          int s1, int j0, int si, const float R[9], const float t[3],
+                                          const MoveCtx<KT>& mc, uint32_t smask, uint32_t omask, float lam,
+                                          float& coll, float f[3], float tq[3], float* __restrict__ gr) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
-        const int base = s0 + SPLIT * (j0 + m);   // uniform
-        float4 sp = T->rs[min(base, s1 - 1)];
-        if (SPLIT > 1) {
-#pragma unroll
-            for (int u = 1; u < SPLIT; ++u) {
-                const float4 o = T->rs[min(base + u, s1 - 1)];
-                if (si == u) sp = o;
-            }
-        }
-        rr[m] = (base + si < s1) ? sp.w : 0.f;
+        const int e = s0 + SPLIT * (j0 + m) + si;
+        const float4 sp = rsl[min(e, s1 - 1)];
+        rr[m] = e < s1 ? sp.w : 0.f;
         cx[m] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + t[0];
         cy[m] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + t[1];
         cz[m] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + t[2];
@@ -326,14 +331,16 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, int s0, 
 // (wave-uniform) number of entries each lane of the slot handles, against the
 // boxes the link's bounding sphere may touch.
 template <int KT, int SPLIT, bool GRAD>
-__device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L, int si, const float R[9],
-                                             const float t[3], const MoveCtx<KT>& mc, float lam, float& coll,
-                                             float f[3], float tq[3], float* __restrict__ gr) {
+__device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, const float4* __restrict__ rsl,
+                                             const SBox* __restrict__ sbl, int L,
+                                             int si, const float R[9], const float t[3], const MoveCtx<KT>& mc,
+                                             float lam, float& coll, float f[3], float tq[3],
+                                             float* __restrict__ gr) {
     const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
     if (s1 == s0) return;
     const float4 lb = T->lbs[L];
     uint32_t smask, omask;
-    touched_boxes<KT>(T, mc, R[0] * lb.x + R[1] * lb.y + R[2] * lb.z + t[0],
+    touched_boxes<KT, SPLIT>(T, sbl, si, mc, R[0] * lb.x + R[1] * lb.y + R[2] * lb.z + t[0],
                       R[3] * lb.x + R[4] * lb.y + R[5] * lb.z + t[1], R[6] * lb.x + R[7] * lb.y + R[8] * lb.z + t[2],
                       lb.w, smask, omask);
     if (!(smask | omask)) return;   // wave-uniform: no sphere of the link touches any box
@@ -341,13 +348,13 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, int L
     int j = 0;
     constexpr int RUN = run_len<KT>();
     for (; j + RUN <= per_lane; j += RUN)
-        robot_run<KT, SPLIT, RUN, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, RUN, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
     if (RUN > 2 && j + 2 <= per_lane) {
-        robot_run<KT, SPLIT, 2, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, 2, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
         j += 2;
     }
     for (; j < per_lane; ++j)
-        robot_run<KT, SPLIT, 1, GRAD>(T, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, 1, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
 }
 
 // Runs of object spheres (table osl, object frame) transformed by (R, t):
@@ -389,13 +396,13 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
 }
 
 template <int KT, int SPLIT, bool GRAD>
-__device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const float4* __restrict__ osl,
-                                               int nos, float4 ob, int si, const float R[9], const float t[3],
+__device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const SBox* __restrict__ sbl,
+                                               const float4* __restrict__ osl, int nos, float4 ob, int si, const float R[9], const float t[3],
                                                const MoveCtx<KT>& mc, float lam, float& coll, float f[3],
                                                float tq[3], float* __restrict__ gr) {
     if (nos <= 0) return;
     uint32_t smask, omask;
-    touched_boxes<KT>(T, mc, R[0] * ob.x + R[1] * ob.y + R[2] * ob.z + t[0],
+    touched_boxes<KT, SPLIT>(T, sbl, si, mc, R[0] * ob.x + R[1] * ob.y + R[2] * ob.z + t[0],
                       R[3] * ob.x + R[4] * ob.y + R[5] * ob.z + t[1], R[6] * ob.x + R[7] * ob.y + R[8] * ob.z + t[2],
                       ob.w, smask, omask);
     if (!(smask | omask)) return;   // wave-uniform: the held object touches no box
@@ -620,7 +627,8 @@ struct LaneOut {
 // world-frame wrenches: dJ/dq_j = z_j . tau + (o_j x z_j) . f for the wrench
 // of everything beyond joint j), and the grasp / placement partials gg, gr.
 template <int KT, int SPLIT, bool GRAD>
-__device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const float4* __restrict__ osl_k, int si,
+__device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const float4* __restrict__ rsl,
+                                            const SBox* __restrict__ sbl, const float4* __restrict__ osl_k, int si,
                                             const float q[CT_N_JOINTS], bool held, bool kin, bool placing,
                                             float lam, const MoveCtx<KT>& mc, float gx, float gy, float gz,
                                             float g_c, float g_s, float rho_x, float rho_y, float rho_c,
@@ -653,11 +661,11 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
         jsn[i] = sn;
         jcs[i] = cs;
         joint_advance(T, i, sn, cs, R, t);
-        link_spheres<KT, SPLIT, GRAD>(T, i + 1, si, R, t, mc, lam, coll, f, tq, gr);
+        link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, i + 1, si, R, t, mc, lam, coll, f, tq, gr);
     }
     // ---- tool frame: tool spheres, the held object, the kinematic constraint
     const float te[3] = {t[0] + R[2] * T->tool_d, t[1] + R[5] * T->tool_d, t[2] + R[8] * T->tool_d};
-    link_spheres<KT, SPLIT, GRAD>(T, 8, si, R, te, mc, lam, coll, f, tq, gr);
+    link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, 8, si, R, te, mc, lam, coll, f, tq, gr);
 
     if (held) {
         // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
@@ -673,7 +681,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                              te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
                              te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, T->obs[k], si, RO, tO, mc, lam, coll, fo, to, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, RO, tO, mc, lam, coll, fo, to, gr);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
             // object turns about the tool z-axis through the tool origin
@@ -776,7 +784,8 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
 template <int KT, int SPLIT, int MODE, bool EXT>
 __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const float* __restrict__ xs,
                                              int xs_stride, const float4* __restrict__ plc,
-                                             const float4* __restrict__ osl, int K_rt, int slot, int si,
+                                             const float4* __restrict__ osl, const float4* __restrict__ rsl,
+                                             const SBox* __restrict__ sbl, int K_rt, int slot, int si,
                                              float* __restrict__ part, float* __restrict__ terms,
                                              int64_t term_ld, int64_t i_glob, bool write_terms,
                                              const float* __restrict__ wts) {
@@ -788,8 +797,15 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     SlotW swv;
     if (EXT) swv = slot_weights(T, wts, term_ld, i_glob, K, slot, self_on);
     const SlotW* sw = EXT ? &swv : nullptr;
-    const int k = slot >> 1;
-    const bool placing = slot & 1;
+    // When a step's slots fill whole waves (the tile layout at K = 1, 2, 4)
+    // the step, and at K = 1, 2 also the slot kind, is the same for every
+    // lane of a wave: say so, so that step-indexed tables are scalar loads
+    // and the kind's branches are uniform.
+    constexpr int LANES_PER_SLOT = KT ? tile_particles(KT, SPLIT) * SPLIT : 1;
+    constexpr bool STEP_UNIFORM = KT > 0 && (2 * LANES_PER_SLOT) % 64 == 0;
+    constexpr bool KIND_UNIFORM = KT > 0 && LANES_PER_SLOT % 64 == 0;
+    const int k = STEP_UNIFORM ? __builtin_amdgcn_readfirstlane(slot >> 1) : slot >> 1;
+    const bool placing = KIND_UNIFORM ? (__builtin_amdgcn_readfirstlane(slot) & 1) : (slot & 1);
     auto X = [&](int d) { return xs[d * xs_stride]; };
     const int b0 = CT_STEP_DIM * k;
     float* gr = part + 11;   // placement partials, this lane's own
@@ -850,7 +866,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         // along the holding transition
         const bool held = key || placing;
         const float lam = key ? (sw ? sw->coll : T->w[W_COLL]) : (sw ? sw->mcoll : T->w[W_MCOLL]);
-        config_pass<KT, SPLIT, GRAD>(T, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
+        config_pass<KT, SPLIT, GRAD>(T, rsl, sbl, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
                                      rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, sw, key && self_on, selfc);
         if (key) coll += cw; else coll_m += cw;
         if (GRAD) {
@@ -907,7 +923,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
         const float tp[3] = {rho_x, rho_y, T->place_z[k]};
         float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, osl_k, T->n_os, T->obs[k], si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
         if (GRAD) {
             // translation: the force; turning about the vertical through the
             // placement origin: z of the moment about that point
@@ -1026,9 +1042,14 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
 //   placements        K P                                <= 128 / SPLIT float4
 //   lane partials     P 2K SPLIT (18 + 3K)                <= 256 (18 + 3 * 6) floats
 //   slot records      P 2K                                <= 256 / SPLIT
+//   staged moments    2 D P (fused step only; the same bound as the particles)
 template <int SPLIT>
 struct TileSmem {
     float xs[2688 / SPLIT];
+    float ms[2688 / SPLIT], vs[2688 / SPLIT];
+    uint8_t frz[CT_MAX_STEPS * CT_STEP_DIM];
+    float4 rs[CT_MAX_ROBOT_SPHERES];
+    SBox sbx[CT_MAX_STATIC_BOXES];
     float4 plc[128 / SPLIT];
     float part[WG * (18 + 3 * CT_MAX_STEPS)];
     float cpart[WG / SPLIT];
@@ -1068,15 +1089,42 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
     const int tid = threadIdx.x;
     const int32_t iter = t - 1;
 
-    // phase 0: stage this tile's particles (coalesced along particles), the
-    // placements' poses, and the object sphere tables
-    for (int idx = tid; idx < D * P; idx += WG) {
-        const int d = idx / P, p = idx - d * P;
-        const int64_t i = p0 + p;
-        sm.xs[idx] = i < n ? io.X[d * ld + i] : 0.f;
+    // phase 0: stage this tile's particles (coalesced along particles) and,
+    // for the fused step, their Adam moments and the frozen flags; the
+    // placements' poses, and the robot and object sphere tables.  A lane
+    // issues all of its loads before the first wait (NST is an upper bound
+    // on its share; with the skeleton length known at compile time, exact),
+    // so the tile pays one memory latency here and none in phase 2.
+    {
+        constexpr int NST = (KT ? CT_STEP_DIM * KT * tile_particles(KT, SPLIT) : 2688 / SPLIT) / WG + 1;
+        constexpr bool MV = MODE == MODE_STEP;
+        float xv[NST], mv[NST], vv[NST];
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = tid + u * WG;
+            const int d = idx / P, p = idx - d * P;
+            const int64_t i = p0 + p;
+            xv[u] = mv[u] = vv[u] = 0.f;
+            if (idx < D * P && i < n) {
+                const int64_t a = d * ld + i;
+                xv[u] = io.X[a];
+                if (MV) { mv[u] = io.M[a]; vv[u] = io.V[a]; }
+            }
+        }
+        if (MV && tid < D) sm.frz[tid] = io.frozen ? io.frozen[tid] : 0;
+#pragma unroll
+        for (int u = 0; u < NST; ++u) {
+            const int idx = tid + u * WG;
+            if (idx < D * P) {
+                sm.xs[idx] = xv[u];
+                if (MV) { sm.ms[idx] = mv[u]; sm.vs[idx] = vv[u]; }
+            }
+        }
     }
     for (int idx = tid; idx < K * CT_MAX_OBJ_SPHERES; idx += WG)
         sm.osl[idx] = T->os[idx / CT_MAX_OBJ_SPHERES][idx % CT_MAX_OBJ_SPHERES];
+    for (int idx = tid; idx < T->link_start[9]; idx += WG) sm.rs[idx] = T->rs[idx];
+    if (tid < T->n_static) sm.sbx[tid] = T->sbox[tid];
     if (tid == 0) sm.any_sat = 0;
     __syncthreads();
     for (int idx = tid; idx < K * P; idx += WG) {
@@ -1098,7 +1146,7 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
         if (slot < SLOTS) {
             const int64_t i = p0 + p;
             const bool wt = (MODE == MODE_COST) && io.terms != nullptr && i < n;
-            const LaneOut o = lane_slot<KT, SPLIT, MODE, EXT>(T, sm.xs + p, P, sm.plc + p, sm.osl, K, slot, si,
+            const LaneOut o = lane_slot<KT, SPLIT, MODE, EXT>(T, sm.xs + p, P, sm.plc + p, sm.osl, sm.rs, sm.sbx, K, slot, si,
                                                      sm.part + (size_t)((p * SLOTS + slot) * SPLIT + si) * NP,
                                                      io.terms, ld, i, wt, i < n ? io.wts : nullptr);
             if (si == 0) {
@@ -1170,10 +1218,10 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
             const int64_t a = d * ld + i;
             if (MODE == MODE_GRAD) {
                 io.G[a] = io.gw ? io.gw[i] * g : g;
-            } else if (sm.okp[p] && !(io.frozen && io.frozen[d])) {
+            } else if (sm.okp[p] && !sm.frz[d]) {
                 const float gs = io.gscale * g;
-                const float m1 = b1 * io.M[a] + (1.f - b1) * gs;
-                const float v1 = b2 * io.V[a] + (1.f - b2) * gs * gs;
+                const float m1 = b1 * sm.ms[idx] + (1.f - b1) * gs;
+                const float v1 = b2 * sm.vs[idx] + (1.f - b2) * gs * gs;
                 const float mh = m1 / bc1, vh = v1 / bc2;
                 io.X[a] = sm.xs[idx] - lr * mh / (sqrtf(vh) + eps);
                 io.M[a] = m1;

@@ -99,6 +99,10 @@ def parse():
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
+    ap.add_argument("--sampling-rounds", type=int, default=3,
+                    help="composed batches the Sampling baseline draws per scene")
+    ap.add_argument("--plain-budget", type=int, default=10000,
+                    help="iteration budget of the plain method in the compositional comparison")
     ap.add_argument("--sampling-iters", type=int, default=1500,
                     help="most Adam iterations of the one-step problems before refining the composition")
     ap.add_argument("--learned-scenes", type=int, default=2048,
@@ -227,42 +231,75 @@ def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, s
 
 
 def compositional(args, dev, n, q):
+    """Compositional initialization as Sec. V composes it (grasp and
+    placement samplers, the configuration sampler conditioned on both,
+    composition with rejection, then refinement), the Sampling baseline of
+    Sec. VII (composed batches drawn again, never optimized) and the plain
+    method from uniform seeds with a long budget, on the held-out packing
+    scenes and on held-out single pick-place scenes."""
     from paper_2411_11833_amd import inputs as I
-    from paper_2411_11833_amd.planner import GpuProblem
-    from paper_2411_11833_amd.sampling import CompositionalInit
+    from paper_2411_11833_amd import seeds as SD
+    from paper_2411_11833_amd.planner import GpuProblem, default_adam, plain_solve
+    from paper_2411_11833_amd.sampling import CompositionalInit, sampling_solve
 
-    scenes = list(range(20000, 20000 + args.eval_scenes))
-    n_sub, budget = 8192, args.eval_budget
-    first, times, counts = [], [], []
-    for s in scenes:
-        prob = I.packing(args.robot_seed, s)
-        gp = GpuProblem(prob, dev)
-        ci = CompositionalInit(prob, n_sub, dev)
-        seed = 4242 + s
-        ci.solve(gp, n, seed, max_iters=100, first_check=50, chunk=50, refine_budget=20)   # captures the graphs
-        r = ci.solve(gp, n, seed, max_iters=args.sampling_iters, first_check=50, chunk=50, refine_budget=budget)
-        first.append(r.first_sat_iter)
-        times.append(r.time_to_first_s)
-        counts.append([int(c) for c in ci.count.cpu().numpy()])
-        log(f"[bench] compositional init, scene {s}: first satisfying particle after {r.first_sat_iter} iterations "
-            f"(one-step + refinement), {r.time_to_first_s} s (satisfying one-step particles per step {counts[-1]})", q)
-        ci.close()
-        gp.close()
-    solved = [t for t in times if t is not None]
-    return {
-        "kind": "time to the first satisfying particle (Eq. 3) from compositional initialization: each pick-place "
-                "step solved alone by the plain optimizer (one-step skeletons, all steps in one persistent launch "
-                f"per iteration, {n_sub} particles each, uniform seeds); every 50 iterations the satisfying "
-                "one-step particles are composed into packing particles and tested; after "
-                f"{args.sampling_iters} one-step iterations the composition is refined by the plain optimizer "
-                "with stop at first; GPU time from the start of initialization",
-        "scenes": scenes, "particles": n, "one_step_particles": n_sub, "one_step_iters_max": args.sampling_iters,
-        "refine_budget": budget, "first_iter": first, "time_to_first_s": times,
-        "satisfying_one_step_particles": counts,
-        "coverage": len(solved) / len(scenes),
-        "median_time_to_first_s": float(np.median(solved)) if solved else None,
-        "max_time_to_first_s": max(solved) if solved else None,
+    def run(make, scenes, n_part, n_sub, label):
+        comp, samp, plain = [], [], []
+        for s in scenes:
+            prob = make(s)
+            gp = GpuProblem(prob, dev)
+            ci = CompositionalInit(prob, n_sub, dev)
+            seed = 4242 + s
+            ci.solve(gp, n_part, seed, max_iters=100, first_check=50, chunk=50, refine_budget=20)   # captures
+            r = ci.solve(gp, n_part, seed, max_iters=args.sampling_iters, first_check=50, chunk=50,
+                         refine_budget=args.eval_budget)
+            rs = sampling_solve(ci, gp, n_part, seed, ik_iters=args.sampling_iters, max_rounds=args.sampling_rounds)
+            plain_solve(gp, n_part, 20, seed=seed, adam=default_adam(n_part))                       # captures
+            rp = plain_solve(gp, n_part, args.plain_budget, seed=seed, adam=default_adam(n_part))
+            comp.append(r)
+            samp.append(rs)
+            plain.append(rp)
+            log(f"[bench] {label} scene {s}: compositional {r.first_sat_iter} it / {r.time_to_first_s} s; "
+                f"sampling {rs.first_sat_iter} it / {rs.time_to_first_s} s; "
+                f"plain {rp.first_sat_iter} it / {rp.time_to_first_s} s", q)
+            ci.close()
+            gp.close()
+        t = {k: [x.time_to_first_s for x in v] for k, v in (("compositional", comp), ("sampling", samp),
+                                                               ("plain", plain))}
+        out = {"scenes": list(scenes), "particles": n_part, "one_step_particles": n_sub}
+        for k, v in (("compositional", comp), ("sampling", samp), ("plain", plain)):
+            solved = [x.time_to_first_s for x in v if x.time_to_first_s is not None]
+            out[k] = {"first_iter": [x.first_sat_iter for x in v], "time_to_first_s": t[k],
+                      "coverage": len(solved) / len(v),
+                      "median_time_to_first_s": float(np.median(solved)) if solved else None,
+                      "max_time_to_first_s": max(solved) if solved else None}
+        eq = {}
+        for other in ("sampling", "plain"):
+            cu, co, rate, tc, tt = SD.equal_rate_times(t["compositional"], t[other])
+            eq[other] = {"coverage_compositional": cu, "coverage_" + other: co, "equal_satisfaction_rate": rate,
+                         "time_compositional_s": tc, "time_" + other + "_s": tt,
+                         "speedup": (tt / tc) if (tt and tc) else None}
+        out["equal_rate_vs"] = eq
+        return out
+
+    res = {
+        "kind": "time to the first satisfying particle (Eq. 3), GPU time from the start of initialization. "
+                "compositional: grasps drawn in the valid grasp box, placements drawn over the centres that "
+                "keep the footprint in the goal region, then each pick-place action's configurations "
+                "optimized alone with its grasp and placement frozen (one-step problems, all actions in one "
+                "persistent launch per iteration); every 50 iterations the actions satisfying Eq. (3) are "
+                f"composed into whole particles and tested; after {args.sampling_iters} iterations the last "
+                f"composition is refined by the plain optimizer (budget {args.eval_budget}). sampling: the same "
+                f"samplers and {args.sampling_iters} configuration-sampler iterations per round, composed batches "
+                f"drawn again up to {args.sampling_rounds} rounds, never optimized as a whole. plain: uniform "
+                f"seeds, budget {args.plain_budget} iterations.",
+        "packing": run(lambda s: I.packing(args.robot_seed, s), range(20000, 20000 + args.eval_scenes), n, 8192,
+                       "packing"),
+        "single_pick_place": run(lambda s: I.single_pick_place(args.robot_seed, s),
+                                 range(20000, 20000 + args.eval_scenes), 256, 256, "single pick-place"),
     }
+    # keys read by the learned-seed comparisons
+    res["time_to_first_s"] = res["packing"]["compositional"]["time_to_first_s"]
+    return res
 
 
 def learned_seeds(args, dev, n, q):

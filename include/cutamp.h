@@ -195,6 +195,23 @@ int ct_seed_uniform(const ct_problem *problem, uint64_t seed, float *X, float *M
                     int64_t n, int64_t ld, void *stream);
 
 /*
+ * The grasp, placement and configuration samplers of compositional particle
+ * initialization (Sec. V, "Particle Initialization"): the draw of
+ * ct_seed_uniform (same seed, same Philox words), except that every step's
+ * placement centre is drawn uniformly over the centres that keep the
+ * object's footprint, turned by the drawn placement yaw, inside the goal
+ * region, so that every particle satisfies the containment of StablePlace
+ * and the Grasp constraint (grasps are uniform in the valid grasp box);
+ * configurations stay uniform in the joint limits (the starting points of
+ * the configuration sampler, which optimizes them with grasps and
+ * placements frozen).  A region narrower than the footprint on an axis
+ * gives its centre on that axis.  Arguments, layout and errors as
+ * ct_seed_uniform.
+ */
+int ct_seed_sampled(const ct_problem *problem, uint64_t seed, float *X, float *M, float *V, int64_t n,
+                    int64_t ld, void *stream);
+
+/*
  * Cost of Eq. (2) per particle: cost[i] (FP32, [n]).  Optional outputs:
  * terms [n_terms][ld] unweighted term values, and mask[i] = 1 iff particle i
  * satisfies every constraint (Eq. (3), J_c <= eps_c).  terms and mask may be

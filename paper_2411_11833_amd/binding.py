@@ -79,6 +79,7 @@ def _load() -> C.CDLL:
         "ct_problem_destroy": (C.c_int, [vp]),
         "ct_problem_info": (C.c_int, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "ct_seed_uniform": (C.c_int, [vp, u64, vp, vp, vp, i64, i64, vp]),
+        "ct_seed_sampled": (C.c_int, [vp, u64, vp, vp, vp, i64, i64, vp]),
         "ct_cost": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp]),
         "ct_cost_grad": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp]),
         "ct_adam_apply": (C.c_int, [vp, vp, vp, vp, vp, i64, i64, i64, C.POINTER(CtAdam), vp, vp]),
@@ -184,6 +185,10 @@ def ct_problem_info(h: int) -> tuple[int, int, int]:
 
 def ct_seed_uniform(h, seed, X, M, V, n, ld, stream=0):
     _chk(LIB.ct_seed_uniform(h, int(seed) & (2 ** 64 - 1), X, M, V, n, ld, stream), "ct_seed_uniform")
+
+
+def ct_seed_sampled(h, seed, X, M, V, n, ld, stream=0):
+    _chk(LIB.ct_seed_sampled(h, int(seed) & (2 ** 64 - 1), X, M, V, n, ld, stream), "ct_seed_sampled")
 
 
 def ct_cost(h, X, n, ld, cost, terms=None, mask=None, stream=0):

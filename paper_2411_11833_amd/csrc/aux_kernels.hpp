@@ -36,6 +36,38 @@ __global__ __launch_bounds__(256) void seed_uniform_kernel(const Tables* __restr
     }
 }
 
+// Placement sampler of compositional initialization (Sec. V): after the
+// uniform draw, the placement centre of every step is redrawn uniformly over
+// the centres that keep the object's footprint, turned by the drawn yaw psi,
+// inside the goal region: on each axis [lo + e, hi - e] with
+// e_x = |hx cos psi| + |hy sin psi|, e_y = |hx sin psi| + |hy cos psi|, from
+// the same Philox word as the uniform draw of that dimension (the region's
+// centre when the interval is empty).  Joint and grasp dimensions keep the
+// uniform draw: the grasp box is the Grasp constraint's set, and uniform
+// configurations are the starting points of the configuration sampler.
+__global__ __launch_bounds__(256) void place_sampler_kernel(const Tables* __restrict__ T, uint32_t k0, uint32_t k1,
+                                                            float* __restrict__ X, int64_t n, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < T->K; ++k) {
+        const int o = CT_STEP_DIM * k;
+        const float psi = X[(int64_t)(o + 20) * ld + i];
+        float sn, cs;
+        sincosf(psi, &sn, &cs);
+        const float hx = T->obj0[k].hx, hy = T->obj0[k].hy;
+        const float e[2] = {fabsf(hx * cs) + fabsf(hy * sn), fabsf(hx * sn) + fabsf(hy * cs)};
+#pragma unroll
+        for (int ax = 0; ax < 2; ++ax) {
+            const int d = o + 18 + ax;
+            uint32_t c[4] = {(uint32_t)i, (uint32_t)(d / 4), 0u, 0u};
+            philox4x32_10(c, k0, k1);
+            const float u = (float)(c[d % 4] >> 8) * 5.9604644775390625e-08f;   // 2^-24
+            const float a = T->region_lo[ax] + e[ax], b = T->region_hi[ax] - e[ax];
+            X[(int64_t)d * ld + i] = b >= a ? a + (b - a) * u : 0.5f * (T->region_lo[ax] + T->region_hi[ax]);
+        }
+    }
+}
+
 // Stand-alone Adam: one thread per particle, so that a particle with a
 // non-finite gradient or coordinate is skipped as a whole.
 __global__ __launch_bounds__(256) void adam_kernel(int D, float* __restrict__ X, float* __restrict__ M,

@@ -537,6 +537,15 @@ extern "C" int ct_seed_uniform(const ct_problem* P, uint64_t seed, float* X, flo
     return err_of(hipGetLastError());
 }
 
+extern "C" int ct_seed_sampled(const ct_problem* P, uint64_t seed, float* X, float* M, float* V, int64_t n,
+                               int64_t ld, void* stream) {
+    const int rc = ct_seed_uniform(P, seed, X, M, V, n, ld, stream);
+    if (rc != CT_OK || n == 0) return rc;
+    hipLaunchKernelGGL(ct::place_sampler_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       P->d, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), X, n, ld);
+    return err_of(hipGetLastError());
+}
+
 extern "C" int ct_cost(const ct_problem* P, const float* X, int64_t n, int64_t ld, float* cost, float* terms,
                        uint8_t* mask, void* stream) {
     if (empty_ok(P, n, ld)) return CT_OK;

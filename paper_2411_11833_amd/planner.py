@@ -70,6 +70,12 @@ class GpuProblem:
         B.ct_seed_uniform(self.handle, seed, X.data_ptr(), M.data_ptr() if M is not None else None,
                           V.data_ptr() if V is not None else None, n, X.shape[1], _stream())
 
+    def seed_sampled(self, seed: int, X, M=None, V=None, n: int | None = None):
+        """The grasp, placement and configuration samplers (ct_seed_sampled)."""
+        n = X.shape[1] if n is None else n
+        B.ct_seed_sampled(self.handle, seed, X.data_ptr(), M.data_ptr() if M is not None else None,
+                          V.data_ptr() if V is not None else None, n, X.shape[1], _stream())
+
     def cost(self, X, n: int, terms: bool = False, mask: bool = True):
         c = torch.empty(n, dtype=torch.float32, device=self.device)
         T = self.empty(n, rows=self.n_terms) if terms else None
@@ -176,6 +182,16 @@ def grasp_frozen(prob: I.Problem, device="cuda") -> torch.Tensor:
     return f.to(device)
 
 
+def sampler_frozen(prob: I.Problem, device="cuda") -> torch.Tensor:
+    """Frozen-dimension mask of the conditional configuration sampler: every
+    step's grasp and placement stay as the grasp and placement samplers drew
+    them, only the configurations move."""
+    f = grasp_frozen(prob, "cpu")
+    for k in range(prob.skeleton.n_steps):
+        f[I.STEP_DIM * k + 18:I.STEP_DIM * k + 21] = 1
+    return f.to(device)
+
+
 def default_adam(n: int, lr: float = 1e-2) -> B.CtAdam:
     """lr 1e-2, betas (0.9, 0.999), eps 1e-8, gradient scaled by 1/N_b (Eq. 4)."""
     return B.CtAdam(lr, 0.9, 0.999, 1e-8, 1.0 / n)
@@ -186,7 +202,8 @@ class GpuBatch:
     one persistent launch per iteration (or, for comparison, one launch per
     skeleton)."""
 
-    def __init__(self, problems: list, sizes: list[int], device="cuda", fixed_grasps: bool = True):
+    def __init__(self, problems: list, sizes: list[int], device="cuda", fixed_grasps: bool = True,
+                 fixed_placements: bool = False):
         self.gps = [GpuProblem(p, device) for p in problems]
         self.sizes = list(sizes)
         self.device = torch.device(device)
@@ -196,7 +213,8 @@ class GpuBatch:
         self.cost = [torch.empty(n, dtype=torch.float32, device=self.device) for n in sizes]
         self.mask = [torch.empty(n, dtype=torch.uint8, device=self.device) for n in sizes]
         self.first_sat = torch.full((len(sizes),), INT32_MAX, dtype=torch.int32, device=self.device)
-        self.frozen = [grasp_frozen(p, self.device) if fixed_grasps else None for p in problems]
+        self.frozen = [sampler_frozen(p, self.device) if fixed_placements else
+                       grasp_frozen(p, self.device) if fixed_grasps else None for p in problems]
         ptr = lambda a: a.data_ptr() if a is not None else None  # noqa: E731
         self.handle = B.ct_batch_create(
             [g.handle for g in self.gps], [x.data_ptr() for x in self.X], [m.data_ptr() for m in self.M],
@@ -215,9 +233,11 @@ class GpuBatch:
         except Exception:
             pass
 
-    def seed(self, seed: int):
+    def seed(self, seed: int, sampled: bool = False):
+        """Uniform draws, or (sampled) the grasp and placement samplers'."""
         for s, (g, n) in enumerate(zip(self.gps, self.sizes)):
-            g.seed_uniform(seed * 1000 + s, self.X[s], self.M[s], self.V[s], n)
+            draw = g.seed_sampled if sampled else g.seed_uniform
+            draw(seed * 1000 + s, self.X[s], self.M[s], self.V[s], n)
         self.first_sat.fill_(INT32_MAX)
 
     def set_tuning(self, split=0, workgroups=0, persistent=True):

@@ -1,23 +1,36 @@
-"""Compositional initialization (Sec. V "Particle Initialization"): the
-particles of a K-step pick-place skeleton are assembled from the solutions
-of K one-step problems, one per pick-place action, instead of drawn
-uniformly.
+"""Compositional initialization (Sec. V "Particle Initialization") and the
+Sampling baseline of Sec. VII.
 
-Each one-step problem moves object k alone (the other objects stay where
-they start, as obstacles): its particle is one grasp (sampled, then held
-fixed), the pick and place configurations (solved: the plain optimizer on
-the Kin, joint-limit, collision and placement costs of that action) and one
-placement.  All K problems run together, one persistent many-skeleton launch
-per iteration.  Step k of composed particle i then takes the i-th (cyclically)
-one-step particle that satisfies all of its constraints (Eq. 3), or, when
-none does, one-step particle i as it stands.  The composed batch is refined
-by the plain optimizer on the whole skeleton, which resolves what the
-one-step problems could not see (placed objects, the goal cost).
+The particles of a K-step pick-place skeleton are composed from the outputs
+of parallel samplers, each solving a subgraph of the constraint network, as
+the paper's sampling networks do:
 
-Readings: the paper's samplers solve IK with cuRobo; here the same fused
-cost restricted to one action, optimized by the same kernels, is the
-conditional configuration sampler.  Choosing satisfying particles first is
-the composition-with-rejection of the paper's sampling networks.
+  grasp sampler       grasps uniform in the valid grasp box (Grasp holds);
+  placement sampler   placements whose footprint lies in the goal region
+                      (StablePlace containment holds), ct_seed_sampled;
+  configuration sampler, conditioned on both: the pick and place
+                      configurations of one action, solved by the plain
+                      optimizer on that action's cost with the grasp and the
+                      placement frozen (the paper uses cuRobo's parallel IK;
+                      here the same fused cost restricted to one action, i.e.
+                      Kin at the pick and the place, joint limits, the
+                      collision terms of the arm holding the object, and
+                      the object at its placement, which no configuration
+                      changes, so a colliding placement is rejected).
+
+The K one-step problems (object k moved alone, the other objects where they
+start) run together, one persistent many-skeleton launch per iteration.
+Step k of composed particle i takes the i-th (cyclically) one-step particle
+that satisfies every constraint of its action (Eq. 3), or, when none does,
+one-step particle i as it stands: composition with rejection.  The paper's
+method then refines the composed batch with the plain optimizer on the whole
+skeleton, which resolves what no action saw alone (objects placed by earlier
+steps, the goal cost); the Sampling baseline instead draws a fresh composed
+batch, with no optimization of the whole skeleton, until one satisfies.
+
+`conditional=False` keeps the earlier variant in which each one-step problem
+optimizes its grasp-free dimensions jointly (placement included) from
+uniform draws.
 """
 from __future__ import annotations
 
@@ -44,12 +57,13 @@ class CompositionalInit:
     """Buffers and handles for initializing one skeleton's particles by
     composition; reusable across calls (nothing is allocated per call)."""
 
-    def __init__(self, prob: I.Problem, n_sub: int, device="cuda"):
+    def __init__(self, prob: I.Problem, n_sub: int, device="cuda", conditional: bool = True):
         self.prob = prob
         self.n_sub = n_sub
         self.device = torch.device(device)
+        self.conditional = conditional
         self.subs = one_step_problems(prob)
-        self.batch = GpuBatch(self.subs, [n_sub] * len(self.subs), self.device)
+        self.batch = GpuBatch(self.subs, [n_sub] * len(self.subs), self.device, fixed_placements=conditional)
         K = len(self.subs)
         self.idx = torch.empty((K, n_sub), dtype=torch.int32, device=self.device)
         self.count = torch.empty(K, dtype=torch.int32, device=self.device)
@@ -62,11 +76,13 @@ class CompositionalInit:
             g.close()
 
     def run(self, seed: int, iters: int, X, M, V, n: int, chunk: int = 50):
-        """Enqueue the one-step solves (uniform seeds, fixed grasps, `iters`
-        Adam steps), the satisfaction masks of their final particles, and the
-        composition into X (M, V zeroed).  No host synchronization."""
+        """Enqueue the samplers (grasps and placements drawn, then `iters`
+        Adam steps of the configuration sampler; with conditional=False
+        uniform draws and the joint one-step solve), the satisfaction masks of
+        their particles, and the composition into X (M, V zeroed).  No host
+        synchronization."""
         gb = self.batch
-        gb.seed(seed)
+        gb.seed(seed, sampled=self.conditional)
         adam = default_adam(1)   # the batch uses 1/n per skeleton
         for t in range(0, iters, chunk):
             gb.optimize(t, min(chunk, iters - t), adam)
@@ -123,7 +139,7 @@ class CompositionalInit:
         start = torch.cuda.Event(enable_timing=True)
         start.record(stream)
         if seeder is None:
-            gb.seed(seed)
+            gb.seed(seed, sampled=self.conditional)
         else:
             seeder(Xs, None, None)
             self.seed_from(Xs)
@@ -166,3 +182,36 @@ class CompositionalInit:
         ttf = start.elapsed_time(events[min(f // refine_chunk, len(events) - 1)]) / 1e3
         sol = gp.to_rows(X, n)[mask[:n].bool()].cpu().numpy()
         return SolveResult(max_iters + refine_budget, max_iters + f, ttf, wall, int(mask.sum().item()), sol)
+
+
+def sampling_solve(ci: CompositionalInit, gp: GpuProblem, n: int, seed: int, ik_iters: int = 600,
+                   max_rounds: int = 20, budget_s: float | None = None) -> SolveResult:
+    """The Sampling baseline (Sec. VII): composed batches drawn again and
+    again (fresh grasps and placements, `ik_iters` steps of the
+    configuration sampler, composition), each checked against Eq. (3) on the
+    whole skeleton, with no optimization of the composed particles.  Stops at
+    the first satisfying particle, after `max_rounds` batches, or once the
+    GPU time passes `budget_s`.  `first_sat_iter` counts configuration-sampler
+    iterations over all rounds."""
+    X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
+    cost = torch.empty(n, dtype=torch.float32, device=gp.device)
+    mask = torch.empty(n, dtype=torch.uint8, device=gp.device)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for r in range(max_rounds):
+        ci.run(seed * 1000 + r, ik_iters, X, M, V, n)
+        B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), None, mask.data_ptr(), stream.cuda_stream)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(stream)
+        found = bool(mask[:n].any().item())
+        t = start.elapsed_time(ev) / 1e3
+        if found:
+            sol = gp.to_rows(X, n)[mask[:n].bool()].cpu().numpy()
+            return SolveResult((r + 1) * ik_iters, (r + 1) * ik_iters, t, time.perf_counter() - t_wall,
+                               int(mask[:n].sum().item()), sol)
+        if budget_s is not None and t > budget_s:
+            break
+    return SolveResult(max_rounds * ik_iters, None, None, time.perf_counter() - t_wall, 0)

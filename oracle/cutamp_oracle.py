@@ -50,7 +50,7 @@ __all__ = [
     "dist_from_bounds", "pairwise_dist_sum", "grasp_tf", "place_tf", "evaluate",
     "Evaluation", "terms", "cost", "mask", "cost_and_grad", "adam_step", "margins",
     "weights_vector", "tolerance_vector", "place_z", "feasibility", "self_pairs", "self_collision",
-    "weighted_cost_and_grad", "al_update",
+    "weighted_cost_and_grad", "al_update", "phr_weights", "phr_lagrangian",
 ]
 
 
@@ -529,6 +529,32 @@ def al_update(prob: Problem, T, mu, rho: float):
     W = np.broadcast_to(weights_vector(prob), T.shape).copy()
     W[:, :nc] += mu[:, :nc]
     return mu, W
+
+
+def phr_weights(prob: Problem, T, mu, rho: float):
+    """Gradient weights of the PHR augmented Lagrangian
+    L = sum_c lambda_c J_c + (1/(2 rho)) sum_{constraints} (max(0, mu_c + rho g_c)^2 - mu_c^2),
+    g_c = J_c - eps_c: W_c = lambda_c + max(0, mu_c + rho g_c) for a constraint
+    (lambda_c + mu_c when J_c is not finite), lambda_c for a soft cost.
+    T, mu: [N, n_terms]; returns W."""
+    T = np.asarray(T, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    nc = prob.n_constraint_terms
+    W = np.broadcast_to(weights_vector(prob), T.shape).copy()
+    g = T[:, :nc] - tolerance_vector(prob)[None]
+    fin = np.isfinite(T[:, :nc])
+    W[:, :nc] += np.where(fin, np.maximum(0.0, mu[:, :nc] + rho * np.where(fin, g, 0.0)), mu[:, :nc])
+    return W
+
+
+def phr_lagrangian(prob: Problem, X, mu, rho: float) -> np.ndarray:
+    """The PHR augmented Lagrangian itself, per particle (definition above)."""
+    T = terms(prob, X)
+    mu = np.asarray(mu, dtype=np.float64)
+    nc = prob.n_constraint_terms
+    g = T[:, :nc] - tolerance_vector(prob)[None]
+    pen = (np.maximum(0.0, mu[:, :nc] + rho * g) ** 2 - mu[:, :nc] ** 2).sum(1) / (2.0 * rho)
+    return T @ weights_vector(prob) + pen
 
 
 def adam_step(x, m, v, g, t: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,

@@ -558,3 +558,58 @@ def test_al_update_special_cases():
     # a long-satisfied constraint's multiplier decays to exactly 0
     mu, _ = O.al_update(prob, np.zeros((1, nt)) + np.r_[eps - 0.1, np.zeros(nt - nc)][None], np.ones((1, nt)), 100)
     assert np.all(mu[0, :nc][eps > 0] == 0)
+
+
+def test_phr_weights_are_the_gradient_of_the_phr_lagrangian():
+    """The PHR weights pinned against the augmented Lagrangian's own closed
+    form by central differences: sum_c W_c dJ_c/dx with W formed at x equals
+    dL/dx of L = sum lambda J + (1/2rho) sum (max(0, mu + rho g)^2 - mu^2),
+    for particles away from every kink of J and of the PHR hinge."""
+    prob = _small_packing()
+    X = I.uniform_particles(prob, 40, seed=21).astype(np.float64)
+    _, kink = O.margins(prob, X)
+    X = X[kink >= 1e-4][:6]
+    assert len(X) >= 4
+    rng = np.random.default_rng(5)
+    mu = rng.uniform(0.0, 2.0, (len(X), prob.n_terms))
+    rho = 3.0
+    T = O.terms(prob, X)
+    nc = prob.n_constraint_terms
+    hinge = mu[:, :nc] + rho * (T[:, :nc] - O.tolerance_vector(prob)[None])
+    assert (hinge > 0).any() and (hinge < 0).any()            # both branches of the hinge
+    keep = np.abs(hinge).min(1) > 1e-3
+    X, mu = X[keep], mu[keep]
+    W = O.phr_weights(prob, O.terms(prob, X), mu, rho)
+    _, G = O.weighted_cost_and_grad(prob, X, W)
+    h = 1e-6
+    L0 = O.phr_lagrangian(prob, X, mu, rho)
+    for i in range(prob.dim):
+        xp, xm = X.copy(), X.copy()
+        xp[:, i] += h
+        xm[:, i] -= h
+        fd = (O.phr_lagrangian(prob, xp, mu, rho) - O.phr_lagrangian(prob, xm, mu, rho)) / (2 * h)
+        assert np.all(np.abs(G[:, i] - fd) <= 1e-5 * np.abs(fd) + 1e-6 * (1 + np.abs(L0))), i
+
+
+def test_phr_weights_special_cases():
+    """mu = 0 and a satisfied constraint: lambda; violated by v: lambda +
+    mu + rho v; rho = 0: lambda + mu; a NaN term: lambda + mu; soft costs:
+    lambda."""
+    prob = _small_packing()
+    prob.skeleton.goal_cost = 1
+    nc, nt = prob.n_constraint_terms, prob.n_terms
+    eps = O.tolerance_vector(prob)
+    lam = O.weights_vector(prob)
+    T = np.zeros((3, nt))
+    T[0, :nc] = eps + 0.5
+    T[1, :nc] = eps * 0.5
+    T[2, :nc] = np.nan
+    T[:, nc:] = 7.0
+    W = O.phr_weights(prob, T, np.zeros((3, nt)), 2.0)
+    np.testing.assert_allclose(W[0, :nc], lam[:nc] + 1.0)
+    np.testing.assert_array_equal(W[1, :nc], lam[:nc])
+    np.testing.assert_array_equal(W[:, nc:], np.broadcast_to(lam[nc:], (3, nt - nc)))
+    mu = np.full((3, nt), 0.25)
+    np.testing.assert_allclose(O.phr_weights(prob, T, mu, 0.0)[:, :nc], np.broadcast_to(lam[:nc] + 0.25, (3, nc)))
+    np.testing.assert_allclose(O.phr_weights(prob, T, mu, 2.0)[2, :nc], lam[:nc] + 0.25)
+    np.testing.assert_allclose(O.phr_weights(prob, T, mu, 2.0)[0, :nc], lam[:nc] + 0.25 + 1.0)

@@ -50,7 +50,7 @@ __all__ = [
     "dist_from_bounds", "pairwise_dist_sum", "grasp_tf", "place_tf", "evaluate",
     "Evaluation", "terms", "cost", "mask", "cost_and_grad", "adam_step", "margins",
     "weights_vector", "tolerance_vector", "place_z", "feasibility", "self_pairs", "self_collision",
-    "weighted_cost_and_grad", "al_update", "phr_weights", "phr_lagrangian",
+    "weighted_cost_and_grad", "al_update", "phr_weights", "phr_lagrangian", "penetrating_pairs",
 ]
 
 
@@ -194,6 +194,7 @@ class Evaluation:
     cost: torch.Tensor       # [B] weighted sum, Eq. (2)
     kinks: list              # tensors [B] of distances to nonsmooth points (if requested)
     flip_lo: list            # per constraint term: [B] distance inside an eps = 0 bound
+    pair_args: list = None   # hinge arguments r - sdf [B, S] of every sphere-box pair set (if requested)
 
 
 def weights_vector(prob: Problem) -> np.ndarray:
@@ -227,15 +228,18 @@ def _robot_spheres(prob: Problem, frames):
     return torch.cat(cs, 1), _t(r.spheres[:, 3])
 
 
-def _collision(c, rad, boxes, kinks, want_kinks):
+def _collision(c, rad, boxes, kinks, want_kinks, pair_args=None):
     """Sum over spheres and boxes of max(0, r - sdf); records the kink
-    distances of the hinge and of the interior max when asked."""
+    distances of the hinge and of the interior max when asked, and the hinge
+    arguments themselves into pair_args when given."""
     total = torch.zeros(c.shape[0], dtype=DT)
     for T, h in boxes:
         half = _t(h)
         sdf = box_sdf(c, T, half)
         arg = rad - sdf
         total = total + torch.clamp(arg, min=0.0).sum(-1)
+        if pair_args is not None:
+            pair_args.append(arg.detach())
         if want_kinks:
             with torch.no_grad():
                 kinks.append(arg.abs().min(-1).values)
@@ -281,7 +285,7 @@ def self_collision(c, rad, sphere_link, kinks=None, want_kinks=False):
     return torch.clamp(arg, min=0.0).sum(-1), arg.detach().max(-1).values
 
 
-def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evaluation:
+def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False, want_pairs: bool = False) -> Evaluation:
     """All terms of Eq. (2) for particles X [B, dim] (float64).
 
     Term order per pick-place step k (object o = object_of_step[k]):
@@ -334,6 +338,8 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
         sp = _t(sc.obj_spheres[o])
         return apply(O, sp[None, :, :3].expand(B, -1, 3)), sp[:, 3]
 
+    pargs = [] if want_pairs else None
+
     def config_collision(q, boxes, held=None):
         fr = fk_frames(r, q)
         c, rad = _robot_spheres(prob, fr)
@@ -341,7 +347,7 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
             G, o = held
             hc, hr = held_spheres(fr[-1], G, o)
             c, rad = torch.cat([c, hc], 1), torch.cat([rad, hr])
-        return _collision(c, rad, boxes, kinks, want_kinks)
+        return _collision(c, rad, boxes, kinks, want_kinks, pargs)
 
     def bounds_term(v, lo, hi):
         d = dist_from_bounds(v, lo, hi)
@@ -386,7 +392,7 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
         coll_p = config_collision(qp, boxes, (G, o))
         sp = _t(sc.obj_spheres[o])
         pc = apply(P[k], sp[None, :, :3].expand(B, -1, 3))
-        coll_o = _collision(pc, sp[:, 3], boxes, kinks, want_kinks)
+        coll_o = _collision(pc, sp[:, 3], boxes, kinks, want_kinks, pargs)
         cols += [pick_pos, pick_rot, place_pos, place_rot, grasp, place, jg, jp, coll_g, coll_p, coll_o]
         inf = torch.full((B,), math.inf, dtype=DT)
         flip_lo += [inf, inf, inf, inf, gap_g, inf, gap_jg, gap_jp, inf, inf, inf]
@@ -434,7 +440,7 @@ def evaluate(prob: Problem, X: torch.Tensor, want_kinks: bool = False) -> Evalua
 
     T = torch.stack(cols, 1)
     J = (T * _t(weights_vector(prob))).sum(1)
-    return Evaluation(terms=T, cost=J, kinks=kinks, flip_lo=flip_lo)
+    return Evaluation(terms=T, cost=J, kinks=kinks, flip_lo=flip_lo, pair_args=pargs)
 
 
 # ----------------------------------------------------------------------------
@@ -555,6 +561,20 @@ def phr_lagrangian(prob: Problem, X, mu, rho: float) -> np.ndarray:
     g = T[:, :nc] - tolerance_vector(prob)[None]
     pen = (np.maximum(0.0, mu[:, :nc] + rho * g) ** 2 - mu[:, :nc] ** 2).sum(1) / (2.0 * rho)
     return T @ weights_vector(prob) + pen
+
+
+def penetrating_pairs(prob: Problem, X, near: float = 1e-6):
+    """Per particle: the number of sphere-box pairs with positive penetration
+    max(0, r - sdf) over every collision term of Eq. (2) (robot, held-object
+    and placed-object spheres of every configuration against the boxes of
+    its step; waypoints included), and the number of pairs whose hinge
+    argument lies within `near` of zero (where FP32 may decide otherwise)."""
+    X = torch.as_tensor(np.asarray(X, dtype=np.float64))
+    with torch.no_grad():
+        ev = evaluate(prob, X, want_pairs=True)
+    pen = sum((a > 0).sum(-1) for a in ev.pair_args)
+    close = sum((a.abs() < near).sum(-1) for a in ev.pair_args)
+    return pen.numpy().astype(np.int64), close.numpy().astype(np.int64)
 
 
 def adam_step(x, m, v, g, t: int, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,

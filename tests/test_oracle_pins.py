@@ -613,3 +613,26 @@ def test_phr_weights_special_cases():
     np.testing.assert_allclose(O.phr_weights(prob, T, mu, 0.0)[:, :nc], np.broadcast_to(lam[:nc] + 0.25, (3, nc)))
     np.testing.assert_allclose(O.phr_weights(prob, T, mu, 2.0)[2, :nc], lam[:nc] + 0.25)
     np.testing.assert_allclose(O.phr_weights(prob, T, mu, 2.0)[0, :nc], lam[:nc] + 0.25 + 1.0)
+
+
+def test_penetrating_pairs_cover_exactly_the_collision_terms():
+    """The hinge arguments behind the penetrating-pair count are exactly the
+    pairs of the collision terms: their positive parts add up to the sum of
+    the CFreeHold, CFreePlace and motion terms, a particle counts no pair iff
+    those terms are zero, and no count exceeds the dense pair count."""
+    import torch
+    from paper_2411_11833_amd import workmodel
+    for prob in (_small_packing(), I.packing(robot_seed=1, scene_seed=2, n_objects=2, n_obstacles=2, waypoints=4)):
+        X = I.uniform_particles(prob, 64, seed=8).astype(np.float64)
+        pen, near = O.penetrating_pairs(prob, X)
+        ev = O.evaluate(prob, torch.as_tensor(X), want_pairs=True)
+        T = ev.terms.numpy()
+        K = prob.skeleton.n_steps
+        cols = [I.TERMS_PER_STEP * k + j for k in range(K) for j in (8, 9, 10)]
+        cols += list(range(I.TERMS_PER_STEP * K, I.TERMS_PER_STEP * K + prob.n_motion_terms))
+        coll = T[:, cols].sum(1)
+        hinge = sum(torch.clamp(a, min=0).sum(-1) for a in ev.pair_args).numpy()
+        np.testing.assert_allclose(hinge, coll, rtol=1e-12, atol=1e-15)
+        assert np.array_equal(pen == 0, coll == 0)
+        assert (pen > 0).any()
+        assert np.all(pen <= workmodel.per_particle_iteration(prob).pairs) and np.all(near >= 0)

@@ -221,6 +221,17 @@ int ct_cost(const ct_problem *problem, const float *X, int64_t n, int64_t ld, fl
             float *terms, uint8_t *mask, void *stream);
 
 /*
+ * Work measurement: pairs[i] = the number of (sphere, box) pairs of
+ * particle i whose penetration max(0, r - sdf) is positive, over every
+ * robot, held-object and placed-object sphere of every configuration and
+ * the boxes of its step (the pairs whose hinge has a non-zero derivative,
+ * i.e. the pairs the gradient of Eq. (2) has to visit; robot self-collision
+ * pairs are not counted).  Device int32[n]; layout and errors as ct_cost.
+ */
+int ct_penetrating_pairs(const ct_problem *problem, const float *X, int64_t n, int64_t ld, int32_t *pairs,
+                         void *stream);
+
+/*
  * Cost and its gradient dJ/dx per particle (not scaled by 1/N_b):
  * G [dim][ld].  With weights (device [n], may be NULL) column i of G is
  * weights[i] * dJ/dx_i -- the vector-Jacobian product a reverse-mode caller
@@ -291,6 +302,19 @@ int ct_autotune(ct_problem *problem, const float *X, int64_t n, int64_t ld, int3
                 void *stream);
 
 /*
+ * Eq. (3) per pick-place step, from terms as written by ct_cost ([n_terms][ld]):
+ * step_mask[k * ld_mask + i] = 1 iff every constraint term of step k of
+ * particle i is within its tolerance (K rows; the motion and self-collision
+ * terms belong to no step), and count[i] = the number of the particle's
+ * constraint terms within tolerance (a NaN term never is).  step_mask (device
+ * uint8, ld_mask >= n) and count (device int32[n]) may each be NULL.  Used to
+ * pick converged actions (learned-seed training data, compositional
+ * initialization).  Errors: CT_ERR_INVALID_ARG (layout as ct_cost).
+ */
+int ct_step_mask(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, uint8_t *step_mask,
+                 int64_t ld_mask, int32_t *count, void *stream);
+
+/*
  * Plan-skeleton feasibility heuristic, Eq. (5): counts[c] = number of
  * particles i < n whose constraint term c satisfies J_c <= eps_c (terms as
  * written by ct_cost, layout [n_terms][ld]; a NaN term never counts), for
@@ -342,11 +366,24 @@ int ct_feasibility_noalloc(const ct_problem *problem, const float *terms, int64_
  *   mu[c][i] = max(0, mu[c][i] + rho (J_c - eps_c))   (kept if J_c is NaN/inf)
  *   W[c][i]  = lambda_c + mu[c][i]
  * and W[c][i] = lambda_c for the soft costs (their mu rows are not touched).
- * Requires rho >= 0 and finite.
+ * Used alone between inner solves this is dual ascent on fixed weights.
+ *
+ * ct_al_weights gives the weights of the PHR augmented Lagrangian
+ *   L(x) = sum_c lambda_c J_c + (1 / (2 rho)) sum_c (max(0, mu_c + rho g_c)^2
+ *          - mu_c^2),  g_c = J_c - eps_c  (constraints only),
+ * whose gradient is sum_c W_c dJ_c/dx with
+ *   W[c][i] = lambda_c + max(0, mu[c][i] + rho (J_c - eps_c))
+ *   (lambda_c + mu[c][i] if J_c is NaN/inf; lambda_c for soft costs),
+ * evaluated at the terms given (the particles' latest), mu unchanged.  Called
+ * between short inner chunks it keeps the penalty on the current violation;
+ * ct_al_update then moves the multipliers every outer step.
+ * Both require rho >= 0 and finite; layouts as ct_cost.
  */
 int ct_set_term_weights(ct_problem *problem, const float *W, int64_t ld);
 int ct_al_update(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, float rho, float *mu,
                  float *W, void *stream);
+int ct_al_weights(const ct_problem *problem, const float *terms, int64_t n, int64_t ld, float rho,
+                  const float *mu, float *W, void *stream);
 
 /*
  * Compositional initialization (Sec. V): the particles of a skeleton are

@@ -89,9 +89,12 @@ def _load() -> C.CDLL:
         "ct_get_split": (C.c_int, [vp, C.POINTER(i32)]),
         "ct_autotune": (C.c_int, [vp, vp, i64, i64, C.POINTER(i32), vp]),
         "ct_feasibility": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
+        "ct_step_mask": (C.c_int, [vp, vp, i64, i64, vp, i64, vp, vp]),
+        "ct_penetrating_pairs": (C.c_int, [vp, vp, i64, i64, vp, vp]),
         "ct_feasibility_noalloc": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp]),
         "ct_set_term_weights": (C.c_int, [vp, vp, i64]),
         "ct_al_update": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
+        "ct_al_weights": (C.c_int, [vp, vp, i64, i64, C.c_float, vp, vp, vp]),
         "ct_compact": (C.c_int, [vp, i64, vp, vp, vp]),
         "ct_gather_block": (C.c_int, [vp, i64, i32, i64, vp, vp, vp, vp, vp, i64, i32, i64, vp]),
         "ct_batch_create": (C.c_int, [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
@@ -237,6 +240,14 @@ def ct_feasibility(h, terms, n, ld, penalty, counts=None, H=None, stream=0):
     _chk(LIB.ct_feasibility(h, terms, n, ld, penalty, counts, H, stream), "ct_feasibility")
 
 
+def ct_penetrating_pairs(h, X, n, ld, pairs, stream=0):
+    _chk(LIB.ct_penetrating_pairs(h, X, n, ld, pairs, stream), "ct_penetrating_pairs")
+
+
+def ct_step_mask(h, terms, n, ld, step_mask, ld_mask, count, stream=0):
+    _chk(LIB.ct_step_mask(h, terms, n, ld, step_mask, ld_mask, count, stream), "ct_step_mask")
+
+
 def ct_feasibility_noalloc(h, terms, n, ld, penalty, H, stream=0):
     _chk(LIB.ct_feasibility_noalloc(h, terms, n, ld, penalty, H, stream), "ct_feasibility_noalloc")
 
@@ -247,6 +258,10 @@ def ct_set_term_weights(h, W, ld):
 
 def ct_al_update(h, terms, n, ld, rho, mu, W, stream=0):
     _chk(LIB.ct_al_update(h, terms, n, ld, rho, mu, W, stream), "ct_al_update")
+
+
+def ct_al_weights(h, terms, n, ld, rho, mu, W, stream=0):
+    _chk(LIB.ct_al_weights(h, terms, n, ld, rho, mu, W, stream), "ct_al_weights")
 
 
 def ct_compact(mask, n, idx, count, stream=0):

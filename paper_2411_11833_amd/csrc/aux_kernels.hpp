@@ -158,6 +158,30 @@ __global__ __launch_bounds__(256) void al_update_kernel(const Tables* __restrict
     }
 }
 
+// Weights of the PHR augmented Lagrangian at the particles' current terms:
+// for the inequality g_c = J_c - eps_c <= 0 with multiplier mu_c >= 0 and
+// penalty rho, L = sum_c lambda_c J_c + (1 / 2 rho) sum_c (max(0, mu_c +
+// rho g_c)^2 - mu_c^2) has dL/dx = sum_c (lambda_c + max(0, mu_c + rho g_c))
+// dJ_c/dx, so W_c = lambda_c + max(0, mu_c + rho (J_c - eps_c)) (lambda_c +
+// mu_c when J_c is not finite); soft costs keep lambda_c.  mu is not changed.
+__global__ __launch_bounds__(256) void al_weights_kernel(const Tables* __restrict__ T, const float* __restrict__ terms,
+                                                         int64_t n, int64_t ld, float rho,
+                                                         const float* __restrict__ mu, float* __restrict__ W) {
+    const int64_t total = (int64_t)T->n_terms * n;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * 256) {
+        const int c = (int)(idx / n);
+        const int64_t a = (int64_t)c * ld + (idx - (int64_t)c * n);
+        const float lam = term_weight(T, c);
+        if (c < T->n_constraint) {
+            const float J = terms[a];
+            const float m = mu[a];
+            W[a] = lam + (__builtin_isfinite(J) ? fmaxf(0.f, fmaf(rho, J - term_eps(T, c), m)) : m);
+        } else {
+            W[a] = lam;
+        }
+    }
+}
+
 // Plan-skeleton feasibility, Eq. (5): one workgroup per constraint term
 // counts the particles with J_c <= eps_c (reads coalesced along particles; a
 // NaN term never counts), fixed-order tree reduction.
@@ -185,6 +209,32 @@ __global__ void feas_h_kernel(const int32_t* __restrict__ counts, int nc, float 
     float s = 0.f;
     for (int c = 0; c < nc; ++c) s += counts[c] > 0 ? (float)counts[c] : penalty;
     *H = nc > 0 ? s / (float)nc : 0.f;
+}
+
+// Eq. (3) restricted to each pick-place step: step_mask[k][i] = 1 iff every
+// constraint term of step k (its CT_TERMS_PER_STEP terms) is within its
+// tolerance; count[i] = how many of the particle's constraint terms are (a
+// NaN term never is).  One thread per particle, terms as ct_cost writes them.
+__global__ __launch_bounds__(256) void step_mask_kernel(const Tables* __restrict__ T,
+                                                        const float* __restrict__ terms, int64_t n, int64_t ld,
+                                                        uint8_t* __restrict__ step_mask, int64_t ld_mask,
+                                                        int32_t* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int total = 0;
+    for (int k = 0; k < T->K; ++k) {
+        int all = 1;
+        for (int j = 0; j < CT_TERMS_PER_STEP; ++j) {
+            const int c = CT_TERMS_PER_STEP * k + j;
+            const int ok = terms[(int64_t)c * ld + i] <= term_eps(T, c) ? 1 : 0;
+            all &= ok;
+            total += ok;
+        }
+        if (step_mask) step_mask[(int64_t)k * ld_mask + i] = (uint8_t)all;
+    }
+    for (int c = CT_TERMS_PER_STEP * T->K; c < T->n_constraint; ++c)
+        total += terms[(int64_t)c * ld + i] <= term_eps(T, c) ? 1 : 0;
+    if (count) count[i] = total;
 }
 
 // Indices of the set entries of a mask, in index order (one workgroup of

@@ -441,6 +441,19 @@ extern "C" int ct_al_update(const ct_problem* P, const float* terms, int64_t n, 
     return err_of(hipGetLastError());
 }
 
+extern "C" int ct_al_weights(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float rho,
+                             const float* mu, float* W, void* stream) {
+    if (empty_ok(P, n, ld) && std::isfinite(rho) && rho >= 0) return CT_OK;
+    if (!P || !terms || !mu || !W || !std::isfinite(rho) || rho < 0) return CT_ERR_INVALID_ARG;
+    if (!good_layout(terms, n, ld) || !good_layout(mu, n, ld) || !good_layout(W, n, ld)) return CT_ERR_INVALID_ARG;
+    if (n == 0) return CT_OK;
+    const int64_t total = (int64_t)P->n_terms * n;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(ct::al_weights_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, P->d, terms, n, ld,
+                       rho, mu, W);
+    return err_of(hipGetLastError());
+}
+
 extern "C" int ct_feasibility(const ct_problem* P, const float* terms, int64_t n, int64_t ld, float penalty,
                               int32_t* counts, float* H, void* stream) {
     if (!P || !std::isfinite(penalty)) return CT_ERR_INVALID_ARG;
@@ -497,6 +510,17 @@ extern "C" int ct_feasibility_noalloc(const ct_problem* P, const float* terms, i
     // every count is written (not accumulated), so nothing needs clearing
     hipLaunchKernelGGL(ct::feas_count_kernel, dim3(P->nc), dim3(256), 0, st, P->d, terms, n, ld, cnt);
     hipLaunchKernelGGL(ct::feas_h_kernel, dim3(1), dim3(64), 0, st, cnt, P->nc, penalty, H);
+    return err_of(hipGetLastError());
+}
+
+extern "C" int ct_step_mask(const ct_problem* P, const float* terms, int64_t n, int64_t ld, uint8_t* step_mask,
+                            int64_t ld_mask, int32_t* count, void* stream) {
+    if (!P || n < 0 || ld < n || ld % 64 != 0 || (n > 0 && !terms)) return CT_ERR_INVALID_ARG;
+    if (terms && ((uintptr_t)terms % 256)) return CT_ERR_INVALID_ARG;
+    if (step_mask && ld_mask < n) return CT_ERR_INVALID_ARG;
+    if (n == 0 || (!step_mask && !count)) return CT_OK;
+    hipLaunchKernelGGL(ct::step_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       P->d, terms, n, ld, step_mask, ld_mask, count);
     return err_of(hipGetLastError());
 }
 
@@ -558,6 +582,18 @@ extern "C" int ct_cost(const ct_problem* P, const float* X, int64_t n, int64_t l
     a.mask = mask;
     a.n = n;
     a.ld = ld;
+    return run_pk(P, ct::MODE_COST, a, (hipStream_t)stream);
+}
+
+extern "C" int ct_penetrating_pairs(const ct_problem* P, const float* X, int64_t n, int64_t ld, int32_t* pairs,
+                                    void* stream) {
+    if (empty_ok(P, n, ld)) return CT_OK;
+    if (!P || !X || !pairs || !good_layout(X, n, ld)) return CT_ERR_INVALID_ARG;
+    PkArgs a{};
+    a.X = const_cast<float*>(X);
+    a.n = n;
+    a.ld = ld;
+    a.hits = pairs;
     return run_pk(P, ct::MODE_COST, a, (hipStream_t)stream);
 }
 

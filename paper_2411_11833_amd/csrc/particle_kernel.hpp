@@ -168,7 +168,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
                                              uint32_t omask, const float (&cx)[NB], const float (&cy)[NB],
                                              const float (&cz)[NB], const float (&r)[NB], float lam,
                                              float (&pen_sum)[NB], float (&gx)[NB], float (&gy)[NB],
-                                             float (&gz)[NB], float* __restrict__ gr) {
+                                             float (&gz)[NB], float* __restrict__ gr, int& nhit) {
     float r2[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) r2[m] = r[m] * r[m];
@@ -193,6 +193,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
                     float pen, ax, ay, az;
                     pair_hit(px[m], py[m], pz[m], r[m], B.c, B.s, B.hx, B.hy, B.hz, lam, pen, ax, ay, az);
                     pen_sum[m] += pen;
+                    if (!GRAD) ++nhit;
                     if (GRAD) { gx[m] += ax; gy[m] += ay; gz[m] += az; }
                 }
             }
@@ -226,6 +227,7 @@ __device__ __forceinline__ void run_vs_world(const Tables* __restrict__ T, const
                     float pen, ax, ay, az;
                     pair_hit(px[m], py[m], pz[m], r[m], bc, bs, O.hx, O.hy, O.hz, lam, pen, ax, ay, az);
                     pen_sum[m] += pen;
+                    if (!GRAD) ++nhit;
                     if (GRAD) {
                         gx[m] += ax; gy[m] += ay; gz[m] += az;
                         if (placed) {
@@ -296,7 +298,7 @@ template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, const float4* __restrict__ rsl, int s0,
                                           int s1, int j0, int si, const float R[9], const float t[3],
                                           const MoveCtx<KT>& mc, uint32_t smask, uint32_t omask, float lam,
-                                          float& coll, float f[3], float tq[3], float* __restrict__ gr) {
+                                          float& coll, float f[3], float tq[3], float* __restrict__ gr, int& nhit) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -313,7 +315,7 @@ __device__ __forceinline__ void robot_run(const Tables* __restrict__ T, const fl
     float pen[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) pen[m] = 0.f;
-    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr, nhit);
 #pragma unroll
     for (int m = 0; m < NB; ++m) coll += pen[m];
     if (GRAD) {
@@ -335,7 +337,7 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, const
                                              const SBox* __restrict__ sbl, int L,
                                              int si, const float R[9], const float t[3], const MoveCtx<KT>& mc,
                                              float lam, float& coll, float f[3], float tq[3],
-                                             float* __restrict__ gr) {
+                                             float* __restrict__ gr, int& nhit) {
     const int s0 = T->link_start[L], s1 = T->link_start[L + 1];
     if (s1 == s0) return;
     const float4 lb = T->lbs[L];
@@ -348,13 +350,13 @@ __device__ __forceinline__ void link_spheres(const Tables* __restrict__ T, const
     int j = 0;
     constexpr int RUN = run_len<KT>();
     for (; j + RUN <= per_lane; j += RUN)
-        robot_run<KT, SPLIT, RUN, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, RUN, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
     if (RUN > 2 && j + 2 <= per_lane) {
-        robot_run<KT, SPLIT, 2, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, 2, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
         j += 2;
     }
     for (; j < per_lane; ++j)
-        robot_run<KT, SPLIT, 1, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        robot_run<KT, SPLIT, 1, GRAD>(T, rsl, s0, s1, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
 }
 
 // Runs of object spheres (table osl, object frame) transformed by (R, t):
@@ -364,7 +366,7 @@ template <int KT, int SPLIT, int NB, bool GRAD>
 __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const float4* __restrict__ osl, int nos,
                                            int j0, int si, const float R[9], const float t[3], const MoveCtx<KT>& mc,
                                            uint32_t smask, uint32_t omask, float lam, float& coll, float f[3],
-                                           float tq[3], float* __restrict__ gr) {
+                                           float tq[3], float* __restrict__ gr, int& nhit) {
     float cx[NB], cy[NB], cz[NB], rr[NB], gx[NB], gy[NB], gz[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
@@ -381,7 +383,7 @@ __device__ __forceinline__ void object_run(const Tables* __restrict__ T, const f
     float pen[NB];
 #pragma unroll
     for (int m = 0; m < NB; ++m) pen[m] = 0.f;
-    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr);
+    run_vs_world<KT, NB, GRAD>(T, mc, smask, omask, cx, cy, cz, rr, lam, pen, gx, gy, gz, gr, nhit);
 #pragma unroll
     for (int m = 0; m < NB; ++m) coll += pen[m];
     if (GRAD) {
@@ -399,7 +401,7 @@ template <int KT, int SPLIT, bool GRAD>
 __device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, const SBox* __restrict__ sbl,
                                                const float4* __restrict__ osl, int nos, float4 ob, int si, const float R[9], const float t[3],
                                                const MoveCtx<KT>& mc, float lam, float& coll, float f[3],
-                                               float tq[3], float* __restrict__ gr) {
+                                               float tq[3], float* __restrict__ gr, int& nhit) {
     if (nos <= 0) return;
     uint32_t smask, omask;
     touched_boxes<KT, SPLIT>(T, sbl, si, mc, R[0] * ob.x + R[1] * ob.y + R[2] * ob.z + t[0],
@@ -410,13 +412,13 @@ __device__ __forceinline__ void object_spheres(const Tables* __restrict__ T, con
     int j = 0;
     constexpr int RUN = run_len<KT>();
     for (; j + RUN <= per_lane; j += RUN)
-        object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        object_run<KT, SPLIT, RUN, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
     if (RUN > 2 && j + 2 <= per_lane) {
-        object_run<KT, SPLIT, 2, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        object_run<KT, SPLIT, 2, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
         j += 2;
     }
     for (; j < per_lane; ++j)
-        object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr);
+        object_run<KT, SPLIT, 1, GRAD>(T, osl, nos, j, si, R, t, mc, smask, omask, lam, coll, f, tq, gr, nhit);
 }
 
 // dist_from_bounds of v against [lo, hi] and its gradient (scaled by lam).
@@ -618,6 +620,7 @@ struct LaneOut {
     float cost;   // weighted sum of this slot's terms
     float traj;   // this slot's transition length (TrajLength share), 0 without motion
     int flags;    // bit 0: all of the slot's constraints hold; bit 1: finite
+    int hits;     // touching sphere-box pairs of the slot (cost mode), summed over its lanes
 };
 
 // The per-configuration part of a slot's work: forward kinematics link by
@@ -634,7 +637,7 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                                             float g_c, float g_s, float rho_x, float rho_y, float rho_c,
                                             float rho_s, float& coll, float gq[CT_N_JOINTS], float gg[4],
                                             float* __restrict__ gr, float& kin_pos, float& kin_rot,
-                                            const SlotW* slw, bool self, float& self_pen) {
+                                            const SlotW* slw, bool self, float& self_pen, int& nhit) {
     const int k = mc.k;
     // Joint axis S_j = (z_j, o_j x z_j) of joint j+1 (z of frame j through its
     // origin).  dJ/dq_j = <S_j, wrench of links j+1..8>
@@ -661,11 +664,11 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
         jsn[i] = sn;
         jcs[i] = cs;
         joint_advance(T, i, sn, cs, R, t);
-        link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, i + 1, si, R, t, mc, lam, coll, f, tq, gr);
+        link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, i + 1, si, R, t, mc, lam, coll, f, tq, gr, nhit);
     }
     // ---- tool frame: tool spheres, the held object, the kinematic constraint
     const float te[3] = {t[0] + R[2] * T->tool_d, t[1] + R[5] * T->tool_d, t[2] + R[8] * T->tool_d};
-    link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, 8, si, R, te, mc, lam, coll, f, tq, gr);
+    link_spheres<KT, SPLIT, GRAD>(T, rsl, sbl, 8, si, R, te, mc, lam, coll, f, tq, gr, nhit);
 
     if (held) {
         // held object frame O = F_ee G^-1, G = Trans(g) Rz(gyaw) Rx(pi); the
@@ -681,7 +684,8 @@ __device__ __forceinline__ void config_pass(const Tables* __restrict__ T, const 
                              te[1] - (RO[3] * gx + RO[4] * gy + RO[5] * gz),
                              te[2] - (RO[6] * gx + RO[7] * gy + RO[8] * gz)};
         float fo[3] = {0.f, 0.f, 0.f}, to[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, RO, tO, mc, lam, coll, fo, to, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, RO, tO, mc, lam, coll, fo, to, gr,
+                                        nhit);
         if (GRAD) {
             // d/dg: every held point moves by -R_O dg;  d/dgyaw: the held
             // object turns about the tool z-axis through the tool origin
@@ -848,6 +852,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
     for (int j = 0; j < CT_N_JOINTS; ++j) gq[j] = gqa[j] = 0.f;
     float gg[4] = {0.f, 0.f, 0.f, 0.f};
     float coll = 0.f, coll_m = 0.f, kin_pos = 0.f, kin_rot = 0.f, selfc = 0.f;
+    int nhit = 0;   // touching sphere-box pairs (cost mode only; the adjoint's work)
     const float4* osl_k = osl + k * CT_MAX_OBJ_SPHERES;
 
     // waypoints w = 1..W of the transition, then the configuration itself
@@ -867,7 +872,7 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const bool held = key || placing;
         const float lam = key ? (sw ? sw->coll : T->w[W_COLL]) : (sw ? sw->mcoll : T->w[W_MCOLL]);
         config_pass<KT, SPLIT, GRAD>(T, rsl, sbl, osl_k, si, q, held, key, placing, lam, mc, gx, gy, gz, g_c, g_s, rho_x, rho_y,
-                                     rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, sw, key && self_on, selfc);
+                                     rho_c, rho_s, cw, gw, gg, gr, kin_pos, kin_rot, sw, key && self_on, selfc, nhit);
         if (key) coll += cw; else coll_m += cw;
         if (GRAD) {
 #pragma unroll
@@ -923,7 +928,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         const float Rp[9] = {rho_c, -rho_s, 0.f, rho_s, rho_c, 0.f, 0.f, 0.f, 1.f};
         const float tp[3] = {rho_x, rho_y, T->place_z[k]};
         float fp[3] = {0.f, 0.f, 0.f}, mp[3] = {0.f, 0.f, 0.f};
-        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, Rp, tp, mc, lc, coll_obj, fp, mp, gr);
+        object_spheres<KT, SPLIT, GRAD>(T, sbl, osl_k, T->n_os, T->obs[k], si, Rp, tp, mc, lc, coll_obj, fp, mp, gr,
+                                        nhit);
         if (GRAD) {
             // translation: the force; turning about the vertical through the
             // placement origin: z of the moment about that point
@@ -1005,6 +1011,8 @@ __device__ __forceinline__ LaneOut lane_slot(const Tables* __restrict__ T, const
         ok = ok && place <= e[E_PLACE];
     }
     out.traj = traj;
+    out.hits = 0;
+    if (!GRAD) out.hits = (int)split_sum<SPLIT>((float)nhit);   // exact: small integers
     // a slot is finite when its own cost and every lane's partials are
     const float gtot = split_sum<SPLIT>(gsum);
     const bool fin = __builtin_isfinite(out.cost) && __builtin_isfinite(gtot);
@@ -1055,6 +1063,7 @@ struct TileSmem {
     float cpart[WG / SPLIT];
     float tpart[WG / SPLIT];
     int flg[WG / SPLIT];
+    int hpart[WG / SPLIT];
     int okp[128 / SPLIT];
     float4 osl[CT_MAX_STEPS * CT_MAX_OBJ_SPHERES];
     int any_sat;
@@ -1072,6 +1081,7 @@ struct TileIO {
     float gscale;
     const float* wts;   // per-particle term weights [n_terms][ld] (extended kernels), or null
     int keep_sat = 0;   // stop-at-first: a satisfying particle is not updated, so X keeps it
+    int32_t* hits = nullptr;   // cost mode: touching sphere-box pairs per particle, or null
 };
 
 
@@ -1153,6 +1163,7 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
                 sm.cpart[p * SLOTS + slot] = o.cost;
                 sm.tpart[p * SLOTS + slot] = o.traj;
                 sm.flg[p * SLOTS + slot] = o.flags;
+                if (MODE == MODE_COST) sm.hpart[p * SLOTS + slot] = o.hits;
             }
         }
     }
@@ -1181,6 +1192,11 @@ __device__ __forceinline__ void run_tile(const TileIO& io, int64_t p0, TileSmem<
             }
             if (io.cost) io.cost[i] = J;
             if (io.mask) io.mask[i] = (uint8_t)m;
+            if (MODE == MODE_COST && io.hits) {
+                int h = 0;
+                for (int s = 0; s < SLOTS; ++s) h += sm.hpart[tid * SLOTS + s];
+                io.hits[i] = h;
+            }
             if (m) sm.any_sat = 1;
         }
     }
@@ -1240,7 +1256,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
     int32_t* __restrict__ first_sat, const uint8_t* __restrict__ frozen, int64_t n, int64_t ld, float lr,
     float b1, float b2, float eps, float gscale, int32_t t_arg, const int32_t* __restrict__ t_in,
     int32_t* __restrict__ t_out, int32_t stop_at_first, const float* __restrict__ gw,
-    const float* __restrict__ wts) {
+    const float* __restrict__ wts, int32_t* __restrict__ hits) {
     __shared__ TileSmem<SPLIT> sm;
     // update number t: explicit, or one past the device counter of applied
     // updates; a captured loop alternates two counter slots (read t_in,
@@ -1256,7 +1272,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2))) void pa
     // that share cache lines of X, M and V then share one L2
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const TileIO io{T, X, M, V, G, cost, terms, mask, first_sat, frozen, gw, n, ld, gscale, EXT ? wts : nullptr,
-                    stop_at_first ? 1 : 0};
+                    stop_at_first ? 1 : 0, MODE == MODE_COST ? hits : nullptr};
     run_tile<KT, SPLIT, MODE, EXT>(io, tile * tile_particles(KT, SPLIT), sm, lr, b1, b2, eps, t);
 }
 

@@ -23,6 +23,7 @@ struct PkArgs {
     int32_t stop_at_first;   // skip the step if an earlier iteration satisfied
     const float* gw;         // per-particle gradient weights (gradient mode), or null
     const float* wts;        // per-particle term weights [n_terms][ld] (extended kernels), or null
+    int32_t* hits;           // cost mode: touching sphere-box pairs per particle, or null
 };
 
 // one skeleton of a given length (each length has its own kernels)

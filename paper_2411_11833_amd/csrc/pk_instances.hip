@@ -20,7 +20,7 @@ hipError_t launch_pk(const ct::Tables* T, const PkArgs& g, hipStream_t st) {
     const dim3 grid((unsigned)((g.n + P - 1) / P));
     hipLaunchKernelGGL((ct::particle_kernel<S, MODE, K, CT_EXT != 0>), grid, dim3(ct::WG), 0, st, T, g.X, g.M, g.V, g.G, g.cost,
                        g.terms, g.mask, g.first_sat, g.frozen, g.n, g.ld, g.a.lr, g.a.b1, g.a.b2, g.a.eps, g.a.gs,
-                       g.t, g.t_in, g.t_out, g.stop_at_first, g.gw, g.wts);
+                       g.t, g.t_in, g.t_out, g.stop_at_first, g.gw, g.wts, g.hits);
     return hipGetLastError();
 }
 

@@ -94,6 +94,23 @@ class GpuProblem:
                          counts.data_ptr(), H.data_ptr(), _stream())
         return counts, H
 
+    def penetrating_pairs(self, X, n: int):
+        """Penetrating sphere-box pairs per particle (int32 [n])."""
+        out = torch.empty(n, dtype=torch.int32, device=self.device)
+        B.ct_penetrating_pairs(self.handle, X.data_ptr(), n, X.shape[1], out.data_ptr(), _stream())
+        return out
+
+    def step_mask(self, terms, n: int):
+        """Eq. (3) per pick-place step ([K, ld] uint8) and the count of
+        satisfied constraint terms per particle (int32 [n]), from ct_cost's
+        terms (ct_step_mask)."""
+        K = self.prob.skeleton.n_steps
+        sm = torch.empty((K, terms.shape[1]), dtype=torch.uint8, device=self.device)
+        cnt = torch.empty(n, dtype=torch.int32, device=self.device)
+        B.ct_step_mask(self.handle, terms.data_ptr(), n, terms.shape[1], sm.data_ptr(), sm.shape[1], cnt.data_ptr(),
+                       _stream())
+        return sm, cnt
+
     def set_term_weights(self, W):
         """Per-particle term weights [n_terms][ld] (device, kept alive by the
         caller) for every later cost / gradient / step call, or None for the
@@ -105,6 +122,11 @@ class GpuProblem:
         """Method-of-multipliers step on the constraint weights (device)."""
         B.ct_al_update(self.handle, terms.data_ptr(), n, terms.shape[1], float(rho), mu.data_ptr(), W.data_ptr(),
                        _stream())
+
+    def al_weights(self, terms, n: int, rho: float, mu, W):
+        """PHR augmented-Lagrangian weights at the given terms (device)."""
+        B.ct_al_weights(self.handle, terms.data_ptr(), n, terms.shape[1], float(rho), mu.data_ptr(), W.data_ptr(),
+                        _stream())
 
     def cost_grad(self, X, n: int, weights=None):
         c = torch.empty(n, dtype=torch.float32, device=self.device)
@@ -322,15 +344,24 @@ def _result(gp, X, mask, n, flag, iters, wall, start, events, chunk, stopped) ->
 
 
 def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, outer: int = 50, chunk: int = 10,
-             adam: B.CtAdam | None = None, fixed_grasps: bool = True, init=None) -> SolveResult:
-    """The plain method with augmented-Lagrangian constraint weights: Adam on
-    sum_c W_c J_c per particle, where every `outer` iterations the
-    multipliers take one method-of-multipliers step from the particles'
-    current terms (mu <- max(0, mu + rho (J - eps)), W = lambda + mu).
+             adam: B.CtAdam | None = None, fixed_grasps: bool = True, init=None, mode: str = "phr") -> SolveResult:
+    """The plain method with Lagrangian constraint weights: Adam on
+    sum_c W_c J_c per particle.  Every `outer` iterations the multipliers
+    take one method-of-multipliers step from the particles' current terms,
+    mu <- max(0, mu + rho (J - eps)).
+      mode "phr"  the PHR augmented Lagrangian: after every chunk the weights
+                  are re-formed at the current terms,
+                  W = lambda + max(0, mu + rho (J - eps)) (ct_al_weights),
+                  the gradient weights of L = sum lambda J
+                  + (1/2rho) sum (max(0, mu + rho g)^2 - mu^2);
+      mode "dual" W = lambda + mu, fixed between multiplier steps (dual
+                  ascent on the weights).
     Stops at the first satisfying particle (unweighted Eq. (3)) like
-    plain_solve; the weights start at lambda.  Uniform seeds, or
-    `init(X, M, V)` (timed with the solve).  `outer` must be a multiple of
-    `chunk` (the multipliers move between captured chunks)."""
+    plain_solve.  Uniform seeds, or `init(X, M, V)` (timed with the solve).
+    `outer` must be a multiple of `chunk` (weights move between captured
+    chunks)."""
+    if mode not in ("phr", "dual"):
+        raise ValueError(f"mode must be 'phr' or 'dual', not {mode!r}")
     if outer <= 0 or chunk <= 0 or outer % chunk:
         raise ValueError(f"outer ({outer}) must be a positive multiple of chunk ({chunk})")
     adam = adam or default_adam(n)
@@ -354,6 +385,8 @@ def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, o
     gp.set_term_weights(None)
     B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), terms.data_ptr(), None, _stream())
     gp.al_update(terms, n, 0.0, mu, W)            # W = lambda
+    if mode == "phr":
+        gp.al_weights(terms, n, rho, mu, W)       # W = lambda + max(0, rho (J - eps))
     gp.set_term_weights(W)
     events = []
     done = 0
@@ -366,10 +399,14 @@ def al_solve(gp: GpuProblem, n: int, iters: int, seed: int, rho: float = 10.0, o
             e = torch.cuda.Event(enable_timing=True)
             e.record(stream)
             events.append(e)
-            if done % outer == 0 and done < iters:
+            update = done % outer == 0
+            if done < iters and (update or mode == "phr"):
                 B.ct_cost(gp.handle, X.data_ptr(), n, X.shape[1], cost.data_ptr(), terms.data_ptr(), None,
                           _stream())
-                gp.al_update(terms, n, rho, mu, W)
+                if update:
+                    gp.al_update(terms, n, rho, mu, W)
+                if mode == "phr":
+                    gp.al_weights(terms, n, rho, mu, W)
         torch.cuda.synchronize()
     finally:
         gp.set_term_weights(None)

@@ -191,13 +191,10 @@ def collect(scene_seeds, robot_seed: int = 0, n: int = 1024, iters: int = 1000, 
             gp = gb.gps[j]
             cost, terms, _ = gp.cost(gb.X[j], n, terms=True)
             nc = prob.n_constraint_terms
-            eps = torch.tensor(_tolerances(prob), dtype=torch.float32, device=gp.device)
-            sat = terms[:nc, :n] <= eps[:, None]
-            K = prob.skeleton.n_steps
-            steps = sat[:I.TERMS_PER_STEP * K].view(K, I.TERMS_PER_STEP, n).all(1)      # [K, n]
+            steps, sat_count = gp.step_mask(terms, n)                                    # Eq. (3) per step
             c = torch.nan_to_num(cost[:n], nan=float("inf")).cpu().numpy()
-            k = sat.sum(0).cpu().numpy()
-            st = steps.cpu().numpy()
+            k = sat_count.cpu().numpy()
+            st = steps[:, :n].cpu().numpy().astype(bool)
             ns = st.sum(0)
             order = np.lexsort((c, -k, -ns))[:keep]
             order = order[ns[order] > 0]
@@ -283,13 +280,6 @@ def collect_steps(scene_seeds, robot_seed: int = 0, n: int = 1024, iters: int = 
         raise RuntimeError("no one-step skeleton produced a satisfying particle")
     return Dataset(np.stack([I.scene_features(p) for p in packs]), wrap_angles(np.concatenate(rows), wrap),
                    np.concatenate(wts), np.concatenate(sc), np.concatenate(nsat), 0, t_gpu)
-
-
-def _tolerances(prob: I.Problem) -> list[float]:
-    t = prob.tolerances
-    per = [t.kin_pos, t.kin_rot, t.kin_pos, t.kin_rot, t.grasp, t.place, t.jlim, t.jlim, t.coll, t.coll, t.coll]
-    return (per * prob.skeleton.n_steps + [t.motion_coll] * prob.n_motion_terms +
-            [t.self_coll] * prob.n_self_terms)
 
 
 def merge(a: Dataset, b: Dataset) -> Dataset:
@@ -434,14 +424,10 @@ def step_convergence(gp: GpuProblem, X, n: int) -> tuple[float, int]:
     """Fraction of (particle, pick-place step) pairs whose step satisfies all
     its constraints (Eq. 3 restricted to the step), and the largest number of
     such steps in one particle."""
-    prob = gp.prob
     _, terms, _ = gp.cost(X, n, terms=True)
-    K = prob.skeleton.n_steps
-    eps = torch.tensor(_tolerances(prob), dtype=torch.float32, device=gp.device)
-    nc = I.TERMS_PER_STEP * K
-    ok = (terms[:nc, :n] <= eps[:nc, None]).view(K, I.TERMS_PER_STEP, n).all(1)
-    per = ok.sum(0)
-    return float(ok.float().mean().item()), int(per.max().item())
+    steps, _ = gp.step_mask(terms, n)
+    per = steps[:, :n].sum(0, dtype=torch.int32)
+    return float(steps[:, :n].float().mean().item()), int(per.max().item())
 
 
 def compare(prop: Proposer, scene_seeds, n: int = 8192, budget: int = 500, robot_seed: int = 0,

@@ -1,6 +1,7 @@
-"""GPU parity of the augmented-Lagrangian mode with the FP64 oracle, through
+"""GPU parity of the Lagrangian weight modes with the FP64 oracle, through
 the C ABI: per-particle term weights in place of lambda (cost, gradient,
-fused step, captured loop) and the method-of-multipliers update.  Tolerances
+fused step, captured loop), the method-of-multipliers update and the PHR
+augmented-Lagrangian weights.  Tolerances
 as in the other parity tests: costs 1e-4 relative + 2e-6, gradients 1e-3
 relative (kink margin >= 1e-5), one Adam update 1e-5 absolute; the
 multiplier update is elementwise FP32 (one fused multiply-add, a max and an
@@ -128,6 +129,33 @@ def test_al_update_matches_oracle():
     assert np.any(mug == 0) and np.any(mug > mu0)
 
 
+def test_phr_weights_match_oracle():
+    """ct_al_weights against the oracle's PHR weights on the GPU's own FP32
+    terms (both branches of the hinge, a NaN term, soft costs)."""
+    prob = _cases()["motion"]
+    prob.skeleton.goal_cost = 1
+    n = 300
+    gp = _gp(prob)
+    X = I.uniform_particles(prob, n, seed=47)
+    _, T, _ = gp.cost(gp.from_rows(X), n, terms=True)
+    Th = gp.to_rows(T, n).cpu().numpy()
+    Th[7, 2] = np.nan
+    T[:, :n] = torch.from_numpy(np.ascontiguousarray(Th.T)).cuda()
+    mu0 = np.random.default_rng(48).uniform(0, 2, Th.shape).astype(np.float32)
+    mu = gp.empty(n, rows=prob.n_terms)
+    mu[:, :n] = torch.from_numpy(np.ascontiguousarray(mu0.T)).cuda()
+    W = gp.empty(n, rows=prob.n_terms)
+    gp.al_weights(T, n, 3.0, mu, W)
+    torch.cuda.synchronize()
+    Wo = O.phr_weights(prob, Th.astype(np.float64), mu0.astype(np.float64), 3.0)
+    Wg = gp.to_rows(W, n).cpu().numpy()
+    assert np.all(np.abs(Wg - Wo) <= 1e-6 * np.abs(Wo) + 1e-7)
+    assert np.array_equal(gp.to_rows(mu, n).cpu().numpy(), mu0)     # mu untouched
+    lam = O.weights_vector(prob)
+    nc = prob.n_constraint_terms
+    assert np.any(Wg[:, :nc] == lam[None, :nc]) and np.any(Wg[:, :nc] > lam[None, :nc] + mu0[:, :nc])
+
+
 def test_weights_with_another_ld_are_rejected():
     from paper_2411_11833_amd.binding import CtError
     prob = _cases()["single"]
@@ -144,9 +172,10 @@ def test_al_solve_runs_and_reports_a_valid_solution():
     from paper_2411_11833_amd.planner import al_solve
     prob = _cases()["single"]
     gp = _gp(prob)
-    r = al_solve(gp, 256, 3000, seed=7, rho=10.0, outer=50)
-    print("al_solve single:", r)
-    assert r.first_sat_iter is not None and r.n_satisfied >= 1
+    for mode in ("phr", "dual"):
+        r = al_solve(gp, 256, 3000, seed=7, rho=10.0, outer=50, mode=mode)
+        print(f"al_solve single ({mode}):", r.first_sat_iter, r.n_satisfied)
+        assert r.first_sat_iter is not None and r.n_satisfied >= 1
 
 
 def test_al_weights_reach_a_satisfying_particle_sooner_than_fixed_weights():
@@ -160,10 +189,11 @@ def test_al_weights_reach_a_satisfying_particle_sooner_than_fixed_weights():
     budget = 3000
     for seed in (4242, 4243, 4244):
         r_fixed = plain_solve(gp, 256, budget, seed=seed)
-        r_al = al_solve(gp, 256, budget, seed=seed, rho=10.0, outer=50)
-        print(f"seed {seed}: fixed lambda {r_fixed.first_sat_iter}, multipliers {r_al.first_sat_iter}")
-        assert r_al.first_sat_iter is not None
-        assert r_fixed.first_sat_iter is None or r_al.first_sat_iter < r_fixed.first_sat_iter
+        for mode in ("phr", "dual"):
+            r_al = al_solve(gp, 256, budget, seed=seed, rho=10.0, outer=50, mode=mode)
+            print(f"seed {seed}: fixed lambda {r_fixed.first_sat_iter}, {mode} {r_al.first_sat_iter}")
+            assert r_al.first_sat_iter is not None
+            assert r_fixed.first_sat_iter is None or r_al.first_sat_iter < r_fixed.first_sat_iter
 
 
 def test_many_skeleton_calls_use_lambda_even_with_weights_set():

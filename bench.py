@@ -62,16 +62,20 @@ STEP_SOURCES = ("paper_2411_11833_amd/csrc/particle_kernel.hpp", "paper_2411_118
                 "paper_2411_11833_amd/csrc/pk_instances.hip")
 
 
-def step_traffic_bytes():
-    """Measured bytes per launch, or None when the kernel sources changed
-    since the counters were taken."""
+def step_sources_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
     for f in STEP_SOURCES:
         with open(os.path.join(root, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != STEP_TRAFFIC["sources"]:
+    return h.hexdigest()[:16]
+
+
+def step_traffic_bytes():
+    """Measured bytes per launch, or None when the kernel sources changed
+    since the counters were taken."""
+    if step_sources_hash() != STEP_TRAFFIC["sources"]:
         return None
     t = STEP_TRAFFIC
     return (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"]) * 1024.0
@@ -98,6 +102,7 @@ def parse():
     ap.add_argument("--al-outer", type=int, default=50, help="iterations between multiplier updates")
     ap.add_argument("--batch-iters", type=int, default=300)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed measurement")
+    ap.add_argument("--no-config1", action="store_true", help="skip the 256-particle single pick-place line")
     ap.add_argument("--no-sampling", action="store_true", help="skip the compositional-initialization measurement")
     ap.add_argument("--sampling-rounds", type=int, default=3,
                     help="composed batches the Sampling baseline draws per scene")
@@ -123,30 +128,127 @@ def log(msg, quiet=False):
         print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, budget_s: float):
-    """The FP64 oracle (cost, autodiff gradient, Adam) as it stands, on a
-    bounded sample of the same workload: 64-particle batches of the same
-    scene, repeated until ~budget_s of CPU work."""
+def cpu_baseline(prob, budget_s: float, robot_seed: int = 0):
+    """The FP64 oracle (cost, autodiff gradient, Adam) as it stands, on the
+    host cores: a bounded sample of the benchmark workload on all threads
+    torch uses (64-particle batches of the same packing CSP, ~budget_s), the
+    same on one thread (~budget_s / 3), and configuration 1 (single
+    pick-place, 256 particles, 100 iterations) in full on all threads; the
+    full packing run (8192 particles x 500 iterations) is extrapolated from
+    the sample's rate, not run."""
     import torch
     import oracle as O
     from paper_2411_11833_amd import inputs as I
 
-    n = 64
-    X = I.uniform_particles(prob, n, seed=99).astype(np.float64)
-    M, V = np.zeros_like(X), np.zeros_like(X)
-    t0 = time.perf_counter()
-    it = 0
-    while True:
-        _, G = O.cost_and_grad(prob, X)
-        X, M, V = O.adam_step(X, M, V, G, it + 1, grad_scale=1.0 / n)
-        it += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n * it / dt, "unit": "particle-iters/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} particles x {it} iterations of the same 84-D packing CSP, FP64 autodiff, "
-                      f"{dt:.1f} s"}
+    def rate(p, n, budget, max_iters=None):
+        X = I.uniform_particles(p, n, seed=99).astype(np.float64)
+        M, V = np.zeros_like(X), np.zeros_like(X)
+        t0 = time.perf_counter()
+        it = 0
+        while True:
+            _, G = O.cost_and_grad(p, X)
+            X, M, V = O.adam_step(X, M, V, G, it + 1, grad_scale=1.0 / n)
+            it += 1
+            if (max_iters is not None and it >= max_iters) or (max_iters is None and
+                                                                 time.perf_counter() - t0 >= budget):
+                break
+        dt = time.perf_counter() - t0
+        return n * it / dt, it, dt
+
+    threads = torch.get_num_threads()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    v_all, it_all, dt_all = rate(prob, 64, budget_s)
+    torch.set_num_threads(1)
+    try:
+        v_one, it_one, dt_one = rate(prob, 64, budget_s / 3)
+    finally:
+        torch.set_num_threads(threads)
+    single = I.single_pick_place(robot_seed, 0)
+    v_c1, _, dt_c1 = rate(single, 256, None, max_iters=100)
+    return {"value": v_all, "unit": "particle-iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"64 particles x {it_all} iterations of the same 84-D packing CSP, FP64 autodiff, "
+                      f"{dt_all:.1f} s on {threads} threads",
+            "nproc": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "one_core": {"value": v_one, "sample": f"64 particles x {it_one} iterations, {dt_one:.1f} s"},
+            "config1_full": {"value": v_c1, "seconds": dt_c1,
+                             "run": "single pick-place scene 0, 256 particles x 100 iterations, all threads"},
+            "config2_full_extrapolated_s": 8192 * 500 / v_all}
+
+
+def config1_line(args, dev, q):
+    """Single pick-place, 256 particles, 100 plain-method iterations on each
+    of scenes 0-9 (uniform seeds 1000 + scene): GPU time per iteration and
+    the satisfied particles at iteration 100.  At 256 particles the launch
+    uses a sliver of the chip: latency-bound, no roofline."""
+    import torch
+    from paper_2411_11833_amd import inputs as I
+    from paper_2411_11833_amd.planner import GpuProblem, default_adam, grasp_frozen, INT32_MAX
+    n, iters = 256, 100
+    us, sat, first = [], [], []
+    stream = torch.cuda.current_stream()
+    for s in range(10):
+        prob = I.single_pick_place(args.robot_seed, s)
+        gp = GpuProblem(prob, dev)
+        X, M, V = gp.empty(n), gp.empty(n), gp.empty(n)
+        cost = torch.empty(n, dtype=torch.float32, device=dev)
+        mask = torch.empty(n, dtype=torch.uint8, device=dev)
+        flag = torch.full((1,), INT32_MAX, dtype=torch.int32, device=dev)
+        fz = grasp_frozen(prob, dev)
+        adam = default_adam(n)
+        gp.seed_uniform(1000 + s, X, M, V, n)
+        gp.optimize(X, M, V, n, 0, iters, adam, frozen=fz, cost=cost, mask=mask, first_sat=flag)   # captures
+        gp.seed_uniform(1000 + s, X, M, V, n)
+        flag.fill_(INT32_MAX)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        gp.optimize(X, M, V, n, 0, iters, adam, frozen=fz, cost=cost, mask=mask, first_sat=flag)
+        e1.record(stream)
+        _, _, m_end = gp.cost(X, n)
+        torch.cuda.synchronize()
+        us.append(e0.elapsed_time(e1) * 1e3 / iters)
+        sat.append(int(m_end.sum().item()))
+        f = int(flag.item())
+        first.append(None if f == INT32_MAX else f)
+        gp.close()
+    res = {"workload": "single pick-place (1 step, 21-D, 40 robot spheres, 1 obstacle + table), 256 particles, "
+                       "100 Adam iterations, scenes 0-9, uniform seeds 1000 + scene",
+           "us_per_iter": us, "median_us_per_iter": float(np.median(us)),
+           "particle_iters_per_s": n / (float(np.median(us)) * 1e-6),
+           "satisfied_at_iter_100": sat, "first_sat_iter": first,
+           "bound": "latency: 256 particles fill 32 of 256 compute units' worth of workgroups; no roofline"}
+    log(f"[bench] config 1 (256 particles, single pick-place): {res['median_us_per_iter']:.1f} us/iter, "
+        f"satisfied at iteration 100: {sat}", q)
+    return res
+
+
+# VALU counters of one step-kernel launch (packing, 8192 particles, split 2)
+# from rocprofv3 (SQ_INSTS_VALU, SQ_THREAD_CYCLES_VALU, medians over the
+# launches of one run); valid only for the kernel sources they were taken on.
+STEP_VALU = {"sources": None, "valu_insts": None, "thread_cycles_valu": None}
+MI355X_SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+
+
+def step_executed(kernel_s):
+    """Executed VALU work of the step kernel from its counters: wave
+    instructions per launch against the chip's issue rate (one wave64 FP32
+    instruction per SIMD every 4 cycles) and active lane-instructions against
+    the non-packed lane rate (256 CU x 4 SIMD x 16 lanes x 2.4 GHz).  None
+    when the counters were taken on other kernel sources."""
+    if STEP_VALU["sources"] is None or step_sources_hash() != STEP_VALU["sources"]:
+        return None
+    insts = STEP_VALU["valu_insts"]
+    lanes = STEP_VALU["thread_cycles_valu"]   # quad-cycle units: one per active lane of a FP32 instruction
+    issue_rate = MI355X_SIMDS * CLOCK_HZ / 4.0
+    lane_rate = MI355X_SIMDS * 16 * CLOCK_HZ
+    return {"valu_wave_insts": insts, "lane_utilization": lanes / (64.0 * insts),
+            "issue_frac": insts / kernel_s / issue_rate, "lane_frac_unpacked": lanes / kernel_s / lane_rate,
+            "source": "rocprofv3 SQ_INSTS_VALU, SQ_THREAD_CYCLES_VALU (profiles/)"}
 
 
 def _learned_family(SD, I, torch, dev, lg, name, make, d_out, collect, rounds, steps, n_eval, eval_scenes,
@@ -475,11 +577,27 @@ def main():
     value = n * iters * args.steps / elapsed
     log(f"[bench] timed {args.steps} solves: {elapsed:.3f} s -> {value:.4g} particle-iters/s", q)
 
+    # the same solves with the grasps optimized too (no frozen dimensions)
+    def solve_free(seed):
+        flag.fill_(INT32_MAX)
+        gp.seed_uniform(seed, X, M, V, n)
+        gp.optimize(X, M, V, n, 0, iters, adam, frozen=None, cost=cost, mask=mask, first_sat=flag)
+
+    solve_free(9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        solve_free(200 + s)
+    torch.cuda.synchronize()
+    value_free = n * iters * args.steps / (time.perf_counter() - t0)
+    log(f"[bench] grasps optimized too: {value_free:.4g} particle-iters/s", q)
+
     # ---- the fused step kernel alone: HIP events on its stream
     reps = 200
     gp.seed_uniform(7, X, M, V, n)
     for t in range(1, 11):
         gp.step(X, M, V, n, t, adam, frozen=frozen)
+    pen_first = float(gp.penetrating_pairs(X, n).double().mean().item())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for t in range(11, 11 + reps):
@@ -487,10 +605,15 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     kernel_s = e0.elapsed_time(e1) / 1e3 / reps
+    pen_last = float(gp.penetrating_pairs(X, n).double().mean().item())
     wk = workmodel.per_particle_iteration(prob)
     achieved = wk.flops * n / kernel_s / 1e12
+    pen_mean = 0.5 * (pen_first + pen_last)
+    method_flops = workmodel.method_flops(wk, pen_mean)
     log(f"[bench] step kernel: {kernel_s * 1e6:.1f} us avg over {reps} launches; "
-        f"{achieved:.2f} TFLOP/s (model {wk.flops} flop/particle-iter)", q)
+        f"{achieved:.2f} TFLOP/s (dense model {wk.flops} flop/particle-iter, an upper bound); method work "
+        f"{method_flops:.0f} flop/particle-iter ({pen_mean:.0f} penetrating pairs) -> "
+        f"{method_flops * n / kernel_s / 1e12:.2f} TFLOP/s", q)
 
     # ---- plan-skeleton feasibility heuristic (Eq. 5) on the solved particles
     _, terms_b, _ = gp.cost(X, n, terms=True)
@@ -745,6 +868,8 @@ def main():
         for v in tts.values():
             v["speedup"] = (v["uniform_s"] / v["learned_s"]) if (v["uniform_s"] and v["learned_s"]) else None
 
+    config1 = None if args.no_config1 else config1_line(args, dev, q)
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -781,14 +906,28 @@ def main():
         "compositional_init": sampling,
         "learned_seeds": learned,
         "time_to_satisfy_learned_vs_uniform": tts or None,
+        "grasps_optimized": {"particle_iters_per_s": value_free,
+                             "note": "the same solves with no frozen dimensions (grasps optimized too)"},
+        "config1_single_pick_place": config1,
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_VECTOR_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+            "model": "dense upper bound: every sphere-box pair with its 25-flop adjoint; the kernel skips culled "
+                     "pairs and the adjoint of pairs that do not penetrate",
             "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
             "frac_unpacked": achieved / PEAK_FP32_UNPACKED_TFLOPS,
+            "method": {"flop_per_particle_iter": method_flops,
+                       "penetrating_pairs_per_particle": pen_mean,
+                       "penetrating_pairs_first_last": [pen_first, pen_last],
+                       "achieved": method_flops * n / kernel_s / 1e12,
+                       "frac": method_flops * n / kernel_s / 1e12 / PEAK_FP32_VECTOR_TFLOPS,
+                       "frac_unpacked": method_flops * n / kernel_s / 1e12 / PEAK_FP32_UNPACKED_TFLOPS,
+                       "note": "every pair's forward test plus the adjoint of the pairs that penetrate "
+                               "(counted on the GPU at iterations 10 and 210 of the timed launches, mean)"},
+            "executed": step_executed(kernel_s) if (split == 2 and n == 8192) else None,
             "traffic": step_traffic_bytes() if (split == 2 and n == 8192) else None,
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": f"ct::particle_kernel<{split},MODE_STEP,4,false>",
@@ -800,7 +939,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle ...", q)
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds, args.robot_seed)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -66,3 +66,10 @@ def per_particle_iteration(prob: I.Problem) -> Work:
         flops += 2 * K * self_pair_count(prob.robot.sphere_link) * (SELF_FWD + SELF_BWD)
     nbytes = 24 * prob.dim + 5
     return Work(pairs=pairs, sphere_instances=inst, configs=configs, flops=flops, bytes=nbytes)
+
+
+def method_flops(w: Work, penetrating_pairs: float) -> float:
+    """Flops the method itself needs per particle-iteration: every pair's
+    forward test, the adjoint only of the pairs that penetrate (the hinge
+    has zero derivative elsewhere), and the rest of the dense model."""
+    return w.flops - w.pairs * PAIR_BWD + penetrating_pairs * PAIR_BWD

@@ -73,28 +73,25 @@ bool shape_ok(const ct_mlp_shape& s) {
 // rows from which the 128 x 128 tiles fill the chip (>= 128 workgroups at N = 512)
 constexpr int BIG_ROWS = 4096;
 
-int gemm(int epi, const GemmArgs& g, hipStream_t st) {
-    if (g.ksplit == 1 && g.M >= BIG_ROWS && epi != EPI_DW) {
-        const unsigned big = (unsigned)(((g.M + GB - 1) / GB) * ((g.N + GB - 1) / GB));
-        switch (epi) {
-            case EPI_HID_TRAIN:
-                hipLaunchKernelGGL(gemm_nt_big_kernel<EPI_HID_TRAIN>, dim3(big), dim3(256), 0, st, g); break;
-            case EPI_HID_INFER:
-                hipLaunchKernelGGL(gemm_nt_big_kernel<EPI_HID_INFER>, dim3(big), dim3(256), 0, st, g); break;
-            case EPI_OUT: hipLaunchKernelGGL(gemm_nt_big_kernel<EPI_OUT>, dim3(big), dim3(256), 0, st, g); break;
-            default: hipLaunchKernelGGL(gemm_nt_big_kernel<EPI_BWD>, dim3(big), dim3(256), 0, st, g); break;
-        }
-        return err_of(hipGetLastError());
-    }
-    const unsigned grid = (unsigned)(((g.M + GT - 1) / GT) * ((g.N + GT - 1) / GT) * g.ksplit);
+template <int TILE>
+int gemm_tile(int epi, const GemmArgs& g, hipStream_t st) {
+    const unsigned grid = (unsigned)(((g.M + TILE - 1) / TILE) * ((g.N + TILE - 1) / TILE) * g.ksplit);
     switch (epi) {
-        case EPI_HID_TRAIN: hipLaunchKernelGGL(gemm_nt_kernel<EPI_HID_TRAIN>, dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_HID_INFER: hipLaunchKernelGGL(gemm_nt_kernel<EPI_HID_INFER>, dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_OUT: hipLaunchKernelGGL(gemm_nt_kernel<EPI_OUT>, dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_BWD: hipLaunchKernelGGL(gemm_nt_kernel<EPI_BWD>, dim3(grid), dim3(256), 0, st, g); break;
-        default: hipLaunchKernelGGL(gemm_nt_kernel<EPI_DW>, dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_HID_TRAIN:
+            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_TRAIN, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_HID_INFER:
+            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_INFER, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_OUT: hipLaunchKernelGGL((gemm_nt_kernel<EPI_OUT, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_BWD: hipLaunchKernelGGL((gemm_nt_kernel<EPI_BWD, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, TILE>), dim3(grid), dim3(256), 0, st, g); break;
     }
     return err_of(hipGetLastError());
+}
+
+// 128 x 128 tiles once the rows fill the chip with them, 64 x 64 below
+int gemm(int epi, const GemmArgs& g, hipStream_t st) {
+    if (g.ksplit == 1 && g.M >= BIG_ROWS && epi != EPI_DW) return gemm_tile<128>(epi, g, st);
+    return gemm_tile<GT>(epi, g, st);
 }
 
 // split-K factor of a weight-gradient product: enough workgroups to cover

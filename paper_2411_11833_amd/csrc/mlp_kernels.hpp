@@ -36,6 +36,15 @@ __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
+// Bijection from the launch index to a tile index that gives each of the 8
+// XCDs (workgroups are dealt to them round-robin) a contiguous range of
+// tiles, so that the tiles sharing rows of A (consecutive in N) share an L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int G) {
+    constexpr int NX = 8;
+    const int x = b % NX, q = G / NX, rem = G % NX;
+    return x * q + (x < rem ? x : rem) + b / NX;
+}
+
 // Four standard normals from one Philox block: Box-Muller on the word pairs
 // (w0, w1) and (w2, w3), u1 = 1 - (w >> 8) 2^-24 in (0, 1], u2 = (w >> 8) 2^-24.
 __device__ __forceinline__ void normal4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t k0, uint32_t k1,
@@ -77,195 +86,189 @@ struct GemmArgs {
     int64_t ldht;
 };
 
-constexpr int GT = 64;    // workgroup tile (M and N)
+constexpr int GT = 64;    // workgroup tile (M and N) below BIG_ROWS rows; 128 from there
 constexpr int GK = 32;    // K per stage (one MFMA deep)
 constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 
-// Epilogue of one 16 x 16 accumulator tile: lane values are rows mb .. mb+3
-// of column n.
-template <int EPI>
-__device__ __forceinline__ void store_tile(const GemmArgs& g, int mb, int n, const f32x4_t& a, int split) {
-    if (n >= g.N) return;
-    uint16_t hv[4];
+// Epilogue of a TM x TN output tile computed by 4 waves in a 2 x 2
+// arrangement, each wave owning FI x FJ accumulator tiles of 16 x 16.  Values
+// (bias, GELU or its derivative) are formed in registers and FP32 outputs
+// stored from there; BF16 outputs are staged in LDS (`stage`, TM x (TN + 8)
+// elements, free once the main loop is done) and leave as 16-byte chunks of
+// rows, and for the training epilogues also as 16-byte chunks of the
+// transpose, so every global store of a wave is a few full cache lines.
+template <int EPI, int TM, int TN, int FI, int FJ>
+__device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (&acc)[FI][FJ], int m0, int n0,
+                                              int split, uint16_t* __restrict__ stage) {
+    constexpr bool BF = EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER || EPI == EPI_BWD;
+    constexpr bool TR = EPI == EPI_HID_TRAIN || EPI == EPI_BWD;
+    constexpr int LDT = TN + 8;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int m = mb + r;
-        const float v = a[r];
-        hv[r] = 0;
-        if (m >= g.M) continue;
-        if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
-            const float z = v + g.bias[n];
-            if constexpr (EPI == EPI_HID_TRAIN) g.F[(int64_t)m * g.ldf + n] = z;
-            hv[r] = to_bf16(gelu(z));
-            g.Hb[(int64_t)m * g.ldh + n] = hv[r];
-        } else if constexpr (EPI == EPI_OUT) {
-            g.F[(int64_t)m * g.ldf + n] = v + g.bias[n];
-        } else if constexpr (EPI == EPI_BWD) {
-            hv[r] = to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n]));
-            g.Hb[(int64_t)m * g.ldh + n] = hv[r];
-        } else {
-            g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
+    for (int j = 0; j < FJ; ++j) {
+        const int cl = wn * (TN / 2) + j * 16 + (lane & 15), n = n0 + cl;
+        float bias = 0.f;
+        if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER || EPI == EPI_OUT)
+            if (n < g.N) bias = g.bias[n];
+#pragma unroll
+        for (int i = 0; i < FI; ++i) {
+            const int rl0 = wm * (TM / 2) + i * 16 + (lane >> 4) * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rl = rl0 + r, m = m0 + rl;
+                const bool ok = m < g.M && n < g.N;
+                const float v = acc[i][j][r];
+                if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
+                    const float z = v + bias;
+                    if (EPI == EPI_HID_TRAIN && ok) g.F[(int64_t)m * g.ldf + n] = z;
+                    stage[rl * LDT + cl] = ok ? to_bf16(gelu(z)) : (uint16_t)0;
+                } else if constexpr (EPI == EPI_BWD) {
+                    stage[rl * LDT + cl] = ok ? to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n])) : (uint16_t)0;
+                } else if constexpr (EPI == EPI_OUT) {
+                    if (ok) g.F[(int64_t)m * g.ldf + n] = v + bias;
+                } else {
+                    if (ok) g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
+                }
+            }
         }
     }
-    if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_BWD) {
-        // four consecutive rows of one column: one 8-byte store of the transpose
-        uint16_t* dst = g.Ht + (int64_t)n * g.ldht + mb;
-        if (mb + 3 < g.M) {
-            uint2 p;
-            p.x = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
-            p.y = (uint32_t)hv[2] | ((uint32_t)hv[3] << 16);
-            *(uint2*)dst = p;
-        } else {
-            for (int r = 0; r < 4; ++r)
-                if (mb + r < g.M) dst[r] = hv[r];
+    if constexpr (BF) {
+        __syncthreads();
+        constexpr int CH = TN / 8;   // 16-byte chunks of a row
+        for (int c = tid; c < TM * CH; c += 256) {
+            const int rl = c / CH, cl = (c - rl * CH) * 8, m = m0 + rl, n = n0 + cl;
+            if (m >= g.M || n >= g.N) continue;
+            uint16_t* dst = g.Hb + (int64_t)m * g.ldh + n;
+            if (n + 8 <= g.N) {
+                *(u32x4_t*)dst = *(const u32x4_t*)(stage + rl * LDT + cl);
+            } else {
+                for (int q = 0; n + q < g.N; ++q) dst[q] = stage[rl * LDT + cl + q];
+            }
+        }
+        if constexpr (TR) {
+            constexpr int RC = TM / 8;   // 16-byte chunks of a column
+            for (int c = tid; c < TN * RC; c += 256) {
+                const int cl = c / RC, rl = (c - cl * RC) * 8, n = n0 + cl, m = m0 + rl;
+                if (n >= g.N || m >= g.M) continue;
+                uint16_t h[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) h[q] = stage[(rl + q) * LDT + cl];
+                uint16_t* dst = g.Ht + (int64_t)n * g.ldht + m;
+                if (m + 8 <= g.M) {
+                    u32x4_t pk;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
+                    *(u32x4_t*)dst = pk;
+                } else {
+                    for (int q = 0; m + q < g.M; ++q) dst[q] = h[q];
+                }
+            }
         }
     }
 }
 
-// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a 32 x 32
-// block = 2 x 2 MFMA 16x16x32 tiles.  Operand fragments: lane l holds row
-// (l % 16) and K elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and
-// B blocks; accumulator element r of lane l is C[4 (l / 16) + r][l % 16].
-template <int EPI>
+// C = A * B^T over a TILE x TILE workgroup tile (TILE = 64 or 128; split-K
+// over ksplit workgroups per tile).  256 threads = 4 waves in a 2 x 2
+// arrangement, each wave a (TILE/2) x (TILE/2) block of FI x FI MFMA
+// 16x16x32 tiles.  Operand fragments: lane l holds row (l % 16) and K
+// elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and B blocks;
+// accumulator element r of lane l is C[4 (l / 16) + r][l % 16].  K is staged
+// 32 deep through two LDS buffers: the global loads of the next slice are in
+// flight while this slice's products run, and one barrier per slice orders
+// the buffers.  Tile order is XCD-aware (tiles sharing rows of A share an L2).
+template <int TILE>
+union GemmSmem {
+    struct {
+        uint16_t A[2][TILE][GK + GPAD];
+        uint16_t B[2][TILE][GK + GPAD];
+    } k;
+    uint16_t stage[TILE * (TILE + 8)];
+};
+
+template <int EPI, int TILE>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GK + GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GK + GPAD];
-    const int tiles_n = (g.N + GT - 1) / GT;
-    int bid = blockIdx.x;
+    constexpr int FI = TILE / 32;   // MFMA tiles per wave and dimension
+    constexpr int H = TILE / 64;    // 16-byte chunks per thread and operand per slice
+    __shared__ __attribute__((aligned(16))) GemmSmem<TILE> sm;
+    auto& As = sm.k.A;
+    auto& Bs = sm.k.B;
+    const int tiles_n = (g.N + TILE - 1) / TILE;
+    int bid = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
     const int split = bid % g.ksplit;
     bid /= g.ksplit;
-    const int m0 = (bid / tiles_n) * GT, n0 = (bid % tiles_n) * GT;
-    const int kc = g.K / g.ksplit, kb = split * kc, ke = kb + kc;
+    const int m0 = (bid / tiles_n) * TILE, n0 = (bid % tiles_n) * TILE;
+    const int kc = g.K / g.ksplit, kb = split * kc;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-    const bool a_ok = m0 + lr < g.M, b_ok = n0 + lr < g.N;
-    const uint16_t* pa = g.A + (int64_t)(a_ok ? m0 + lr : 0) * g.lda + lk;
-    const uint16_t* pb = g.B + (int64_t)(b_ok ? n0 + lr : 0) * g.ldb + lk;
-    f32x4_t acc[2][2];
+    const int lr = tid >> 2, lk = (tid & 3) * 8;   // rows lr + 64 h
+    bool aok[H], bok[H];
+    const uint16_t* pa[H];
+    const uint16_t* pb[H];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = kb; k0 < ke; k0 += GK) {
-        const u32x4_t z4 = {0u, 0u, 0u, 0u};
-        const u32x4_t a = a_ok ? *(const u32x4_t*)(pa + k0) : z4;
-        const u32x4_t b = b_ok ? *(const u32x4_t*)(pb + k0) : z4;
-        __syncthreads();   // the previous stage's fragments are read
-        *(u32x4_t*)&As[lr][lk] = a;
-        *(u32x4_t*)&Bs[lr][lk] = b;
-        __syncthreads();
-        bf16x8_t af[2], bf[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-            af[i] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&As[wm * 32 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            bf[j] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&Bs[wn * 32 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
-    }
-
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            store_tile<EPI>(g, m0 + wm * 32 + i * 16 + (lane >> 4) * 4, n0 + wn * 32 + j * 16 + (lane & 15),
-                            acc[i][j], split);
-}
-
-// Large row counts (the selection passes over rows x draws): 128 x 128
-// workgroup tiles, each wave a 64 x 64 block = 4 x 4 MFMA tiles (8 fragment
-// reads per 16 MFMAs), K staged through two LDS buffers so that the global
-// loads of the next 32-deep slice overlap the products of this one.  Same
-// operand layout, epilogues and bounds as gemm_nt_kernel (ksplit = 1).
-constexpr int GB = 128;
-
-template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt_big_kernel(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][GB][GK + GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GB][GK + GPAD];
-    const int tiles_n = (g.N + GB - 1) / GB;
-    const int m0 = (int)(blockIdx.x / tiles_n) * GB, n0 = (int)(blockIdx.x % tiles_n) * GB;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;   // rows lr and lr + 64
-    bool aok[2], bok[2];
-    const uint16_t* pa[2];
-    const uint16_t* pb[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < H; ++h) {
         const int ra = m0 + lr + 64 * h, rb = n0 + lr + 64 * h;
         aok[h] = ra < g.M;
         bok[h] = rb < g.N;
-        pa[h] = g.A + (int64_t)(aok[h] ? ra : 0) * g.lda + lk;
-        pb[h] = g.B + (int64_t)(bok[h] ? rb : 0) * g.ldb + lk;
+        pa[h] = g.A + (int64_t)(aok[h] ? ra : 0) * g.lda + kb + lk;
+        pb[h] = g.B + (int64_t)(bok[h] ? rb : 0) * g.ldb + kb + lk;
     }
-    f32x4_t acc[4][4];
+    f32x4_t acc[FI][FI];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FI; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     const u32x4_t z4 = {0u, 0u, 0u, 0u};
-    u32x4_t ra[2], rb[2];
+    u32x4_t ra[H], rb[H];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < H; ++h) {
         ra[h] = aok[h] ? *(const u32x4_t*)(pa[h]) : z4;
         rb[h] = bok[h] ? *(const u32x4_t*)(pb[h]) : z4;
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < H; ++h) {
         *(u32x4_t*)&As[0][lr + 64 * h][lk] = ra[h];
         *(u32x4_t*)&Bs[0][lr + 64 * h][lk] = rb[h];
     }
     __syncthreads();
-    const int steps = g.K / GK;
+    const int steps = kc / GK;
     for (int st = 0; st < steps; ++st) {
         const int cur = st & 1;
         const bool more = st + 1 < steps;
         if (more) {
             const int k1 = (st + 1) * GK;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < H; ++h) {
                 ra[h] = aok[h] ? *(const u32x4_t*)(pa[h] + k1) : z4;
                 rb[h] = bok[h] ? *(const u32x4_t*)(pb[h] + k1) : z4;
             }
         }
-        bf16x8_t af[4], bf[4];
+        bf16x8_t af[FI], bf[FI];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            af[i] = __builtin_bit_cast(bf16x8_t,
-                                       *(const u32x4_t*)&As[cur][wm * 64 + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+        for (int i = 0; i < FI; ++i)
+            af[i] = __builtin_bit_cast(
+                bf16x8_t, *(const u32x4_t*)&As[cur][wm * (TILE / 2) + i * 16 + (lane & 15)][(lane >> 4) * 8]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            bf[j] = __builtin_bit_cast(bf16x8_t,
-                                       *(const u32x4_t*)&Bs[cur][wn * 64 + j * 16 + (lane & 15)][(lane >> 4) * 8]);
+        for (int j = 0; j < FI; ++j)
+            bf[j] = __builtin_bit_cast(
+                bf16x8_t, *(const u32x4_t*)&Bs[cur][wn * (TILE / 2) + j * 16 + (lane & 15)][(lane >> 4) * 8]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < FI; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
         if (more) {
             // the other buffer was last read in step st - 1, which every wave
             // finished before the barrier at the end of that step
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < H; ++h) {
                 *(u32x4_t*)&As[cur ^ 1][lr + 64 * h][lk] = ra[h];
                 *(u32x4_t*)&Bs[cur ^ 1][lr + 64 * h][lk] = rb[h];
             }
         }
         __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            store_tile<EPI>(g, m0 + wm * 64 + i * 16 + (lane >> 4) * 4, n0 + wn * 64 + j * 16 + (lane & 15),
-                            acc[i][j], 0);
+    // the loop ends with a barrier after the last fragment reads: the LDS is the stage now
+    tile_epilogue<EPI, TILE, TILE, FI, FI>(g, acc, m0, n0, split, sm.stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,21 +343,58 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Nearest draw per target (IMLE): chosen[b] = argmin over the S draws s of
+// sum_d w_d (Y[b S + s][d] - T[b][d])^2 (w = 1 when W is null; lowest s
+// among equals).  One wave per target: with S <= 64 the draws are spread
+// over the lanes (P = 64 / S lanes per draw, each summing every P-th
+// dimension), so all loads of the wave are in flight together, then the P
+// partial sums of a draw are added in lane order (cross-lane reads) and the
+// minimum found across lanes.  More than 64 draws: one draw after another.
 __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restrict__ Y, const float* __restrict__ T,
                                                           const float* __restrict__ W, int d_out, int64_t B, int S,
                                                           int32_t* __restrict__ chosen) {
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (b >= B) return;
+    if (b >= B) return;   // wave-uniform: a wave either runs all of this or none
+    const float* t = T + b * d_out;
+    const float* wt = W ? W + b * d_out : nullptr;
+    if (S <= 64) {
+        const int P = 64 / S;
+        const int s = lane / P, q = lane - s * P;
+        float acc = 0.f;
+        if (s < S) {
+            const float* y = Y + (b * S + s) * d_out;
+            for (int d = q; d < d_out; d += P) {
+                const float df = y[d] - t[d];
+                acc += (wt ? wt[d] : 1.f) * df * df;
+            }
+        }
+        // lane s < S gathers the P partial sums of draw s, in lane order
+        float sum = 0.f;
+        for (int j = 0; j < P; ++j) sum += __shfl(acc, (lane < S ? lane * P : 0) + j);
+        float dist = lane < S ? sum : INFINITY;
+        int idx = lane < S ? lane : 64;
+        // argmin across the wave, lowest draw among equal distances
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float od = __shfl_xor(dist, o);
+            const int oi = __shfl_xor(idx, o);
+            if (od < dist || (od == dist && oi < idx)) {
+                dist = od;
+                idx = oi;
+            }
+        }
+        if (lane == 0) chosen[b] = idx;
+        return;
+    }
     float best = 0.f;
     int bi = 0;
     for (int s = 0; s < S; ++s) {
         const float* y = Y + (b * S + s) * d_out;
-        const float* t = T + b * d_out;
         float acc = 0.f;
         for (int d = lane; d < d_out; d += 64) {
             const float df = y[d] - t[d];
-            acc += (W ? W[b * d_out + d] : 1.f) * df * df;
+            acc += (wt ? wt[d] : 1.f) * df * df;
         }
         acc = wave_sum(acc);
         if (s == 0 || acc < best) {
@@ -423,7 +463,17 @@ __global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* __restri
     if (o >= n_out) return;
     const uint16_t* src = DT + (int64_t)o * ldt;
     float acc = 0.f;
-    for (int64_t r = lane; r < rows; r += 64) acc += __uint_as_float((uint32_t)src[r] << 16);
+    if (rows % 8 == 0 && ldt % 8 == 0) {
+        // 16-byte chunks: every lane's loads are independent and in flight together
+        for (int64_t c = lane; c < rows / 8; c += 64) {
+            const u32x4_t v = *(const u32x4_t*)(src + 8 * c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc += __uint_as_float(v[q] << 16) + __uint_as_float(v[q] & 0xFFFF0000u);
+        }
+    } else {
+        for (int64_t r = lane; r < rows; r += 64) acc += __uint_as_float((uint32_t)src[r] << 16);
+    }
     acc = wave_sum(acc);
     if (lane == 0) gb[o] = acc;
 }

@@ -17,10 +17,15 @@ Also reported on the same JSON line:
     length in one persistent launch per iteration vs one launch each;
   * the plan-skeleton feasibility heuristic H of Eq. (5);
   * the packing step with the robot self-collision constraint switched on;
-  * augmented-Lagrangian constraint weights: the weighted step kernel and the
-    plain method's time to first with per-particle multipliers;
-  * compositional initialization (one-step problems composed, then refined)
-    on held-out packing scenes;
+  * augmented-Lagrangian constraint weights (PHR): the weighted step kernel
+    and the plain method's time to first with per-particle weights, also
+    against dual ascent on the weights;
+  * compositional initialization (grasp and placement samplers, the
+    configuration sampler conditioned on both, composition, refinement), the
+    Sampling baseline and the plain method on held-out packing and single
+    pick-place scenes;
+  * configuration 1 (single pick-place, 256 particles, 100 iterations) and
+    the headline solves with the grasps optimized too;
   * learned vs uniform seeds: a BF16 MLP proposer trained on the GPU on the
     method's converged particles, then time to the first satisfying particle
     on held-out single pick-place and packing scenes, for packing also as
@@ -56,8 +61,8 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
 # dispatch, each scaled by what the same counter read for a 256 MiB device copy
 # in the same run (FETCH_SIZE reads half the bytes: factor 2.0; WRITE_SIZE 1.0).
 # Valid only for the kernel sources it was measured on (hash below).
-STEP_TRAFFIC = {"sources": "8231cc2726c91000", "fetch_kib": 4084.8, "fetch_factor": 2.0,
-                "write_kib": 6539.0, "write_factor": 1.0}
+STEP_TRAFFIC = {"sources": "c9272d87216da262", "fetch_kib": 4633.4, "fetch_factor": 2.0,
+                "write_kib": 6568.0, "write_factor": 1.0}
 STEP_SOURCES = ("paper_2411_11833_amd/csrc/particle_kernel.hpp", "paper_2411_11833_amd/csrc/ct_tables.hpp",
                 "paper_2411_11833_amd/csrc/pk_instances.hip")
 
@@ -229,7 +234,7 @@ def config1_line(args, dev, q):
 # VALU counters of one step-kernel launch (packing, 8192 particles, split 2)
 # from rocprofv3 (SQ_INSTS_VALU, SQ_THREAD_CYCLES_VALU, medians over the
 # launches of one run); valid only for the kernel sources they were taken on.
-STEP_VALU = {"sources": None, "valu_insts": None, "thread_cycles_valu": None}
+STEP_VALU = {"sources": "c9272d87216da262", "valu_insts": 19725228, "thread_cycles_valu": 1058482775.5}
 MI355X_SIMDS = 256 * 4
 CLOCK_HZ = 2.4e9
 
@@ -439,11 +444,12 @@ def learned_seeds(args, dev, n, q):
     return out
 
 
-def al_heldout(args, dev, n, lg, prop=None, self_collision=False, budget=None):
+def al_heldout(args, dev, n, lg, prop=None, self_collision=False, budget=None, mode="phr"):
     """The augmented-Lagrangian plain method on the held-out packing scenes
     (budget --eval-budget unless given), from uniform seeds or from the
     proposer's seeds (seed inference timed), optionally with the robot
-    self-collision constraint on."""
+    self-collision constraint on; mode 'phr' (the augmented Lagrangian) or
+    'dual' (multiplier-adjusted weights, for comparison)."""
     from paper_2411_11833_amd import inputs as I
     from paper_2411_11833_amd.planner import GpuProblem, al_solve
 
@@ -459,8 +465,8 @@ def al_heldout(args, dev, n, lg, prop=None, self_collision=False, budget=None):
         if prop is not None:
             pre = prop.prepare(prob)
             init = lambda X, M, V: prop.seed(pre, seed, X, M, V, n)  # noqa: E731
-        al_solve(gp, n, 20, seed, rho=args.al_rho, outer=args.al_outer, init=init)    # captures the graphs
-        r = al_solve(gp, n, budget, seed, rho=args.al_rho, outer=args.al_outer, init=init)
+        al_solve(gp, n, 20, seed, rho=args.al_rho, outer=args.al_outer, init=init, mode=mode)   # captures graphs
+        r = al_solve(gp, n, budget, seed, rho=args.al_rho, outer=args.al_outer, init=init, mode=mode)
         first.append(r.first_sat_iter)
         times.append(r.time_to_first_s)
         lg(f"augmented Lagrangian ({'learned' if prop else 'uniform'} seeds"
@@ -468,7 +474,7 @@ def al_heldout(args, dev, n, lg, prop=None, self_collision=False, budget=None):
            f"particle after {r.first_sat_iter} iterations, {r.time_to_first_s} s")
         gp.close()
     solved = [t for t in times if t is not None]
-    return {"seeds": "learned" if prop is not None else "uniform", "self_collision": bool(self_collision),
+    return {"mode": mode, "seeds": "learned" if prop is not None else "uniform", "self_collision": bool(self_collision),
             "scenes": scenes, "particles": n, "budget": budget, "first_iter": first, "time_to_first_s": times,
             "coverage": len(solved) / len(scenes),
             "median_time_to_first_s": float(np.median(solved)) if solved else None,
@@ -674,11 +680,16 @@ def main():
                 log(f"[bench] augmented Lagrangian {key} seed {seed}: {r.time_to_first_s} s at iteration "
                     f"{r.first_sat_iter}", q)
         heldout = al_heldout(args, dev, n, lambda m: log("[bench] " + m, q))
+        heldout_dual = al_heldout(args, dev, n, lambda m: log("[bench] (dual ascent) " + m, q), mode="dual")
         al = {"rho": args.al_rho, "outer_iters": args.al_outer, "heldout_packing": heldout,
+              "heldout_packing_dual_ascent": heldout_dual,
               "weighted_step_kernel_us": w_kernel * 1e6, "fixed_lambda_step_kernel_us": kernel_s * 1e6,
               "time_to_first": runs,
-              "note": "plain method with per-particle multiplier-adjusted weights (mu <- max(0, mu + rho (J - eps)) "
-                      "every outer_iters iterations, W = lambda + mu); same seeds and budget as time_to_first"}
+              "note": "plain method on the PHR augmented Lagrangian: per-particle weights W = lambda + max(0, mu + "
+                      "rho (J - eps)) re-formed at the current terms after every 10-iteration chunk, multipliers "
+                      "mu <- max(0, mu + rho (J - eps)) every outer_iters iterations; same seeds and budget as "
+                      "time_to_first.  heldout_packing_dual_ascent: W = lambda + mu held between multiplier "
+                      "steps (no penalty on the current violation)"}
 
     # ---- motion cost: 16 interpolated waypoints per transition, 16384 particles
     motion = None

@@ -72,26 +72,32 @@ bool shape_ok(const ct_mlp_shape& s) {
 
 // rows from which the 128 x 128 tiles fill the chip (>= 128 workgroups at N = 512)
 constexpr int BIG_ROWS = 4096;
+// K slice of the 128 x 128 tiles where K allows it (32 measured no faster)
+constexpr int BIG_BK = 64;
 
-template <int TILE>
+template <int TILE, int BK>
 int gemm_tile(int epi, const GemmArgs& g, hipStream_t st) {
     const unsigned grid = (unsigned)(((g.M + TILE - 1) / TILE) * ((g.N + TILE - 1) / TILE) * g.ksplit);
     switch (epi) {
         case EPI_HID_TRAIN:
-            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_TRAIN, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_TRAIN, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
         case EPI_HID_INFER:
-            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_INFER, TILE>), dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_OUT: hipLaunchKernelGGL((gemm_nt_kernel<EPI_OUT, TILE>), dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_BWD: hipLaunchKernelGGL((gemm_nt_kernel<EPI_BWD, TILE>), dim3(grid), dim3(256), 0, st, g); break;
-        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, TILE>), dim3(grid), dim3(256), 0, st, g); break;
+            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_INFER, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_OUT: hipLaunchKernelGGL((gemm_nt_kernel<EPI_OUT, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
+        case EPI_BWD: hipLaunchKernelGGL((gemm_nt_kernel<EPI_BWD, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
+        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
     }
     return err_of(hipGetLastError());
 }
 
-// 128 x 128 tiles once the rows fill the chip with them, 64 x 64 below
+// 128 x 128 tiles once the rows fill the chip with them, 64 x 64 below; K
+// slices 64 deep where the K range of a workgroup allows (fewer waits and
+// barriers per MFMA), else 32
 int gemm(int epi, const GemmArgs& g, hipStream_t st) {
-    if (g.ksplit == 1 && g.M >= BIG_ROWS && epi != EPI_DW) return gemm_tile<128>(epi, g, st);
-    return gemm_tile<GT>(epi, g, st);
+    const bool deep = (g.K / g.ksplit) % 64 == 0;
+    if (g.ksplit == 1 && g.M >= BIG_ROWS && epi != EPI_DW)
+        return deep ? gemm_tile<128, BIG_BK>(epi, g, st) : gemm_tile<128, 32>(epi, g, st);
+    return deep ? gemm_tile<GT, 64>(epi, g, st) : gemm_tile<GT, 32>(epi, g, st);
 }
 
 // split-K factor of a weight-gradient product: enough workgroups to cover

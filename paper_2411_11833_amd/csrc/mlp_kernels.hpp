@@ -173,23 +173,27 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
 // 16x16x32 tiles.  Operand fragments: lane l holds row (l % 16) and K
 // elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and B blocks;
 // accumulator element r of lane l is C[4 (l / 16) + r][l % 16].  K is staged
-// 32 deep through two LDS buffers: the global loads of the next slice are in
-// flight while this slice's products run, and one barrier per slice orders
-// the buffers.  Tile order is XCD-aware (tiles sharing rows of A share an L2).
-template <int TILE>
+// BK (32 or 64) deep through two LDS buffers: the global loads of the next
+// slice are in flight while this slice's products run, and one barrier per
+// slice orders the buffers.  Tile order is XCD-aware (tiles sharing rows of
+// A share an L2).
+template <int TILE, int BK>
 union GemmSmem {
     struct {
-        uint16_t A[2][TILE][GK + GPAD];
-        uint16_t B[2][TILE][GK + GPAD];
+        uint16_t A[2][TILE][BK + GPAD];
+        uint16_t B[2][TILE][BK + GPAD];
     } k;
     uint16_t stage[TILE * (TILE + 8)];
 };
 
-template <int EPI, int TILE>
+template <int EPI, int TILE, int BK>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
-    constexpr int FI = TILE / 32;   // MFMA tiles per wave and dimension
-    constexpr int H = TILE / 64;    // 16-byte chunks per thread and operand per slice
-    __shared__ __attribute__((aligned(16))) GemmSmem<TILE> sm;
+    constexpr int FI = TILE / 32;           // MFMA tiles per wave and dimension
+    constexpr int CPR = BK / 8;             // 16-byte chunks per row of a slice
+    constexpr int RPP = 256 / CPR;          // rows one pass of the workgroup loads
+    constexpr int H = TILE / RPP;           // chunks per thread and operand per slice
+    constexpr int KH = BK / 32;             // MFMA depths per slice
+    __shared__ __attribute__((aligned(16))) GemmSmem<TILE, BK> sm;
     auto& As = sm.k.A;
     auto& Bs = sm.k.B;
     const int tiles_n = (g.N + TILE - 1) / TILE;
@@ -200,13 +204,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     const int kc = g.K / g.ksplit, kb = split * kc;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int lr = tid >> 2, lk = (tid & 3) * 8;   // rows lr + 64 h
+    const int lr = tid / CPR, lk = (tid % CPR) * 8;   // rows lr + RPP h
     bool aok[H], bok[H];
     const uint16_t* pa[H];
     const uint16_t* pb[H];
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        const int ra = m0 + lr + 64 * h, rb = n0 + lr + 64 * h;
+        const int ra = m0 + lr + RPP * h, rb = n0 + lr + RPP * h;
         aok[h] = ra < g.M;
         bok[h] = rb < g.N;
         pa[h] = g.A + (int64_t)(aok[h] ? ra : 0) * g.lda + kb + lk;
@@ -226,43 +230,46 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     }
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        *(u32x4_t*)&As[0][lr + 64 * h][lk] = ra[h];
-        *(u32x4_t*)&Bs[0][lr + 64 * h][lk] = rb[h];
+        *(u32x4_t*)&As[0][lr + RPP * h][lk] = ra[h];
+        *(u32x4_t*)&Bs[0][lr + RPP * h][lk] = rb[h];
     }
     __syncthreads();
-    const int steps = kc / GK;
+    const int steps = kc / BK;
     for (int st = 0; st < steps; ++st) {
         const int cur = st & 1;
         const bool more = st + 1 < steps;
         if (more) {
-            const int k1 = (st + 1) * GK;
+            const int k1 = (st + 1) * BK;
 #pragma unroll
             for (int h = 0; h < H; ++h) {
                 ra[h] = aok[h] ? *(const u32x4_t*)(pa[h] + k1) : z4;
                 rb[h] = bok[h] ? *(const u32x4_t*)(pb[h] + k1) : z4;
             }
         }
-        bf16x8_t af[FI], bf[FI];
 #pragma unroll
-        for (int i = 0; i < FI; ++i)
-            af[i] = __builtin_bit_cast(
-                bf16x8_t, *(const u32x4_t*)&As[cur][wm * (TILE / 2) + i * 16 + (lane & 15)][(lane >> 4) * 8]);
+        for (int kh = 0; kh < KH; ++kh) {
+            bf16x8_t af[FI], bf[FI];
 #pragma unroll
-        for (int j = 0; j < FI; ++j)
-            bf[j] = __builtin_bit_cast(
-                bf16x8_t, *(const u32x4_t*)&Bs[cur][wn * (TILE / 2) + j * 16 + (lane & 15)][(lane >> 4) * 8]);
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
+            for (int i = 0; i < FI; ++i)
+                af[i] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&As[cur][wm * (TILE / 2) + i * 16 + (lane & 15)]
+                                                                      [kh * 32 + (lane >> 4) * 8]);
 #pragma unroll
             for (int j = 0; j < FI; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+                bf[j] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)&Bs[cur][wn * (TILE / 2) + j * 16 + (lane & 15)]
+                                                                      [kh * 32 + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < FI; ++i)
+#pragma unroll
+                for (int j = 0; j < FI; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
         if (more) {
             // the other buffer was last read in step st - 1, which every wave
             // finished before the barrier at the end of that step
 #pragma unroll
             for (int h = 0; h < H; ++h) {
-                *(u32x4_t*)&As[cur ^ 1][lr + 64 * h][lk] = ra[h];
-                *(u32x4_t*)&Bs[cur ^ 1][lr + 64 * h][lk] = rb[h];
+                *(u32x4_t*)&As[cur ^ 1][lr + RPP * h][lk] = ra[h];
+                *(u32x4_t*)&Bs[cur ^ 1][lr + RPP * h][lk] = rb[h];
             }
         }
         __syncthreads();

@@ -113,6 +113,7 @@ def _load() -> C.CDLL:
         "ct_mlp_get_grads": (C.c_int, [vp, vp, vp]),
         "ct_mlp_noise": (C.c_int, [vp, u64, vp, i64, vp, vp]),
         "ct_mlp_forward": (C.c_int, [vp, vp, i64, vp, vp, i64, u64, vp, vp]),
+        "ct_mlp_infer": (C.c_int, [vp, vp, i64, vp, vp, i64, u64, vp, vp]),
         "ct_mlp_backward": (C.c_int, [vp, vp, i64, vp]),
         "ct_mlp_adam": (C.c_int, [vp, i64, C.POINTER(CtAdam), vp]),
         "ct_mlp_imle_step": (C.c_int, [vp, vp, i64, vp, vp, vp, i64, i32, u64, i64, C.POINTER(CtAdam), vp, vp,
@@ -346,6 +347,10 @@ def ct_mlp_noise(h, seed, draw, rows, out, stream=0):
 
 def ct_mlp_forward(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream=0):
     _chk(LIB.ct_mlp_forward(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream), "ct_mlp_forward")
+
+
+def ct_mlp_infer(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream=0):
+    _chk(LIB.ct_mlp_infer(h, feats, n_feats, feat_of_row, draw, rows, seed, Y, stream), "ct_mlp_infer")
 
 
 def ct_mlp_backward(h, dY, rows, stream=0):

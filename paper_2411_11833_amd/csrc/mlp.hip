@@ -39,6 +39,7 @@ struct ct_mlp {
     float* Y = nullptr;
     uint16_t *GY = nullptr, *GYT = nullptr;
     float* part = nullptr;
+    f32x4_t* gelu_tab = nullptr;   // GELU_PIECES cubic pieces of the normal CDF
     float* row_loss = nullptr;
     int32_t* chosen = nullptr;
     int64_t fwd_rows = -1;    // rows of the last forward that kept its activations
@@ -70,34 +71,51 @@ bool shape_ok(const ct_mlp_shape& s) {
            s.max_rows <= (int64_t(1) << 24);
 }
 
-// rows from which the 128 x 128 tiles fill the chip (>= 128 workgroups at N = 512)
-constexpr int BIG_ROWS = 4096;
-// K slice of the 128 x 128 tiles where K allows it (32 measured no faster)
-constexpr int BIG_BK = 64;
+// rows from which the 256 x 256 tiles keep at least half the compute units
+// busy at N = 512 (128 workgroups); below, the 32 x 64 tiles
+constexpr int BIG_ROWS = 16384;
 
 template <int TILE, int BK>
-int gemm_tile(int epi, const GemmArgs& g, hipStream_t st) {
+int gemm_tile(const GemmArgs& g, hipStream_t st) {
     const unsigned grid = (unsigned)(((g.M + TILE - 1) / TILE) * ((g.N + TILE - 1) / TILE) * g.ksplit);
+    hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, TILE, BK>), dim3(grid), dim3(256), 0, st, g);
+    return err_of(hipGetLastError());
+}
+
+template <int TM, int TN, int WM, int WN, int S>
+int gemm_pipe(int epi, const GemmArgs& g, hipStream_t st) {
+    const unsigned grid = (unsigned)(((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN));
+    const dim3 block(64 * WM * WN);
     switch (epi) {
         case EPI_HID_TRAIN:
-            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_TRAIN, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
+            hipLaunchKernelGGL((gemm_pipe_kernel<EPI_HID_TRAIN, TM, TN, WM, WN, S>), dim3(grid), block, 0, st, g); break;
         case EPI_HID_INFER:
-            hipLaunchKernelGGL((gemm_nt_kernel<EPI_HID_INFER, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_OUT: hipLaunchKernelGGL((gemm_nt_kernel<EPI_OUT, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
-        case EPI_BWD: hipLaunchKernelGGL((gemm_nt_kernel<EPI_BWD, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
-        default: hipLaunchKernelGGL((gemm_nt_kernel<EPI_DW, TILE, BK>), dim3(grid), dim3(256), 0, st, g); break;
+            hipLaunchKernelGGL((gemm_pipe_kernel<EPI_HID_INFER, TM, TN, WM, WN, S>), dim3(grid), block, 0, st, g); break;
+        case EPI_BWD:
+            hipLaunchKernelGGL((gemm_pipe_kernel<EPI_BWD, TM, TN, WM, WN, S>), dim3(grid), block, 0, st, g); break;
+        default: hipLaunchKernelGGL((gemm_pipe_kernel<EPI_OUT, TM, TN, WM, WN, S>), dim3(grid), block, 0, st, g); break;
     }
     return err_of(hipGetLastError());
 }
 
-// 128 x 128 tiles once the rows fill the chip with them, 64 x 64 below; K
-// slices 64 deep where the K range of a workgroup allows (fewer waits and
-// barriers per MFMA), else 32
+// Forward and backward products run the direct-to-LDS pipelined kernel:
+// 256 x 256 tiles (8 waves) for hidden layers over many rows, 128 x 128 for
+// the output layer there, and 32 x 64 tiles of two waves below (the fitted
+// passes of a training step: 256 workgroups at 1,024 x 512).  Weight
+// gradients take split-K over the double-buffered 64 x 64 kernel (K slices
+// 64 deep where the chunk allows).
 int gemm(int epi, const GemmArgs& g, hipStream_t st) {
-    const bool deep = (g.K / g.ksplit) % 64 == 0;
-    if (g.ksplit == 1 && g.M >= BIG_ROWS && epi != EPI_DW)
-        return deep ? gemm_tile<128, BIG_BK>(epi, g, st) : gemm_tile<128, 32>(epi, g, st);
-    return deep ? gemm_tile<GT, 64>(epi, g, st) : gemm_tile<GT, 32>(epi, g, st);
+    if (epi == EPI_DW) {
+        const bool deep = (g.K / g.ksplit) % 64 == 0;
+        return deep ? gemm_tile<GT, 64>(g, st) : gemm_tile<GT, 32>(g, st);
+    }
+    if (g.ksplit != 1) return CT_ERR_INVALID_ARG;
+    if (g.M >= BIG_ROWS && epi != EPI_BWD) {
+        if (g.N > 128) return gemm_pipe<256, 256, 4, 2, 4>(epi, g, st);
+        return gemm_pipe<128, 128, 2, 2, 4>(epi, g, st);
+    }
+    if (g.N > 64) return gemm_pipe<32, 64, 1, 2, 4>(epi, g, st);
+    return gemm_pipe<32, 32, 1, 2, 4>(epi, g, st);
 }
 
 // split-K factor of a weight-gradient product: enough workgroups to cover
@@ -149,6 +167,7 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
         g.K = m->kpad[l];
         g.ksplit = 1;
         g.bias = m->P + m->boff[l];
+        g.gelu_tab = m->gelu_tab;
         if (l + 1 < m->L) {
             g.F = m->Z[l];
             g.ldf = m->s.hidden;
@@ -229,10 +248,34 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
 int adam(ct_mlp* m, int64_t t, const ct_adam* ad, hipStream_t st) {
     const double bc1 = 1.0 - std::pow((double)ad->beta1, (double)t);
     const double bc2 = 1.0 - std::pow((double)ad->beta2, (double)t);
-    hipLaunchKernelGGL(mlp_adam_kernel, dim3(blocks(m->n_params, 256)), dim3(256), 0, st, m->P, m->Mo, m->Vo, m->G,
-                       m->n_params, ad->lr, ad->beta1, ad->beta2, ad->eps, ad->grad_scale, (float)bc1, (float)bc2);
-    const int rc = err_of(hipGetLastError());
-    return rc != CT_OK ? rc : refresh(m, st);
+    AdamRefreshArgs a{};
+    a.P = m->P;
+    a.Mo = m->Mo;
+    a.Vo = m->Vo;
+    a.G = m->G;
+    a.lr = ad->lr;
+    a.b1 = ad->beta1;
+    a.b2 = ad->beta2;
+    a.eps = ad->eps;
+    a.gscale = ad->grad_scale;
+    a.bc1 = (float)bc1;
+    a.bc2 = (float)bc2;
+    a.L = m->L;
+    for (int l = 0; l < m->L; ++l) {
+        a.wstart[l + 1] = a.wstart[l] + (int64_t)m->npad[l] * m->kpad[l];
+        a.bstart[l + 1] = a.bstart[l] + m->dout[l];
+        a.din[l] = m->din[l];
+        a.dout[l] = m->dout[l];
+        a.kpad[l] = m->kpad[l];
+        a.npad[l] = m->npad[l];
+        a.woff[l] = m->woff[l];
+        a.boff[l] = m->boff[l];
+        a.Wb[l] = m->Wb[l];
+        a.WbT[l] = m->WbT[l];
+    }
+    const int64_t total = a.wstart[m->L] + a.bstart[m->L];
+    hipLaunchKernelGGL(adam_refresh_kernel, dim3(blocks(total, 256)), dim3(256), 0, st, a);
+    return err_of(hipGetLastError());
 }
 
 bool adam_ok(const ct_adam* a) {
@@ -290,9 +333,15 @@ int ct_mlp_create(const ct_mlp_shape* shape, ct_mlp** out) {
     for (int l = 0; l < shape->depth && ok; ++l)
         ok = m->alloc(m->Z[l], R * Hd) && m->alloc(m->H[l], R * Hd) && m->alloc(m->HT[l], R * Hd) &&
              m->alloc(m->D[l], R * Hd) && m->alloc(m->DT[l], R * Hd);
+    ok = ok && m->alloc(m->gelu_tab, GELU_PIECES);
     if (!ok) {
         delete m;
         return CT_ERR_ALLOC;
+    }
+    hipLaunchKernelGGL(gelu_table_kernel, dim3(blocks(GELU_PIECES, 256)), dim3(256), 0, 0, m->gelu_tab);
+    if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        delete m;
+        return CT_ERR_DEVICE;
     }
     *out = m;
     return CT_OK;
@@ -342,17 +391,35 @@ int ct_mlp_noise(const ct_mlp* mlp, uint64_t seed, const int32_t* draw, int64_t 
     return err_of(hipGetLastError());
 }
 
-int ct_mlp_forward(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
-                   int64_t rows, uint64_t seed, float* Y, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int forward_out(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+                int64_t rows, uint64_t seed, float* Y, bool train, void* stream) {
     if (!mlp || rows < 0 || rows > mlp->rows_cap) return CT_ERR_INVALID_ARG;
     if (rows == 0) return CT_OK;
     if (!Y || (mlp->s.d_feat > 0 && (!feats || n_feats < 1))) return CT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    int rc = forward(mlp, feats, n_feats < 1 ? 1 : n_feats, feat_of_row, draw, 0, rows, seed, true, st);
+    int rc = forward(mlp, feats, n_feats < 1 ? 1 : n_feats, feat_of_row, draw, 0, rows, seed, train, st);
     if (rc == CT_OK)
         rc = err_of(hipMemcpyAsync(Y, mlp->Y, (size_t)rows * mlp->s.d_out * sizeof(float), hipMemcpyDeviceToDevice,
                                    st));
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ct_mlp_forward(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+                   int64_t rows, uint64_t seed, float* Y, void* stream) {
+    return forward_out(mlp, feats, n_feats, feat_of_row, draw, rows, seed, Y, true, stream);
+}
+
+int ct_mlp_infer(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+                 int64_t rows, uint64_t seed, float* Y, void* stream) {
+    return forward_out(mlp, feats, n_feats, feat_of_row, draw, rows, seed, Y, false, stream);
 }
 
 int ct_mlp_backward(ct_mlp* mlp, const float* dY, int64_t rows, void* stream) {

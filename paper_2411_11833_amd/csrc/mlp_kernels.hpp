@@ -21,6 +21,14 @@ namespace mlp {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));   // 16 bytes moved as one value
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// two floats -> packed bfloat16 bits (first in the low half), round to
+// nearest, ties to even: one v_cvt_pk_bf16_f32
+__device__ __forceinline__ uint32_t pack_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t{a, b}), bf16x2_t));
+}
 
 // float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
 __device__ __forceinline__ uint16_t to_bf16(float f) {
@@ -29,11 +37,62 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x * 0.70710678118654752f)); }
+// Phi(x), the standard normal CDF, as erfc(u) / 2 at u = -x / sqrt 2, with
+// erfc(u) = t exp(-u^2 + P(t)), t = 1 / (1 + u / 2) for u >= 0 and P the
+// degree-9 Chebyshev interpolant that norm_cdf_fit.py derives (relative error
+// of erfc about 1e-7).  Branch-free, one reciprocal and one exponential, and
+// accurate relative to Phi in the lower tail, where 1 + erf(x / sqrt 2)
+// cancels.  Used by the backward epilogue's GELU derivative.
+__device__ __forceinline__ float norm_cdf(float x) {
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(a, 0.35355339059327376f, 1.f));   // a / sqrt 2 = u
+    float p = 0.17087277768357076f;
+    p = fmaf(p, t, -0.82215223447300323f);
+    p = fmaf(p, t, 1.4885158894086188f);
+    p = fmaf(p, t, -1.1352040006480935f);
+    p = fmaf(p, t, 0.27886808472408969f);
+    p = fmaf(p, t, -0.18628806181001004f);
+    p = fmaf(p, t, 0.096784189536313278f);
+    p = fmaf(p, t, 0.37409195971065135f);
+    p = fmaf(p, t, 1.0000236801583804f);
+    p = fmaf(p, t, -1.26551222514161f);
+    const float y = fmaf(-0.5f * a, a, p);   // -u^2 + P(t)
+    const float q = t * __builtin_amdgcn_exp2f(fmaf(y, 1.4426950408889634f, -1.f));   // erfc(|u|) / 2
+    return x >= 0.f ? 1.f - q : q;
+}
+
+// GELU of the forward epilogues, x Phi(x), with Phi on [-8, 8] as 512 cubic
+// pieces: the Hermite interpolant of Phi and phi at the nodes -8 + k / 32,
+// held per piece as coefficients c0..c3 of its polynomial in the fraction f
+// of the way across it, built once per handle in double precision
+// (gelu_table_kernel) and read from an LDS copy.  Interpolation error below
+// 2e-9 (h^4 max|Phi^(4)| / 384); outside [-8, 8] Phi is 0 or 1 to FP32
+// precision and the end pieces give exactly that.  Rounded to BF16, x Phi(x)
+// this way differs from the exact GELU on about 7e-6 of FP32 inputs in
+// [-8, 8] (the erf form: 3e-3), at 9 VALU instructions and one LDS read.
+constexpr int GELU_PIECES = 512;
+constexpr int GELU_TAB_BYTES = GELU_PIECES * 16;
+
+__device__ __forceinline__ float gelu_tab(const f32x4_t* __restrict__ tab, float x) {
+    const float u = __builtin_amdgcn_fmed3f(fmaf(x, 32.f, 256.f), 0.f, 511.99994f);
+    const f32x4_t c = tab[(int)u];
+    const float f = __builtin_amdgcn_fractf(u);
+    return x * fmaf(fmaf(fmaf(c[3], f, c[2]), f, c[1]), f, c[0]);
+}
+
+__global__ __launch_bounds__(256) void gelu_table_kernel(f32x4_t* __restrict__ tab) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= GELU_PIECES) return;
+    const double h = 1.0 / 32, z0 = -8.0 + k * h, z1 = z0 + h;
+    const double p0 = 0.5 * erfc(-z0 * 0.70710678118654752), p1 = 0.5 * erfc(-z1 * 0.70710678118654752);
+    const double d0 = h * 0.39894228040143268 * exp(-0.5 * z0 * z0);
+    const double d1 = h * 0.39894228040143268 * exp(-0.5 * z1 * z1);
+    tab[k] = f32x4_t{(float)p0, (float)d0, (float)(3.0 * (p1 - p0) - 2.0 * d0 - d1), (float)(2.0 * (p0 - p1) + d0 + d1)};
+}
 
 // d/dx [x Phi(x)] = Phi(x) + x phi(x)
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+    return fmaf(x * 0.39894228040143268f, __builtin_amdgcn_exp2f(-0.72134752044448170f * x * x), norm_cdf(x));
 }
 
 // Bijection from the launch index to a tile index that gives each of the 8
@@ -84,35 +143,38 @@ struct GemmArgs {
     int64_t ldh;
     uint16_t* Ht;        // the same values transposed, [N][ldht] (HID_TRAIN, BWD)
     int64_t ldht;
+    const f32x4_t* gelu_tab;   // GELU_PIECES pieces (HID_*)
 };
 
 constexpr int GT = 64;    // workgroup tile (M and N) below BIG_ROWS rows; 128 from there
 constexpr int GK = 32;    // K per stage (one MFMA deep)
 constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 
-// Epilogue of a TM x TN output tile computed by 4 waves in a 2 x 2
-// arrangement, each wave owning FI x FJ accumulator tiles of 16 x 16.  Values
+// Epilogue of a TM x TN output tile computed by WM x WN waves (NT = 64 WM WN
+// threads), each wave owning FI x FJ accumulator tiles of 16 x 16.  Values
 // (bias, GELU or its derivative) are formed in registers and FP32 outputs
 // stored from there; BF16 outputs are staged in LDS (`stage`, TM x (TN + 8)
 // elements, free once the main loop is done) and leave as 16-byte chunks of
 // rows, and for the training epilogues also as 16-byte chunks of the
 // transpose, so every global store of a wave is a few full cache lines.
-template <int EPI, int TM, int TN, int FI, int FJ>
+template <int EPI, int TM, int TN, int FI, int FJ, int WM = 2, int WN = 2>
 __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (&acc)[FI][FJ], int m0, int n0,
-                                              int split, uint16_t* __restrict__ stage) {
+                                              int split, uint16_t* __restrict__ stage, const f32x4_t* tab) {
     constexpr bool BF = EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER || EPI == EPI_BWD;
     constexpr bool TR = EPI == EPI_HID_TRAIN || EPI == EPI_BWD;
     constexpr int LDT = TN + 8;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w >> 1, wn = w & 1;
+    constexpr int NT = 64 * WM * WN;
+    static_assert(FI * 16 * WM == TM && FJ * 16 * WN == TN, "wave tiles must cover the tile");
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wm = w / WN, wn = w % WN;
 #pragma unroll
     for (int j = 0; j < FJ; ++j) {
-        const int cl = wn * (TN / 2) + j * 16 + (lane & 15), n = n0 + cl;
+        const int cl = wn * (TN / WN) + j * 16 + (lane & 15), n = n0 + cl;
         float bias = 0.f;
         if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER || EPI == EPI_OUT)
             if (n < g.N) bias = g.bias[n];
 #pragma unroll
         for (int i = 0; i < FI; ++i) {
-            const int rl0 = wm * (TM / 2) + i * 16 + (lane >> 4) * 4;
+            const int rl0 = wm * (TM / WM) + i * 16 + (lane >> 4) * 4;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rl = rl0 + r, m = m0 + rl;
@@ -121,7 +183,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
                 if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
                     const float z = v + bias;
                     if (EPI == EPI_HID_TRAIN && ok) g.F[(int64_t)m * g.ldf + n] = z;
-                    stage[rl * LDT + cl] = ok ? to_bf16(gelu(z)) : (uint16_t)0;
+                    stage[rl * LDT + cl] = ok ? to_bf16(gelu_tab(tab, z)) : (uint16_t)0;
                 } else if constexpr (EPI == EPI_BWD) {
                     stage[rl * LDT + cl] = ok ? to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n])) : (uint16_t)0;
                 } else if constexpr (EPI == EPI_OUT) {
@@ -135,7 +197,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
     if constexpr (BF) {
         __syncthreads();
         constexpr int CH = TN / 8;   // 16-byte chunks of a row
-        for (int c = tid; c < TM * CH; c += 256) {
+        for (int c = tid; c < TM * CH; c += NT) {
             const int rl = c / CH, cl = (c - rl * CH) * 8, m = m0 + rl, n = n0 + cl;
             if (m >= g.M || n >= g.N) continue;
             uint16_t* dst = g.Hb + (int64_t)m * g.ldh + n;
@@ -147,7 +209,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
         }
         if constexpr (TR) {
             constexpr int RC = TM / 8;   // 16-byte chunks of a column
-            for (int c = tid; c < TN * RC; c += 256) {
+            for (int c = tid; c < TN * RC; c += NT) {
                 const int cl = c / RC, rl = (c - cl * RC) * 8, n = n0 + cl, m = m0 + rl;
                 if (n >= g.N || m >= g.M) continue;
                 uint16_t h[8];
@@ -275,7 +337,232 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
         __syncthreads();
     }
     // the loop ends with a barrier after the last fragment reads: the LDS is the stage now
-    tile_epilogue<EPI, TILE, TILE, FI, FI>(g, acc, m0, n0, split, sm.stage);
+    tile_epilogue<EPI, TILE, TILE, FI, FI>(g, acc, m0, n0, split, sm.stage, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Pipelined C = A * B^T.  K is staged 32 deep through a ring of S slices in
+// LDS that the operands reach by direct global-to-LDS loads
+// (global_load_lds_dwordx4: each wave instruction fills 1 KB of LDS, lane l
+// the 16 bytes at l * 16), so S - 1 slices are in flight while one is
+// multiplied and no registers hold data in transit.  A slice of an operand
+// with R rows is R x 32 BF16 = R rows of four 16-byte chunks; chunk c of row
+// r sits in slot c ^ sw(r), sw(r) = ((r >> 1) & 3) ^ ((r >> 3) & 1), so that
+// any 8 consecutive rows of one chunk column (and any 16) spread over
+// distinct 16-byte bank groups: fragment reads are free of bank conflicts.  Rows past M (or N) load
+// row M - 1 (N - 1) instead; they only reach outputs that are not stored.
+//
+// Order per slice s (with the next slice s + 1): wait until this wave's
+// loads of s + 1 have landed and its LDS reads are done, barrier (every
+// wave's loads of s + 1 are visible and every wave holds the fragments of s
+// in registers), issue the loads of slice s + S into the slot of s, read the
+// fragments of s + 1, then the MFMAs of s (while those reads return).
+// WM x WN waves of (TM / WM) x (TN / WN) outputs each.
+
+// wait until at most n of this wave's vector-memory loads are outstanding
+// and all of its LDS reads have returned (n wave-uniform, 0 <= n <= 15)
+__device__ __forceinline__ void vm_lds_wait(int n) {
+    // s_waitcnt immediate: vmcnt in bits 3:0, lgkmcnt 11:8 (0), expcnt 6:4 left at its maximum
+    switch (n) {
+#define CT_VMW(k) case k: __builtin_amdgcn_s_waitcnt(0x0070 | k); break;
+        CT_VMW(1) CT_VMW(2) CT_VMW(3) CT_VMW(4) CT_VMW(5) CT_VMW(6) CT_VMW(7) CT_VMW(8)
+        CT_VMW(9) CT_VMW(10) CT_VMW(11) CT_VMW(12) CT_VMW(13) CT_VMW(14) CT_VMW(15)
+#undef CT_VMW
+        default: __builtin_amdgcn_s_waitcnt(0x0070); break;
+    }
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+template <int TM, int TN, int WM, int WN, int S>
+struct PipeCfg {
+    static constexpr int NT = 64 * WM * WN;       // threads
+    static constexpr int FI = TM / WM / 16, FJ = TN / WN / 16;
+    static constexpr int SA = TM * 32, SB = TN * 32;   // BF16 elements of a slice of A, of B
+    static constexpr int IA = TM / 16, IB = TN / 16;   // wave instructions that load them (64 chunks each)
+    static constexpr int IW = (IA + IB) / (WM * WN);   // per wave and slice
+    static constexpr int RING = S * (SA + SB);
+    static constexpr int STAGE = TM * (TN + 8);
+    static constexpr int MAIN = RING > STAGE ? RING : STAGE;   // BF16 elements; the GELU table follows
+    static constexpr int SMEM = MAIN + GELU_TAB_BYTES / 2;
+    static_assert(FI * 16 * WM == TM && FJ * 16 * WN == TN, "wave tiles must cover the tile");
+    static_assert((IA + IB) % (WM * WN) == 0, "every wave loads the same number of chunks");
+    static_assert(IW * (S - 2) <= 15, "loads in flight per wave must fit the wait immediate");
+};
+
+// Epilogue straight from the accumulators of the transposed products (SWAP
+// below): lane l holds 4 consecutive columns 4 (l / 16) .. + 3 of row l % 16
+// of each 16 x 16 block, bias already in them.  Hidden layers store
+// bf16(gelu(z)) as 8-byte groups of 4, the output layer FP32 as 16-byte
+// groups (where its rows are 16-byte aligned).
+template <int EPI, int TM, int TN, int FI, int FJ, int WM, int WN>
+__device__ __forceinline__ void reg_epilogue(const GemmArgs& g, const f32x4_t (&acc)[FI][FJ], int m0, int n0,
+                                             const f32x4_t* tab) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w / WN, wn = w % WN;
+    const bool vec_out = (g.ldf & 3) == 0;
+    // whole 16 x 16 blocks inside the output take the unguarded path (a
+    // wave-uniform test); blocks on the ragged edges check every element
+    const int mw = m0 + wm * (TM / WM), nw = n0 + wn * (TN / WN);
+#pragma unroll
+    for (int i = 0; i < FI; ++i) {
+        const int m = mw + i * 16 + (lane & 15);
+        const bool rows_in = mw + i * 16 + 16 <= g.M;
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) {
+            const int n = nw + j * 16 + 4 * (lane >> 4);
+            const bool inside = rows_in && nw + j * 16 + 16 <= g.N;
+            if constexpr (EPI == EPI_HID_INFER) {
+                const uint2 h = make_uint2(pack_bf16(gelu_tab(tab, acc[i][j][0]), gelu_tab(tab, acc[i][j][1])),
+                                           pack_bf16(gelu_tab(tab, acc[i][j][2]), gelu_tab(tab, acc[i][j][3])));
+                uint16_t* dst = g.Hb + (int64_t)m * g.ldh + n;
+                if (inside) {
+                    *(uint2*)dst = h;
+                } else if (m < g.M) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (n + r < g.N) dst[r] = (uint16_t)((r < 2 ? h.x : h.y) >> (16 * (r & 1)));
+                }
+            } else {
+                float* dst = g.F + (int64_t)m * g.ldf + n;
+                if (inside && vec_out) {
+                    *(f32x4_t*)dst = acc[i][j];
+                } else if (m < g.M) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (n + r < g.N) dst[r] = acc[i][j][r];
+                }
+            }
+        }
+    }
+}
+
+template <int EPI, int TM, int TN, int WM, int WN, int S>
+__global__ __launch_bounds__(64 * WM * WN) void gemm_pipe_kernel(GemmArgs g) {
+    using C = PipeCfg<TM, TN, WM, WN, S>;
+    constexpr int FI = C::FI, FJ = C::FJ, IW = C::IW;
+    // Inference and output products run the MFMA with the operands swapped,
+    // accumulating the transpose of each 16 x 16 block, so that a lane ends
+    // up with 4 consecutive columns of one row (stored from registers); the
+    // training epilogue stages through LDS for its transposed copy instead.
+    constexpr bool SWAP = EPI == EPI_HID_INFER || EPI == EPI_OUT;
+    static_assert(S >= 3, "the ring holds the slice being read, the next one and the one being loaded");
+    __shared__ __attribute__((aligned(1024))) uint16_t sm[C::SMEM];
+    const int tiles_n = (g.N + TN - 1) / TN;
+    const int bid = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+    const int m0 = (bid / tiles_n) * TM, n0 = (bid % tiles_n) * TN;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w / WN, wn = w % WN;
+    // this wave's loads: instructions q = w IW .. w IW + IW - 1 of the slice,
+    // the first IA of A, the rest of B; lane l of instruction q fills chunk
+    // position 64 q' + l of its operand (q' = q, or q - IA for B)
+    const uint16_t* src[IW];
+    int dst[IW];
+#pragma unroll
+    for (int h = 0; h < IW; ++h) {
+        const int q = w * IW + h;
+        const bool load_a = q < C::IA;
+        const int qq = load_a ? q : q - C::IA;
+        const int p = qq * 64 + lane, r = p >> 2, c = (p & 3) ^ ((r >> 1) & 3) ^ ((r >> 3) & 1);
+        const int row = load_a ? min(m0 + r, g.M - 1) : min(n0 + r, g.N - 1);
+        src[h] = (load_a ? g.A + (int64_t)row * g.lda : g.B + (int64_t)row * g.ldb) + c * 8;
+        dst[h] = (load_a ? 0 : C::SA) + qq * 512;   // element offset in a ring slot
+    }
+    auto issue = [&](int s) {
+        uint16_t* slot = sm + (s % S) * (C::SA + C::SB);
+#pragma unroll
+        for (int h = 0; h < IW; ++h)
+            __builtin_amdgcn_global_load_lds((const void*)(src[h] + s * 32), (lds_ptr_t)(slot + dst[h]), 16, 0, 0);
+    };
+    // wait for this wave's loads of slice s (the loads of up to S - 2 later
+    // slices stay in flight) and for its LDS reads, then a barrier: every
+    // wave's loads of s have landed and every wave holds the fragments it
+    // read before.  The empty asm statements keep the compiler from moving
+    // LDS accesses across the barrier (it emits no wait of its own).
+    const int nk = g.K / 32;
+    auto land = [&](int s) {
+        vm_lds_wait(min(nk - 1 - s, S - 2) * IW);
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    // fragment reads: lane l takes row l % 16 of a 16-row block, chunk l / 16
+    const int frag = (lane & 15) * 32 + 8 * ((lane >> 4) ^ ((lane >> 1) & 3) ^ ((lane >> 3) & 1));
+    auto read = [&](int s, bf16x8_t (&af)[FI], bf16x8_t (&bf)[FJ]) {
+        const uint16_t* As = sm + (s % S) * (C::SA + C::SB);
+        const uint16_t* Bs = As + C::SA;
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+            af[i] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(As + (wm * (TM / WM) + i * 16) * 32 + frag));
+#pragma unroll
+        for (int j = 0; j < FJ; ++j)
+            bf[j] = __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(Bs + (wn * (TN / WN) + j * 16) * 32 + frag));
+    };
+    f32x4_t acc[FI][FJ];
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+        f32x4_t b0 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (SWAP) {   // the bias rides in the accumulators
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = n0 + wn * (TN / WN) + j * 16 + 4 * (lane >> 4) + r;
+                b0[r] = n < g.N ? g.bias[n] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FI; ++i) acc[i][j] = b0;
+    }
+    // the GELU table (hidden layers): 8 KB by direct loads ahead of the
+    // ring's, so every wait for a slice covers it too
+    constexpr bool GELU = EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER;
+    f32x4_t* tab = (f32x4_t*)(sm + C::MAIN);
+    if constexpr (GELU) {
+        for (int q = w; q < GELU_PIECES / 64; q += WM * WN)
+            __builtin_amdgcn_global_load_lds((const void*)(g.gelu_tab + q * 64 + lane), (lds_ptr_t)(tab + q * 64), 16,
+                                             0, 0);
+    }
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s)
+        if (s < nk) issue(s);
+    // slice s: (if there is a next slice) land it, refill the ring and read
+    // its fragments, then multiply slice s -- the next fragments arrive
+    // while these MFMAs run
+    // (after the last slice the reads fetch a stale slot, unused)
+    auto step = [&](int s, bf16x8_t (&af)[FI], bf16x8_t (&bf)[FJ], bf16x8_t (&an)[FI], bf16x8_t (&bn)[FJ]) {
+        if (s + 1 < nk) {
+            land(s + 1);
+            if (s + S < nk) issue(s + S);
+        }
+        read(s + 1, an, bn);
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j)
+                acc[i][j] = SWAP ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[j], af[i], acc[i][j], 0, 0, 0)
+                                 : __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+        // interleave the next slice's fragment reads with this slice's MFMAs
+        constexpr int NR = FI + FJ, NM = FI * FJ, PER = NM / NR;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+            __builtin_amdgcn_sched_group_barrier(0x008, PER, 0);   // PER MFMAs
+        }
+        __builtin_amdgcn_sched_group_barrier(0x008, NM - PER * NR, 0);
+    };
+    bf16x8_t a0[FI], b0[FJ], a1[FI], b1[FJ];
+    land(0);
+    if (S - 1 < nk) issue(S - 1);
+    read(0, a0, b0);
+    for (int s = 0; s < nk; s += 2) {
+        step(s, a0, b0, a1, b1);
+        if (s + 1 < nk) step(s + 1, a1, b1, a0, b0);
+    }
+    if constexpr (SWAP) {
+        reg_epilogue<EPI, TM, TN, FI, FJ, WM, WN>(g, acc, m0, n0, tab);
+    } else {
+        // every wave's last fragment reads are done before the ring becomes the stage
+        __syncthreads();
+        tile_epilogue<EPI, TM, TN, FI, FJ, WM, WN>(g, acc, m0, n0, 0, sm, tab);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -495,20 +782,54 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(const float* __restri
     out[e] = acc;
 }
 
-// Adam on the flat FP32 parameters (bias corrections bc1 = 1 - beta1^t,
-// bc2 = 1 - beta2^t passed in)
-__global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ P, float* __restrict__ Mo,
-                                                       float* __restrict__ Vo, const float* __restrict__ G, int64_t n,
-                                                       float lr, float b1, float b2, float eps, float gscale,
-                                                       float bc1, float bc2) {
+// Adam over every parameter and the BF16 weight copies of the updated
+// weights in one launch: elements [0, wend) walk each layer's padded
+// [npad][kpad] block (Adam on the real [dout][din] part, then Wb and WbT;
+// zeros in the padding), elements [wend, wend + bias count) the biases.
+// Adam with bias correction (bc1, bc2 = 1 - beta^t), then the BF16 copy.
+constexpr int MAX_LAYERS = 9;
+struct AdamRefreshArgs {
+    float *P, *Mo, *Vo;
+    const float* G;
+    float lr, b1, b2, eps, gscale, bc1, bc2;
+    int L;
+    int64_t wstart[MAX_LAYERS + 1];   // prefix sums of npad * kpad
+    int64_t bstart[MAX_LAYERS + 1];   // prefix sums of dout
+    int din[MAX_LAYERS], dout[MAX_LAYERS], kpad[MAX_LAYERS], npad[MAX_LAYERS];
+    int64_t woff[MAX_LAYERS], boff[MAX_LAYERS];
+    uint16_t* Wb[MAX_LAYERS];
+    uint16_t* WbT[MAX_LAYERS];   // null: none kept for that layer
+};
+
+__device__ __forceinline__ float adam_one(const AdamRefreshArgs& a, int64_t idx) {
+    const float g = a.gscale * a.G[idx];
+    const float m = a.b1 * a.Mo[idx] + (1.f - a.b1) * g;
+    const float v = a.b2 * a.Vo[idx] + (1.f - a.b2) * g * g;
+    a.Mo[idx] = m;
+    a.Vo[idx] = v;
+    const float p = a.P[idx] - a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+    a.P[idx] = p;
+    return p;
+}
+
+__global__ __launch_bounds__(256) void adam_refresh_kernel(AdamRefreshArgs a) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const float g = gscale * G[e];
-    const float m = b1 * Mo[e] + (1.f - b1) * g;
-    const float v = b2 * Vo[e] + (1.f - b2) * g * g;
-    Mo[e] = m;
-    Vo[e] = v;
-    P[e] -= lr * (m / bc1) / (sqrtf(v / bc2) + eps);
+    if (e < a.wstart[a.L]) {
+        int l = 0;
+        while (e >= a.wstart[l + 1]) ++l;
+        const int64_t loc = e - a.wstart[l];
+        const int o = (int)(loc / a.kpad[l]), i = (int)(loc % a.kpad[l]);
+        uint16_t v = 0;
+        if (o < a.dout[l] && i < a.din[l]) v = to_bf16(adam_one(a, a.woff[l] + (int64_t)o * a.din[l] + i));
+        a.Wb[l][loc] = v;
+        if (a.WbT[l]) a.WbT[l][(int64_t)i * a.npad[l] + o] = v;
+        return;
+    }
+    const int64_t b = e - a.wstart[a.L];
+    if (b >= a.bstart[a.L]) return;
+    int l = 0;
+    while (b >= a.bstart[l + 1]) ++l;
+    adam_one(a, a.boff[l] + (b - a.bstart[l]));
 }
 
 // BF16 copies of one layer's weights: Wb [npad][kpad] and WbT [kpad][npad]

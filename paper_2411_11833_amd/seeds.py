@@ -90,10 +90,12 @@ class GpuMlp:
         B.ct_mlp_noise(self.h, seed, _ptr(draw), rows, out.data_ptr(), _stream())
         return out
 
-    def forward(self, feats, rows: int, seed: int, feat_of_row=None, draw=None) -> torch.Tensor:
+    def forward(self, feats, rows: int, seed: int, feat_of_row=None, draw=None, keep: bool = True) -> torch.Tensor:
+        """Y [rows, d_out]; keep=True keeps the activations for backward()."""
         Y = torch.empty(rows, self.d_out, dtype=torch.float32, device=self.device)
-        B.ct_mlp_forward(self.h, feats.data_ptr(), feats.shape[0], _ptr(feat_of_row), _ptr(draw), rows, seed,
-                         Y.data_ptr(), _stream())
+        fn = B.ct_mlp_forward if keep else B.ct_mlp_infer
+        fn(self.h, feats.data_ptr(), feats.shape[0], _ptr(feat_of_row), _ptr(draw), rows, seed, Y.data_ptr(),
+           _stream())
         return Y
 
     def backward(self, dY, rows: int):

@@ -9,8 +9,15 @@ go the other way (one BF16 ulp, 2^-8 relative, on that element).  Hence
 norm-wise relative errors: outputs <= 2e-3, weight gradients <= 5e-3 per layer,
 and element-wise within one BF16 ulp (2^-8) of the element's own magnitude
 plus one BF16 ulp of the tensor's RMS (a flipped rounding of an input moves
-an element by at most about one ulp of the typical magnitude, not of that
-element, which cancellation can make arbitrarily small);
+an element by about one ulp of the typical magnitude, not of that element,
+which cancellation can make arbitrarily small).  For the outputs of the
+forward pass that band is a typical bound, not a worst case: a flip of one
+activation h of the last hidden layer moves every output y_n of its row by
+w_n h 2^-8 to 2^-7, the largest weight-activation products of a 512-wide
+layer reach about the RMS of the row's outputs, and a row can hold several
+flips (FP32 accumulation of the same network with the exact GELU leaves the
+band on the 4100-row case).  So at most 1e-4 of the outputs may leave the
+one-ulp band, and none may exceed four times it;
 noise (FP32 log / sin / cos vs FP64) <= 2e-5 absolute; nearest-draw choices
 identical wherever the oracle's best and second-best distances differ by more
 than 1e-3 relative.
@@ -83,19 +90,29 @@ def test_noise_matches_oracle():
     m.close()
 
 
-# 4096 and more rows take the 128 x 128 double-buffered kernel; 4100 leaves a ragged last tile
+# 16384 and more rows take the 256 x 256 hidden and 128 x 128 output tiles
+# of the pipelined kernel, fewer rows its 32 x 64 and 32 x 32 tiles; 4100,
+# 5000 and 16400 leave ragged last tiles.  keep=False runs the inference
+# epilogues (transposed accumulators, stores from registers), keep=True the
+# training ones (Z, H and H^T kept).
+@pytest.mark.parametrize("keep", [True, False])
 @pytest.mark.parametrize("name,rows", [("small", 100), ("small", 64), ("proposer", 4096), ("proposer", 200),
-                                       ("proposer", 4100), ("small", 5000)])
-def test_forward_matches_oracle(name, rows):
+                                       ("proposer", 4100), ("small", 5000), ("proposer", 16400),
+                                       ("small", 16384)])
+def test_forward_matches_oracle(name, rows, keep):
     m, dims, p, feats, fr, draw = _setup(name, rows)
-    Y = m.forward(_dev(feats), rows, 77, _dev(fr, torch.int32), _dev(draw, torch.int32)).cpu().numpy()
+    Y = m.forward(_dev(feats), rows, 77, _dev(fr, torch.int32), _dev(draw, torch.int32), keep=keep).cpu().numpy()
     X = MO.input_rows(feats, fr, 77, np.arange(rows), draw, m.d_noise)
     want, _ = MO.forward(MO.unflatten(p, dims), X, bf16=True)
     err = _rel(Y, want)
     ew = _elementwise(Y, want, axis=1)
-    print(f"{name} rows={rows}: forward rel err {err:.2e}, element-wise {ew:.3f} of the one-ulp bound")
+    rms = np.sqrt(np.mean(want * want, axis=1, keepdims=True))
+    outside = float(np.mean(np.abs(Y - want) > ULP_BF16 * (np.abs(want) + rms)))
+    print(f"{name} rows={rows} keep={keep}: forward rel err {err:.2e}, element-wise {ew:.3f} of the one-ulp "
+          f"band ({outside:.1e} of outputs outside it)")
     assert err <= 2e-3
-    assert ew <= 1.0
+    assert outside <= 1e-4
+    assert ew <= 4.0
     # and well away from the unrounded network, so the rounding points are real
     plain, _ = MO.forward(MO.unflatten(p, dims), X, bf16=False)
     assert _rel(want, plain) > 1e-4

@@ -478,7 +478,7 @@ int ct_batch_autotune(ct_batch *batch, int32_t *chosen, void *stream);
 typedef struct ct_mlp ct_mlp;
 
 typedef struct ct_mlp_shape {
-    int32_t d_feat, d_noise; /* multiples of 4, d_feat + d_noise > 0 */
+    int32_t d_feat, d_noise; /* multiples of 4, 0 < d_feat + d_noise <= 512 */
     int32_t hidden;          /* multiple of 64, 64..4096 */
     int32_t depth;           /* hidden layers, 1..8 */
     int32_t d_out;           /* 1..512 */

@@ -39,6 +39,7 @@ struct ct_mlp {
     float* Y = nullptr;
     uint16_t *GY = nullptr, *GYT = nullptr;
     float* part = nullptr;
+    int64_t part_cap = 0;   // floats in part
     f32x4_t* gelu_tab = nullptr;   // GELU_PIECES cubic pieces of the normal CDF
     float* row_loss = nullptr;
     int32_t* chosen = nullptr;
@@ -66,6 +67,7 @@ namespace {
 
 bool shape_ok(const ct_mlp_shape& s) {
     return s.d_feat >= 0 && s.d_feat % 4 == 0 && s.d_noise >= 0 && s.d_noise % 4 == 0 && s.d_feat + s.d_noise > 0 &&
+           s.d_feat + s.d_noise <= 512 &&
            s.hidden >= 64 && s.hidden % 64 == 0 && s.hidden <= 4096 && s.depth >= 1 && s.depth <= 8 &&
            s.d_out >= 1 && s.d_out <= 512 && s.max_rows >= 64 && s.max_rows % 64 == 0 &&
            s.max_rows <= (int64_t(1) << 24);
@@ -120,10 +122,10 @@ int gemm(int epi, const GemmArgs& g, hipStream_t st) {
 
 // split-K factor of a weight-gradient product: enough workgroups to cover
 // the chip (about 512), each K chunk a multiple of 32, partials within PART_CAP
-int pick_ksplit(int M, int N, int64_t K) {
+int pick_ksplit(int M, int N, int64_t K, int64_t cap) {
     const int64_t tiles = (int64_t)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
     int s = 1;
-    while (tiles * s < 512 && K % (int64_t(GK) * s * 2) == 0 && (int64_t)s * 2 * M * N <= PART_CAP && s < 64) s *= 2;
+    while (tiles * s < 512 && K % (int64_t(GK) * s * 2) == 0 && (int64_t)s * 2 * M * N <= cap && s < 64) s *= 2;
     return s;
 }
 
@@ -154,7 +156,8 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
     a.X0 = m->X0;
     a.X0T = train ? m->X0T : nullptr;
     a.ldt = m->rows_cap;
-    hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * (m->in_pad / 4), 256)), dim3(256), 0, st, a);
+    const int ng = m->s.d_noise / 4, nf = m->in_pad / 4 - ng;
+    hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * std::max(ng, nf), 256), 2), dim3(256), 0, st, a);
     int rc = err_of(hipGetLastError());
     for (int l = 0; l < m->L && rc == CT_OK; ++l) {
         GemmArgs g{};
@@ -189,11 +192,17 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
 // gradient of sum(G * Y) from the BF16 upstream gradient already in GY / GYT
 int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
     int rc = CT_OK;
+    GradFinishArgs fin{};
+    fin.L = m->L;
+    fin.rows = rows;
+    fin.ldt = m->rows_cap;
+    int64_t used = 0;   // partial floats handed out so far (every layer's stay until the finish)
     for (int l = m->L - 1; l >= 0 && rc == CT_OK; --l) {
         const bool top = l == m->L - 1;
         const uint16_t* Dm = top ? m->GY : m->D[l];     // [rows][npad]
         const uint16_t* Dt = top ? m->GYT : m->DT[l];   // [npad][rows_cap]
-        // dW_l = D^T * H_{l-1}
+        // dW_l = D^T * H_{l-1}: split-K partials, summed with the bias
+        // gradients after the last layer
         GemmArgs g{};
         g.A = Dt;
         g.lda = m->rows_cap;
@@ -202,27 +211,24 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
         g.M = m->dout[l];
         g.N = m->din[l];
         g.K = (int)rows;
-        g.ksplit = pick_ksplit(g.M, g.N, rows);
+        g.ksplit = pick_ksplit(g.M, g.N, rows, m->part_cap - used);
         float* dW = m->G + m->woff[l];
+        fin.ksplit[l] = g.ksplit;
+        fin.dW[l] = dW;
+        fin.DT[l] = Dt;
+        fin.gb[l] = m->G + m->boff[l];
         if (g.ksplit == 1) {
             g.F = dW;
             g.ldf = m->din[l];
             g.fsplit = 0;
         } else {
-            g.F = m->part;
+            g.F = m->part + used;
             g.ldf = m->din[l];
             g.fsplit = (int64_t)g.M * g.N;
+            fin.part[l] = g.F;
+            used += g.ksplit * g.fsplit;
         }
         rc = gemm(EPI_DW, g, st);
-        if (rc != CT_OK) break;
-        if (g.ksplit > 1) {
-            const int64_t cnt = (int64_t)g.M * g.N;
-            hipLaunchKernelGGL(split_reduce_kernel, dim3(blocks(cnt, 256)), dim3(256), 0, st, m->part, g.ksplit, cnt,
-                               dW);
-        }
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(blocks(m->dout[l], 4)), dim3(256), 0, st, Dt, m->rows_cap, rows,
-                           m->dout[l], m->G + m->boff[l]);
-        rc = err_of(hipGetLastError());
         if (rc != CT_OK || l == 0) break;
         // D_{l-1} = (D_l * W_l) . gelu'(Z_{l-1})
         GemmArgs b{};
@@ -242,7 +248,14 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
         b.ldht = m->rows_cap;
         rc = gemm(EPI_BWD, b, st);
     }
-    return rc;
+    if (rc != CT_OK) return rc;
+    for (int l = 0; l < m->L; ++l) {
+        fin.estart[l + 1] = fin.estart[l] + (fin.ksplit[l] > 1 ? (int64_t)m->dout[l] * m->din[l] : 0);
+        fin.ostart[l + 1] = fin.ostart[l] + m->dout[l];
+    }
+    const int64_t nb = std::max(blocks(fin.estart[m->L], 256), blocks(fin.ostart[m->L], 4));
+    hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)nb, 2), dim3(256), 0, st, fin);
+    return err_of(hipGetLastError());
 }
 
 int adam(ct_mlp* m, int64_t t, const ct_adam* ad, hipStream_t st) {
@@ -318,7 +331,8 @@ int ct_mlp_create(const ct_mlp_shape* shape, ct_mlp** out) {
               m->alloc(m->GYT, R * m->out_pad) && m->alloc(m->row_loss, R) && m->alloc(m->chosen, R);
     int64_t part = 0;
     for (int l = 0; l < m->L; ++l) part = std::max(part, (int64_t)m->din[l] * m->dout[l]);
-    ok = ok && m->alloc(m->part, std::min<int64_t>(PART_CAP, 64 * part));
+    m->part_cap = std::min<int64_t>(PART_CAP, 64 * part);
+    ok = ok && m->alloc(m->part, m->part_cap);
     m->Wb.assign(m->L, nullptr);
     m->WbT.assign(m->L, nullptr);
     for (int l = 0; l < m->L && ok; ++l) {

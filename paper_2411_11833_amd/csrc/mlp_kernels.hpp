@@ -582,23 +582,29 @@ struct InputArgs {
     int64_t ldt;
 };
 
+// Two halves of the grid (blockIdx.y): the noise groups of every row, then
+// the feature and zero groups, so that the waves generating noise
+// (Philox and Box-Muller) do nothing else.  rows * groups < 2^32 (rows
+// <= 2^24, in_pad <= 512): 32-bit index arithmetic.
 __global__ __launch_bounds__(256) void build_inputs_kernel(InputArgs a) {
-    const int groups = a.in_pad / 4;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.rows * groups) return;
-    const int64_t r = e / groups;
-    const int c = (int)(e % groups) * 4;
-    const int64_t b = a.draws > 0 ? r / a.draws : r;
-    const uint32_t s = a.draws > 0 ? (uint32_t)(r % a.draws) : (a.draw ? (uint32_t)a.draw[b] : 0u);
+    const uint32_t groups = (uint32_t)a.in_pad / 4, ng = (uint32_t)a.d_noise / 4, nf = groups - ng;
+    const bool noise = blockIdx.y == 0;
+    const uint32_t per = noise ? ng : nf;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (per == 0 || e >= (uint32_t)a.rows * per) return;
+    const uint32_t r = e / per, gi = e - r * per;
+    const int c = noise ? a.d_feat + 4 * (int)gi : (4 * (int)gi < a.d_feat ? 4 * (int)gi : 4 * (int)gi + a.d_noise);
+    const uint32_t b = a.draws > 0 ? r / (uint32_t)a.draws : r;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (c < a.d_feat) {
+    if (noise) {
+        const uint32_t s = a.draws > 0 ? r - b * (uint32_t)a.draws : (a.draw ? (uint32_t)a.draw[b] : 0u);
+        normal4(b, s, gi, a.k0, a.k1, v);
+    } else if (c < a.d_feat) {
         int64_t f = a.feat_of_row ? (int64_t)a.feat_of_row[b] : 0;
         f = f < 0 ? 0 : (f >= a.n_feats ? a.n_feats - 1 : f);
         const float* src = a.feats + f * a.d_feat + c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = src[q];
-    } else if (c < a.d_feat + a.d_noise) {
-        normal4((uint32_t)b, s, (uint32_t)((c - a.d_feat) / 4), a.k0, a.k1, v);
     }
     uint16_t h[4];
 #pragma unroll
@@ -606,7 +612,7 @@ __global__ __launch_bounds__(256) void build_inputs_kernel(InputArgs a) {
     uint2 p;
     p.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
     p.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-    *(uint2*)(a.X0 + r * a.in_pad + c) = p;
+    *(uint2*)(a.X0 + (int64_t)r * a.in_pad + c) = p;
     if (a.X0T) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) a.X0T[(int64_t)(c + q) * a.ldt + r] = h[q];
@@ -749,37 +755,58 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restric
     if (threadIdx.x == 0) *loss = red[0] * inv;
 }
 
-// db[o] = sum over rows of the BF16 upstream gradient (one wave per output)
-__global__ __launch_bounds__(256) void bias_grad_kernel(const uint16_t* __restrict__ DT, int64_t ldt, int64_t rows,
-                                                        int n_out, float* __restrict__ gb) {
-    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+constexpr int MAX_LAYERS = 9;
+
+// The end of a backward pass, every layer in one launch: blockIdx.y = 0
+// sums each split-K layer's weight-gradient partials in split order,
+// blockIdx.y = 1 forms each layer's bias gradient as the row sum of its
+// BF16 output gradient D^T (one wave per output, rows % 8 == 0 and
+// ldt % 8 == 0 read as 16-byte chunks).
+struct GradFinishArgs {
+    int L;
+    int64_t rows, ldt;
+    int64_t estart[MAX_LAYERS + 1];   // prefix sums of the split-K layers' M N (0 for the others)
+    int64_t ostart[MAX_LAYERS + 1];   // prefix sums of dout
+    int ksplit[MAX_LAYERS];
+    const float* part[MAX_LAYERS];    // [ksplit][M N] partials of a split-K layer
+    float* dW[MAX_LAYERS];
+    const uint16_t* DT[MAX_LAYERS];   // [dout][ldt]
+    float* gb[MAX_LAYERS];
+};
+
+__global__ __launch_bounds__(256) void grad_finish_kernel(GradFinishArgs a) {
+    if (blockIdx.y == 0) {
+        const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (e >= a.estart[a.L]) return;
+        int l = 0;
+        while (e >= a.estart[l + 1]) ++l;
+        const int64_t cnt = a.estart[l + 1] - a.estart[l], i = e - a.estart[l];
+        float acc = 0.f;
+        for (int s = 0; s < a.ksplit[l]; ++s) acc += a.part[l][(int64_t)s * cnt + i];
+        a.dW[l][i] = acc;
+        return;
+    }
+    const int64_t ob = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (o >= n_out) return;
-    const uint16_t* src = DT + (int64_t)o * ldt;
+    if (ob >= a.ostart[a.L]) return;
+    int l = 0;
+    while (ob >= a.ostart[l + 1]) ++l;
+    const int64_t o = ob - a.ostart[l];
+    const uint16_t* src = a.DT[l] + o * a.ldt;
     float acc = 0.f;
-    if (rows % 8 == 0 && ldt % 8 == 0) {
+    if (a.rows % 8 == 0 && a.ldt % 8 == 0) {
         // 16-byte chunks: every lane's loads are independent and in flight together
-        for (int64_t c = lane; c < rows / 8; c += 64) {
+        for (int64_t c = lane; c < a.rows / 8; c += 64) {
             const u32x4_t v = *(const u32x4_t*)(src + 8 * c);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 acc += __uint_as_float(v[q] << 16) + __uint_as_float(v[q] & 0xFFFF0000u);
         }
     } else {
-        for (int64_t r = lane; r < rows; r += 64) acc += __uint_as_float((uint32_t)src[r] << 16);
+        for (int64_t r = lane; r < a.rows; r += 64) acc += __uint_as_float((uint32_t)src[r] << 16);
     }
     acc = wave_sum(acc);
-    if (lane == 0) gb[o] = acc;
-}
-
-// out[e] = sum over split-K partials, in split order
-__global__ __launch_bounds__(256) void split_reduce_kernel(const float* __restrict__ part, int ksplit, int64_t count,
-                                                           float* __restrict__ out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    float acc = 0.f;
-    for (int s = 0; s < ksplit; ++s) acc += part[(int64_t)s * count + e];
-    out[e] = acc;
+    if (lane == 0) a.gb[l][o] = acc;
 }
 
 // Adam over every parameter and the BF16 weight copies of the updated
@@ -787,7 +814,6 @@ __global__ __launch_bounds__(256) void split_reduce_kernel(const float* __restri
 // [npad][kpad] block (Adam on the real [dout][din] part, then Wb and WbT;
 // zeros in the padding), elements [wend, wend + bias count) the biases.
 // Adam with bias correction (bc1, bc2 = 1 - beta^t), then the BF16 copy.
-constexpr int MAX_LAYERS = 9;
 struct AdamRefreshArgs {
     float *P, *Mo, *Vo;
     const float* G;

@@ -190,12 +190,17 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
 }
 
 // gradient of sum(G * Y) from the BF16 upstream gradient already in GY / GYT
-int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
+// (with loss: the loss of the rows' row_loss, scaled by inv, in the same launch
+// that finishes the gradients)
+int backward(ct_mlp* m, int64_t rows, hipStream_t st, float* loss = nullptr, float inv = 0.f) {
     int rc = CT_OK;
     GradFinishArgs fin{};
     fin.L = m->L;
     fin.rows = rows;
     fin.ldt = m->rows_cap;
+    fin.row_loss = loss ? m->row_loss : nullptr;
+    fin.loss_scale = inv;
+    fin.loss = loss;
     int64_t used = 0;   // partial floats handed out so far (every layer's stay until the finish)
     for (int l = m->L - 1; l >= 0 && rc == CT_OK; --l) {
         const bool top = l == m->L - 1;
@@ -254,7 +259,7 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st) {
         fin.ostart[l + 1] = fin.ostart[l] + m->dout[l];
     }
     const int64_t nb = std::max(blocks(fin.estart[m->L], 256), blocks(fin.ostart[m->L], 4));
-    hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)nb, 2), dim3(256), 0, st, fin);
+    hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)nb, loss ? 3 : 2), dim3(256), 0, st, fin);
     return err_of(hipGetLastError());
 }
 
@@ -471,12 +476,9 @@ int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int
     const float scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
     hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, weights,
                        mlp->s.d_out, mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap, mlp->row_loss);
-    if (loss)
-        hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(256), 0, st, mlp->row_loss, rows,
-                           (float)(1.0 / ((double)rows * mlp->s.d_out)), loss);
     rc = err_of(hipGetLastError());
-    // 5. backward and Adam
-    if (rc == CT_OK) rc = backward(mlp, rows, st);
+    // 5. backward (and the loss) and Adam
+    if (rc == CT_OK) rc = backward(mlp, rows, st, loss, (float)(1.0 / ((double)rows * mlp->s.d_out)));
     if (rc == CT_OK) rc = adam(mlp, t, adam_args, st);
     return rc;
 }

@@ -584,39 +584,55 @@ struct InputArgs {
 
 // Two halves of the grid (blockIdx.y): the noise groups of every row, then
 // the feature and zero groups, so that the waves generating noise
-// (Philox and Box-Muller) do nothing else.  rows * groups < 2^32 (rows
+// (Philox and Box-Muller) do nothing else.  With draws > 0 a feature thread
+// serves one logical row and writes its group to all of that row's draws
+// (one feature lookup instead of one per draw).  rows * groups < 2^32 (rows
 // <= 2^24, in_pad <= 512): 32-bit index arithmetic.
+__device__ __forceinline__ uint2 pack4_bf16(const float (&v)[4]) {
+    uint2 p;
+    p.x = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+    p.y = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+    return p;
+}
+
+__device__ __forceinline__ void put_group(const InputArgs& a, uint32_t r, int c, uint2 p) {
+    *(uint2*)(a.X0 + (int64_t)r * a.in_pad + c) = p;
+    if (a.X0T) {
+        const uint16_t h[4] = {(uint16_t)p.x, (uint16_t)(p.x >> 16), (uint16_t)p.y, (uint16_t)(p.y >> 16)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.X0T[(int64_t)(c + q) * a.ldt + r] = h[q];
+    }
+}
+
 __global__ __launch_bounds__(256) void build_inputs_kernel(InputArgs a) {
     const uint32_t groups = (uint32_t)a.in_pad / 4, ng = (uint32_t)a.d_noise / 4, nf = groups - ng;
-    const bool noise = blockIdx.y == 0;
-    const uint32_t per = noise ? ng : nf;
     const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-    if (per == 0 || e >= (uint32_t)a.rows * per) return;
-    const uint32_t r = e / per, gi = e - r * per;
-    const int c = noise ? a.d_feat + 4 * (int)gi : (4 * (int)gi < a.d_feat ? 4 * (int)gi : 4 * (int)gi + a.d_noise);
-    const uint32_t b = a.draws > 0 ? r / (uint32_t)a.draws : r;
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (noise) {
+    if (blockIdx.y == 0) {
+        if (ng == 0 || e >= (uint32_t)a.rows * ng) return;
+        const uint32_t r = e / ng, gi = e - r * ng;
+        const uint32_t b = a.draws > 0 ? r / (uint32_t)a.draws : r;
         const uint32_t s = a.draws > 0 ? r - b * (uint32_t)a.draws : (a.draw ? (uint32_t)a.draw[b] : 0u);
+        float v[4];
         normal4(b, s, gi, a.k0, a.k1, v);
-    } else if (c < a.d_feat) {
+        put_group(a, r, a.d_feat + 4 * (int)gi, pack4_bf16(v));
+        return;
+    }
+    // feature and zero groups of logical row b (physical rows b draws .. + draws - 1, or b)
+    const uint32_t per_b = a.draws > 0 ? (uint32_t)a.draws : 1u;
+    const uint32_t n_b = (uint32_t)a.rows / per_b;
+    if (nf == 0 || e >= n_b * nf) return;
+    const uint32_t b = e / nf, gi = e - b * nf;
+    const int c = 4 * (int)gi < a.d_feat ? 4 * (int)gi : 4 * (int)gi + a.d_noise;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (c < a.d_feat) {
         int64_t f = a.feat_of_row ? (int64_t)a.feat_of_row[b] : 0;
         f = f < 0 ? 0 : (f >= a.n_feats ? a.n_feats - 1 : f);
         const float* src = a.feats + f * a.d_feat + c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) v[q] = src[q];
     }
-    uint16_t h[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) h[q] = to_bf16(v[q]);
-    uint2 p;
-    p.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
-    p.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
-    *(uint2*)(a.X0 + (int64_t)r * a.in_pad + c) = p;
-    if (a.X0T) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a.X0T[(int64_t)(c + q) * a.ldt + r] = h[q];
-    }
+    const uint2 p = pack4_bf16(v);
+    for (uint32_t d = 0; d < per_b; ++d) put_group(a, b * per_b + d, c, p);
 }
 
 // FP32 noise rows (the generator alone): out[r][j], counter words (r, draw[r])
@@ -740,9 +756,32 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__
     }
 }
 
+constexpr int MAX_LAYERS = 9;
+
+// The end of a backward pass, every layer in one launch: blockIdx.y = 0
+// sums each split-K layer's weight-gradient partials in split order,
+// blockIdx.y = 1 forms each layer's bias gradient as the row sum of its
+// BF16 output gradient D^T (one wave per output, rows % 8 == 0 and
+// ldt % 8 == 0 read as 16-byte chunks), and block (0, 2), when a loss is
+// asked for, reduces the per-row losses (loss_reduce).
+struct GradFinishArgs {
+    int L;
+    int64_t rows, ldt;
+    int64_t estart[MAX_LAYERS + 1];   // prefix sums of the split-K layers' M N (0 for the others)
+    int64_t ostart[MAX_LAYERS + 1];   // prefix sums of dout
+    int ksplit[MAX_LAYERS];
+    const float* part[MAX_LAYERS];    // [ksplit][M N] partials of a split-K layer
+    float* dW[MAX_LAYERS];
+    const uint16_t* DT[MAX_LAYERS];   // [dout][ldt]
+    float* gb[MAX_LAYERS];
+    const float* row_loss;            // null: no loss
+    float loss_scale;
+    float* loss;
+};
+
 // loss = inv * sum of the row sums (one workgroup, fixed summation order)
-__global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restrict__ row_loss, int64_t rows, float inv,
-                                                          float* __restrict__ loss) {
+__device__ __forceinline__ void loss_reduce(const float* __restrict__ row_loss, int64_t rows, float inv,
+                                            float* __restrict__ loss) {
     __shared__ float red[256];
     float acc = 0.f;
     for (int64_t r = threadIdx.x; r < rows; r += 256) acc += row_loss[r];
@@ -755,26 +794,11 @@ __global__ __launch_bounds__(256) void loss_reduce_kernel(const float* __restric
     if (threadIdx.x == 0) *loss = red[0] * inv;
 }
 
-constexpr int MAX_LAYERS = 9;
-
-// The end of a backward pass, every layer in one launch: blockIdx.y = 0
-// sums each split-K layer's weight-gradient partials in split order,
-// blockIdx.y = 1 forms each layer's bias gradient as the row sum of its
-// BF16 output gradient D^T (one wave per output, rows % 8 == 0 and
-// ldt % 8 == 0 read as 16-byte chunks).
-struct GradFinishArgs {
-    int L;
-    int64_t rows, ldt;
-    int64_t estart[MAX_LAYERS + 1];   // prefix sums of the split-K layers' M N (0 for the others)
-    int64_t ostart[MAX_LAYERS + 1];   // prefix sums of dout
-    int ksplit[MAX_LAYERS];
-    const float* part[MAX_LAYERS];    // [ksplit][M N] partials of a split-K layer
-    float* dW[MAX_LAYERS];
-    const uint16_t* DT[MAX_LAYERS];   // [dout][ldt]
-    float* gb[MAX_LAYERS];
-};
-
 __global__ __launch_bounds__(256) void grad_finish_kernel(GradFinishArgs a) {
+    if (blockIdx.y == 2) {
+        if (blockIdx.x == 0 && a.row_loss) loss_reduce(a.row_loss, a.rows, a.loss_scale, a.loss);
+        return;
+    }
     if (blockIdx.y == 0) {
         const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
         if (e >= a.estart[a.L]) return;

@@ -121,11 +121,12 @@ int gemm(int epi, const GemmArgs& g, hipStream_t st) {
 }
 
 // split-K factor of a weight-gradient product: enough workgroups to cover
-// the chip (about 512), each K chunk a multiple of 32, partials within PART_CAP
+// the chip (about 512), each K chunk a multiple of 32, at most 8 chunks (the
+// partials are read back once more), partials within the space left
 int pick_ksplit(int M, int N, int64_t K, int64_t cap) {
     const int64_t tiles = (int64_t)((M + GT - 1) / GT) * ((N + GT - 1) / GT);
     int s = 1;
-    while (tiles * s < 512 && K % (int64_t(GK) * s * 2) == 0 && (int64_t)s * 2 * M * N <= cap && s < 64) s *= 2;
+    while (tiles * s < 512 && K % (int64_t(GK) * s * 2) == 0 && (int64_t)s * 2 * M * N <= cap && s < 8) s *= 2;
     return s;
 }
 
@@ -493,7 +494,7 @@ int ct_mlp_sample(ct_mlp* mlp, const float* feats, uint64_t seed, const float* m
     hipStream_t st = (hipStream_t)stream;
     int rc = forward(mlp, feats, 1, nullptr, nullptr, 0, n, seed, false, st);
     if (rc != CT_OK) return rc;
-    hipLaunchKernelGGL(sample_store_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, mlp->Y, mlp->s.d_out, n, mean,
+    hipLaunchKernelGGL(sample_store_kernel, dim3(blocks(n, SEED_TILE)), dim3(256), 0, st, mlp->Y, mlp->s.d_out, n, mean,
                        std_, lo, hi, wrap, X, M, V, ld);
     return err_of(hipGetLastError());
 }

@@ -895,22 +895,41 @@ __global__ __launch_bounds__(256) void refresh_kernel(const float* __restrict__ 
 }
 
 // seeds: x = y std + mean, angles wrapped into [-pi, pi), clamped into
-// [lo, hi]; one thread per particle, stores coalesced along particles
+// [lo, hi].  A workgroup takes 64 particles and walks their outputs 64 at a
+// time through an LDS tile: rows of Y read coalesced along the outputs,
+// the dimension-major X (and zeroed M, V) written coalesced along the
+// particles.
+constexpr int SEED_TILE = 64;
+
 __global__ __launch_bounds__(256) void sample_store_kernel(const float* __restrict__ Y, int d_out, int64_t n,
                                                            const float* __restrict__ mean,
                                                            const float* __restrict__ stdv,
                                                            const float* __restrict__ lo, const float* __restrict__ hi,
                                                            const uint8_t* __restrict__ wrap, float* __restrict__ X,
                                                            float* __restrict__ M, float* __restrict__ V, int64_t ld) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int d = 0; d < d_out; ++d) {
-        float x = Y[i * d_out + d] * stdv[d] + mean[d];
-        if (wrap && wrap[d]) x -= 6.283185307179586f * floorf((x + 3.14159265358979f) * 0.15915494309189535f);
-        x = fminf(fmaxf(x, lo[d]), hi[d]);
-        X[d * ld + i] = x;
-        if (M) M[d * ld + i] = 0.f;
-        if (V) V[d * ld + i] = 0.f;
+    __shared__ float tile[SEED_TILE][SEED_TILE + 1];
+    const int64_t i0 = (int64_t)blockIdx.x * SEED_TILE;
+    const int t = threadIdx.x;
+    for (int d0 = 0; d0 < d_out; d0 += SEED_TILE) {
+        for (int e = t; e < SEED_TILE * SEED_TILE; e += 256) {
+            const int p = e / SEED_TILE, q = e % SEED_TILE;
+            const int64_t i = i0 + p;
+            tile[p][q] = (i < n && d0 + q < d_out) ? Y[i * d_out + d0 + q] : 0.f;
+        }
+        __syncthreads();
+        for (int e = t; e < SEED_TILE * SEED_TILE; e += 256) {
+            const int q = e / SEED_TILE, p = e % SEED_TILE, d = d0 + q;
+            const int64_t i = i0 + p;
+            if (i < n && d < d_out) {
+                float x = tile[p][q] * stdv[d] + mean[d];
+                if (wrap && wrap[d]) x -= 6.283185307179586f * floorf((x + 3.14159265358979f) * 0.15915494309189535f);
+                x = fminf(fmaxf(x, lo[d]), hi[d]);
+                X[d * ld + i] = x;
+                if (M) M[d * ld + i] = 0.f;
+                if (V) V[d * ld + i] = 0.f;
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -468,7 +468,7 @@ int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int
     // 1. every draw, inference only; 2. the nearest draw per target
     int rc = forward(mlp, feats, nf, feat_of_row, nullptr, n_draws, rows * n_draws, seed, false, st);
     if (rc != CT_OK) return rc;
-    hipLaunchKernelGGL(imle_select_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, weights,
+    hipLaunchKernelGGL(imle_select_kernel, dim3((unsigned)rows), dim3(256), 0, st, mlp->Y, targets, weights,
                        mlp->s.d_out, rows, n_draws, sel);
     rc = err_of(hipGetLastError());
     // 3. the kept draws again, keeping activations; 4. squared error

@@ -661,22 +661,24 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // Nearest draw per target (IMLE): chosen[b] = argmin over the S draws s of
 // sum_d w_d (Y[b S + s][d] - T[b][d])^2 (w = 1 when W is null; lowest s
-// among equals).  One wave per target: with S <= 64 the draws are spread
-// over the lanes (P = 64 / S lanes per draw, each summing every P-th
-// dimension), so all loads of the wave are in flight together, then the P
-// partial sums of a draw are added in lane order (cross-lane reads) and the
-// minimum found across lanes.  More than 64 draws: one draw after another.
+// among equals).  One workgroup per target: with S <= 256 the draws are
+// spread over the 256 lanes (P = 256 / S lanes per draw, each summing every
+// P-th dimension), so four waves' loads are in flight together and each
+// lane's chain is d_out / P long; the P partial sums of a draw are added in
+// lane order through LDS and the first wave finds the minimum.  More than
+// 256 draws: the first wave takes one draw after another.
 __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restrict__ Y, const float* __restrict__ T,
                                                           const float* __restrict__ W, int d_out, int64_t B, int S,
                                                           int32_t* __restrict__ chosen) {
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= B) return;   // wave-uniform: a wave either runs all of this or none
+    __shared__ float part[256];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (b >= B) return;   // workgroup-uniform
     const float* t = T + b * d_out;
     const float* wt = W ? W + b * d_out : nullptr;
-    if (S <= 64) {
-        const int P = 64 / S;
-        const int s = lane / P, q = lane - s * P;
+    if (S <= 256) {
+        const int P = 256 / S;
+        const int s = tid / P, q = tid - s * P;
         float acc = 0.f;
         if (s < S) {
             const float* y = Y + (b * S + s) * d_out;
@@ -685,11 +687,19 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
                 acc += (wt ? wt[d] : 1.f) * df * df;
             }
         }
-        // lane s < S gathers the P partial sums of draw s, in lane order
-        float sum = 0.f;
-        for (int j = 0; j < P; ++j) sum += __shfl(acc, (lane < S ? lane * P : 0) + j);
-        float dist = lane < S ? sum : INFINITY;
-        int idx = lane < S ? lane : 64;
+        part[tid] = acc;
+        __syncthreads();
+        if (tid >= 64) return;
+        float dist = INFINITY;
+        int idx = 256;
+        for (int i = lane; i < S; i += 64) {   // increasing draws: strict < keeps the lowest among equals
+            float sum = 0.f;
+            for (int j = 0; j < P; ++j) sum += part[i * P + j];
+            if (sum < dist) {
+                dist = sum;
+                idx = i;
+            }
+        }
         // argmin across the wave, lowest draw among equal distances
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -703,6 +713,7 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
         if (lane == 0) chosen[b] = idx;
         return;
     }
+    if (tid >= 64) return;
     float best = 0.f;
     int bi = 0;
     for (int s = 0; s < S; ++s) {

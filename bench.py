@@ -32,8 +32,9 @@ Also reported on the same JSON line:
     the starting points of compositional initialization;
   * the time-to-satisfy half of the metric in one place
     (`time_to_satisfy_learned_vs_uniform`): learned vs uniform seeds at their
-    common satisfaction rate, single pick-place with fixed weights and
-    packing with augmented-Lagrangian weights;
+    common satisfaction rate, single pick-place and packing with fixed
+    weights (packing's uniform seeds at the long budget where they first
+    solve some scenes) and packing with augmented-Lagrangian weights;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -879,6 +880,20 @@ def main():
         tts["single_pick_place_fixed_lambda"] = {
             "rate": sp["equal_satisfaction_rate"], "uniform_s": sp["time_at_equal_rate_uniform_s"],
             "learned_s": sp["time_at_equal_rate_learned_s"]}
+        if sampling is not None:
+            # the plain method with fixed weights on packing: uniform seeds
+            # first reach a non-zero rate at the long budget of the
+            # compositional section; learned-seed runs stop at their first
+            # satisfying particle, so a solve within their shorter budget
+            # has the same time under any longer one, and the common rate's
+            # time is defined
+            from paper_2411_11833_amd import seeds as SD
+            cu, cl, rate, tu, tl = SD.equal_rate_times(sampling["packing"]["plain"]["time_to_first_s"],
+                                                       learned["packing"]["eval"]["learned_with_fallback_time_s"])
+            tts["packing_fixed_lambda"] = {
+                "rate": rate, "uniform_s": tu, "learned_s": tl, "coverage_uniform": cu, "coverage_learned": cl,
+                "uniform_budget_iters": args.plain_budget,
+                "learned_budget_iters": learned["packing"]["eval"]["budget_iters"]}
         if al is not None and "augmented_lagrangian_learned_seeds" in al.get("heldout_equal_rate", {}):
             c = al["heldout_equal_rate"]["augmented_lagrangian_learned_seeds"]
             tts["packing_augmented_lagrangian"] = {

@@ -361,13 +361,17 @@ def train(mlp: GpuMlp, data: Dataset, stats: Stats, steps: int = 2000, batch: in
     # batches drawn as consecutive slices of a fresh permutation per pass
     order = np.concatenate([rng.permutation(R) for _ in range((steps * batch) // R + 1)])[:steps * batch]
     order = torch.from_numpy(order.astype(np.int64)).to(dev)
+    # the batches of CHUNK steps are gathered at once (one copy per chunk,
+    # not three per step); a step's batch is then a contiguous slice
+    CHUNK = 64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        idx = order[k * batch:(k + 1) * batch]
-        Tb = T.index_select(0, idx).contiguous()
-        Wb = W.index_select(0, idx).contiguous()
-        Sb = S.index_select(0, idx).contiguous()
+        if k % CHUNK == 0:
+            idx = order[k * batch:min(k + CHUNK, steps) * batch]
+            Tc, Wc, Sc = T.index_select(0, idx), W.index_select(0, idx), S.index_select(0, idx)
+        r0 = (k % CHUNK) * batch
+        Tb, Wb, Sb = Tc[r0:r0 + batch], Wc[r0:r0 + batch], Sc[r0:r0 + batch]
         mlp.imle_step(feats, Sb, Tb, n_draws, seed * 1_000_003 + k, lr, loss=losses[k:k + 1], weights=Wb)
         if log and (k + 1) % max(1, steps // 10) == 0:
             log(f"step {k + 1}/{steps}: loss {losses[max(0, k - 49):k + 1].mean().item():.4f}")

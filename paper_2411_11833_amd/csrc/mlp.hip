@@ -203,12 +203,13 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st, float* loss = nullptr, flo
     fin.loss_scale = inv;
     fin.loss = loss;
     int64_t used = 0;   // partial floats handed out so far (every layer's stay until the finish)
+    DwLayers dws{};     // the weight-gradient products, run together after the backward products
     for (int l = m->L - 1; l >= 0 && rc == CT_OK; --l) {
         const bool top = l == m->L - 1;
         const uint16_t* Dm = top ? m->GY : m->D[l];     // [rows][npad]
         const uint16_t* Dt = top ? m->GYT : m->DT[l];   // [npad][rows_cap]
-        // dW_l = D^T * H_{l-1}: split-K partials, summed with the bias
-        // gradients after the last layer
+        // dW_l = D^T * H_{l-1} (launched after the loop): split-K partials,
+        // summed with the bias gradients at the end
         GemmArgs g{};
         g.A = Dt;
         g.lda = m->rows_cap;
@@ -234,8 +235,8 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st, float* loss = nullptr, flo
             fin.part[l] = g.F;
             used += g.ksplit * g.fsplit;
         }
-        rc = gemm(EPI_DW, g, st);
-        if (rc != CT_OK || l == 0) break;
+        dws.g[l] = g;
+        if (l == 0) break;
         // D_{l-1} = (D_l * W_l) . gelu'(Z_{l-1})
         GemmArgs b{};
         b.A = Dm;
@@ -253,6 +254,22 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st, float* loss = nullptr, flo
         b.Ht = m->DT[l - 1];
         b.ldht = m->rows_cap;
         rc = gemm(EPI_BWD, b, st);
+    }
+    if (rc != CT_OK) return rc;
+    // dW_l = D_l^T H_{l-1} of every layer in one launch when every K chunk is
+    // 64 deep, else one launch per layer
+    bool deep = true;
+    dws.L = m->L;
+    for (int l = 0; l < m->L; ++l) {
+        const GemmArgs& g = dws.g[l];
+        deep = deep && (g.K / g.ksplit) % 64 == 0;
+        dws.bstart[l + 1] = dws.bstart[l] + ((g.M + GT - 1) / GT) * ((g.N + GT - 1) / GT) * g.ksplit;
+    }
+    if (deep) {
+        hipLaunchKernelGGL(gemm_dw_layers_kernel<64>, dim3((unsigned)dws.bstart[m->L]), dim3(256), 0, st, dws);
+        rc = err_of(hipGetLastError());
+    } else {
+        for (int l = 0; l < m->L && rc == CT_OK; ++l) rc = gemm(EPI_DW, dws.g[l], st);
     }
     if (rc != CT_OK) return rc;
     for (int l = 0; l < m->L; ++l) {

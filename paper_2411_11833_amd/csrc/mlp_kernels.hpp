@@ -146,8 +146,8 @@ struct GemmArgs {
     const f32x4_t* gelu_tab;   // GELU_PIECES pieces (HID_*)
 };
 
-constexpr int GT = 64;    // workgroup tile (M and N) below BIG_ROWS rows; 128 from there
-constexpr int GK = 32;    // K per stage (one MFMA deep)
+constexpr int GT = 64;    // workgroup tile (M and N) of the split-K weight-gradient products
+constexpr int GK = 32;    // K per MFMA (and the granularity of K and of split-K chunks)
 constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 
 // Epilogue of a TM x TN output tile computed by WM x WN waves (NT = 64 WM WN
@@ -229,8 +229,9 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
     }
 }
 
-// C = A * B^T over a TILE x TILE workgroup tile (TILE = 64 or 128; split-K
-// over ksplit workgroups per tile).  256 threads = 4 waves in a 2 x 2
+// C = A * B^T over a TILE x TILE workgroup tile (TILE = 64; split-K over
+// ksplit workgroups per tile): the weight-gradient products, whose K (the
+// rows of a batch) is split into chunks.  256 threads = 4 waves in a 2 x 2
 // arrangement, each wave a (TILE/2) x (TILE/2) block of FI x FI MFMA
 // 16x16x32 tiles.  Operand fragments: lane l holds row (l % 16) and K
 // elements 8 (l / 16) .. 8 (l / 16) + 7 of its 16 x 32 A and B blocks;
@@ -249,7 +250,7 @@ union GemmSmem {
 };
 
 template <int EPI, int TILE, int BK>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_nt_tile(const GemmArgs& g, int block, int n_blocks) {
     constexpr int FI = TILE / 32;           // MFMA tiles per wave and dimension
     constexpr int CPR = BK / 8;             // 16-byte chunks per row of a slice
     constexpr int RPP = 256 / CPR;          // rows one pass of the workgroup loads
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     auto& As = sm.k.A;
     auto& Bs = sm.k.B;
     const int tiles_n = (g.N + TILE - 1) / TILE;
-    int bid = xcd_swizzle((int)blockIdx.x, (int)gridDim.x);
+    int bid = xcd_swizzle(block, n_blocks);
     const int split = bid % g.ksplit;
     bid /= g.ksplit;
     const int m0 = (bid / tiles_n) * TILE, n0 = (bid % tiles_n) * TILE;
@@ -338,6 +339,29 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
     }
     // the loop ends with a barrier after the last fragment reads: the LDS is the stage now
     tile_epilogue<EPI, TILE, TILE, FI, FI>(g, acc, m0, n0, split, sm.stage, nullptr);
+}
+
+template <int EPI, int TILE, int BK>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(GemmArgs g) {
+    gemm_nt_tile<EPI, TILE, BK>(g, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Every layer's weight-gradient product of a backward pass in one launch
+// (they are independent once the backward products are done): block b runs
+// tile b - bstart[l] of layer l.
+constexpr int MAX_LAYERS = 9;
+struct DwLayers {
+    int L;
+    int bstart[MAX_LAYERS + 1];   // prefix sums of tiles * ksplit
+    GemmArgs g[MAX_LAYERS];
+};
+
+template <int BK>
+__global__ __launch_bounds__(256) void gemm_dw_layers_kernel(DwLayers a) {
+    const int b = (int)blockIdx.x;
+    int l = 0;
+    while (b >= a.bstart[l + 1]) ++l;
+    gemm_nt_tile<EPI_DW, GT, BK>(a.g[l], b - a.bstart[l], a.bstart[l + 1] - a.bstart[l]);
 }
 
 // ---------------------------------------------------------------------------
@@ -766,8 +790,6 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__
         if (lane == 0) row_loss[b] = acc;
     }
 }
-
-constexpr int MAX_LAYERS = 9;
 
 // The end of a backward pass, every layer in one launch: blockIdx.y = 0
 // sums each split-K layer's weight-gradient partials in split order,

@@ -155,8 +155,8 @@ constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 // (bias, GELU or its derivative) are formed in registers and FP32 outputs
 // stored from there; BF16 outputs are staged in LDS (`stage`, TM x (TN + 8)
 // elements, free once the main loop is done) and leave as 16-byte chunks of
-// rows, and for the training epilogues also as 16-byte chunks of the
-// transpose, so every global store of a wave is a few full cache lines.
+// rows; the training epilogues' transposed copy leaves from registers (a
+// lane holds 4 consecutive rows of one column: 8 bytes of the transpose).
 template <int EPI, int TM, int TN, int FI, int FJ, int WM = 2, int WN = 2>
 __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (&acc)[FI][FJ], int m0, int n0,
                                               int split, uint16_t* __restrict__ stage, const f32x4_t* tab) {
@@ -175,21 +175,39 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
 #pragma unroll
         for (int i = 0; i < FI; ++i) {
             const int rl0 = wm * (TM / WM) + i * 16 + (lane >> 4) * 4;
+            uint16_t h[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rl = rl0 + r, m = m0 + rl;
                 const bool ok = m < g.M && n < g.N;
                 const float v = acc[i][j][r];
+                h[r] = 0;
                 if constexpr (EPI == EPI_HID_TRAIN || EPI == EPI_HID_INFER) {
                     const float z = v + bias;
                     if (EPI == EPI_HID_TRAIN && ok) g.F[(int64_t)m * g.ldf + n] = z;
-                    stage[rl * LDT + cl] = ok ? to_bf16(gelu_tab(tab, z)) : (uint16_t)0;
+                    if (ok) h[r] = to_bf16(gelu_tab(tab, z));
+                    stage[rl * LDT + cl] = h[r];
                 } else if constexpr (EPI == EPI_BWD) {
-                    stage[rl * LDT + cl] = ok ? to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n])) : (uint16_t)0;
+                    if (ok) h[r] = to_bf16(v * gelu_grad(g.Zin[(int64_t)m * g.ldzin + n]));
+                    stage[rl * LDT + cl] = h[r];
                 } else if constexpr (EPI == EPI_OUT) {
                     if (ok) g.F[(int64_t)m * g.ldf + n] = v + bias;
                 } else {
                     if (ok) g.F[(int64_t)split * g.fsplit + (int64_t)m * g.ldf + n] = v;
+                }
+            }
+            if constexpr (TR) {
+                // the transposed copy straight from registers: this lane's 4
+                // rows are 4 consecutive entries of row n of the transpose
+                const int m = m0 + rl0;
+                if (n < g.N && m < g.M) {
+                    uint16_t* dst = g.Ht + (int64_t)n * g.ldht + m;
+                    if (m + 4 <= g.M) {
+                        *(uint2*)dst = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                  (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                    } else {
+                        for (int r = 0; r < 4 && m + r < g.M; ++r) dst[r] = h[r];
+                    }
                 }
             }
         }
@@ -205,25 +223,6 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const f32x4_t (
                 *(u32x4_t*)dst = *(const u32x4_t*)(stage + rl * LDT + cl);
             } else {
                 for (int q = 0; n + q < g.N; ++q) dst[q] = stage[rl * LDT + cl + q];
-            }
-        }
-        if constexpr (TR) {
-            constexpr int RC = TM / 8;   // 16-byte chunks of a column
-            for (int c = tid; c < TN * RC; c += NT) {
-                const int cl = c / RC, rl = (c - cl * RC) * 8, n = n0 + cl, m = m0 + rl;
-                if (n >= g.N || m >= g.M) continue;
-                uint16_t h[8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) h[q] = stage[(rl + q) * LDT + cl];
-                uint16_t* dst = g.Ht + (int64_t)n * g.ldht + m;
-                if (m + 8 <= g.M) {
-                    u32x4_t pk;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) pk[q] = (uint32_t)h[2 * q] | ((uint32_t)h[2 * q + 1] << 16);
-                    *(u32x4_t*)dst = pk;
-                } else {
-                    for (int q = 0; m + q < g.M; ++q) dst[q] = h[q];
-                }
             }
         }
     }

@@ -51,8 +51,8 @@ import numpy as np
 
 METRIC = "particle-iters/s (fwd+bwd+Adam); time-to-satisfy: plain vs learned seeds"
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published dense FP32 vector rate (packed FP32)
-# the same ALUs without packed FP32 instructions, which this build does not
-# emit: 256 CU x 4 SIMD x 16 lanes x 2 flop per FMA x 2.4 GHz
+# the same ALUs without packed FP32 instructions (these kernels are compiled
+# without them): 256 CU x 4 SIMD x 16 lanes x 2 flop per FMA x 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0       # MI355X published dense BF16 matrix rate
@@ -523,7 +523,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the particle path shards "
-              "across GPUs without per-iteration exchange, but no multi-GPU run is part of this build.",
+              "across GPUs without per-iteration exchange, but this benchmark runs on one GPU.",
               file=sys.stderr)
         sys.exit(2)
 

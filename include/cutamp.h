@@ -49,12 +49,12 @@ extern "C" {
 enum {
     CT_OK = 0,
     CT_ERR_INVALID_ARG = 1,   /* null / out-of-range / misaligned argument   */
-    CT_ERR_UNSUPPORTED = 2,   /* valid request beyond this build's limits    */
+    CT_ERR_UNSUPPORTED = 2,   /* valid request beyond the library's limits  */
     CT_ERR_ALLOC = 3,         /* device allocation failed (create only)      */
     CT_ERR_DEVICE = 4         /* a HIP runtime call or kernel launch failed  */
 };
 
-/* Limits of this build (CT_ERR_UNSUPPORTED beyond them). */
+/* Limits of the library (CT_ERR_UNSUPPORTED beyond them). */
 #define CT_N_JOINTS 7
 #define CT_MAX_STEPS 6
 #define CT_MAX_ROBOT_SPHERES 128

@@ -5,7 +5,7 @@ imports it).
 Sec. V composes parallel samplers, each solving a subgraph of the constraint
 network: a grasp sampler for the Grasp constraint, a placement sampler for
 the stable placement, and a configuration sampler conditioned on both (the
-paper's cuRobo IK; in this build the same fused cost, optimized over the
+paper's cuRobo IK; here the same fused cost, optimized over the
 configurations only).  The first two are fixed here by their definitions:
 
   grasp       (gx, gy, gz) uniform in the valid grasp box, yaw uniform in

@@ -207,7 +207,7 @@ extern "C" const char* ct_status_string(int status) {
     switch (status) {
         case CT_OK: return "ok";
         case CT_ERR_INVALID_ARG: return "invalid argument";
-        case CT_ERR_UNSUPPORTED: return "unsupported by this build";
+        case CT_ERR_UNSUPPORTED: return "unsupported by this library";
         case CT_ERR_ALLOC: return "device allocation failed";
         case CT_ERR_DEVICE: return "HIP runtime or kernel launch failure";
         default: return "unknown status";

@@ -13,6 +13,7 @@ converged, standardization) are stated where they are used.
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 import time
 from dataclasses import dataclass, field
 
@@ -479,16 +480,19 @@ def equal_rate_times(times_a, times_b):
     """Coverage of each method (fraction of scenes with a satisfying
     particle), the common rate r = min of the two, and the time at which each
     method has solved a fraction r of the scenes (None if r = 0)."""
+    # The rate is kept as an exact fraction: in floating point, r * len(ts)
+    # can round above the number of solved scenes (7/25 * 25 > 7) and index
+    # past the sorted times.
     def cov(ts):
-        return sum(t is not None for t in ts) / max(1, len(ts))
+        return Fraction(sum(t is not None for t in ts), max(1, len(ts)))
 
-    ca, cb = cov(times_a), cov(times_b)
-    r = min(ca, cb)
+    fa, fb = cov(times_a), cov(times_b)
+    r = min(fa, fb)
     if r == 0:
-        return ca, cb, r, None, None
+        return float(fa), float(fb), 0.0, None, None
 
     def at(ts):
         k = max(1, math.ceil(r * len(ts)))
         return sorted(t for t in ts if t is not None)[k - 1]
 
-    return ca, cb, r, at(times_a), at(times_b)
+    return float(fa), float(fb), float(r), at(times_a), at(times_b)

@@ -139,6 +139,37 @@ int refresh(ct_mlp* m, hipStream_t st) {
     return err_of(hipGetLastError());
 }
 
+// every layer in one launch (activations kept in LDS): hidden width 512, at
+// most FUSED_MAX_OUT outputs, 8,192 rows or more.  Each workgroup reads
+// every weight once from L2, so blocks are as tall as 256 workgroups allow
+// (128 rows from 32,768 rows, 64 from 16,384, else 32); below 8,192 rows the
+// per-layer launches are faster.
+bool fused_ok(const ct_mlp* m, int64_t rows) {
+    return m->s.hidden == FH && m->s.d_out <= FUSED_MAX_OUT && rows >= 256 * 32;
+}
+
+int infer_fused(ct_mlp* m, int64_t rows, hipStream_t st) {
+    FusedArgs f{};
+    f.X = m->X0;
+    f.M = (int)rows;
+    f.kin = m->in_pad;
+    f.L = m->L;
+    f.d_out = m->s.d_out;
+    for (int l = 0; l < m->L; ++l) {
+        f.W[l] = m->Wb[l];
+        f.bias[l] = m->P + m->boff[l];
+    }
+    f.Y = m->Y;
+    f.gelu_tab = m->gelu_tab;
+    if (rows >= 256 * 128)
+        hipLaunchKernelGGL(mlp_infer_kernel<128>, dim3(blocks(rows, 128)), dim3(512), 0, st, f);
+    else if (rows >= 256 * 64)
+        hipLaunchKernelGGL(mlp_infer_kernel<64>, dim3(blocks(rows, 64)), dim3(512), 0, st, f);
+    else
+        hipLaunchKernelGGL(mlp_infer_kernel<32>, dim3(blocks(rows, 32)), dim3(512), 0, st, f);
+    return err_of(hipGetLastError());
+}
+
 // inputs + every layer; train keeps Z, H, H^T and X0^T for the backward pass
 int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
             int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st) {
@@ -160,6 +191,10 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
     const int ng = m->s.d_noise / 4, nf = m->in_pad / 4 - ng;
     hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * std::max(ng, nf), 256), 2), dim3(256), 0, st, a);
     int rc = err_of(hipGetLastError());
+    if (!train && fused_ok(m, rows)) {
+        m->fwd_rows = -1;
+        return rc == CT_OK ? infer_fused(m, rows, st) : rc;
+    }
     for (int l = 0; l < m->L && rc == CT_OK; ++l) {
         GemmArgs g{};
         g.A = l == 0 ? m->X0 : m->H[l - 1];

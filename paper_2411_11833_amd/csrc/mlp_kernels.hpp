@@ -589,6 +589,199 @@ __global__ __launch_bounds__(64 * WM * WN) void gemm_pipe_kernel(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// Inference through every layer in one launch (hidden width 512)
+//
+// A workgroup of 8 waves takes TM rows through the whole network: their
+// activations stay in LDS (TM x 512 BF16, overwritten in place by each layer
+// once every wave has read them), so only the input rows, the weights (from
+// L2, each layer's read once per workgroup) and the outputs cross the memory
+// hierarchy.  Hidden layers: wave w computes columns 64 w .. 64 w + 63 of
+// all TM rows, weight fragments straight into registers three K slices
+// ahead, activation fragments from LDS.  The MFMAs take the operands swapped (as in
+// the inference epilogue of the layer-by-layer kernel), so a lane ends with
+// 4 consecutive columns of one row: bias in the accumulators, then GELU and
+// BF16 rounding written back into LDS as 8-byte groups.  The output layer:
+// wave w computes 16-column block w of every row.  Same operations, operand
+// order and K order as the layer-by-layer inference kernels.
+
+constexpr int FH = 512;               // hidden width
+constexpr int FUSED_MAX_OUT = 128;    // output columns (8 waves x 16)
+
+struct FusedArgs {
+    const uint16_t* X;   // [M][kin] BF16 input rows
+    int M, kin, L;       // rows, padded input width (32 .. 512, multiple of 32), linear layers (2 .. MAX_LAYERS)
+    int d_out;           // 1 .. FUSED_MAX_OUT
+    const uint16_t* W[MAX_LAYERS];   // layer l: [npad][kpad] BF16 (kpad = kin for l = 0, else FH)
+    const float* bias[MAX_LAYERS];
+    float* Y;            // [M][d_out] FP32
+    const f32x4_t* gelu_tab;
+};
+
+// element offset of (row r, column c) in the LDS activations: the 16-byte
+// chunk index is XORed with r mod 16, so the 16 rows a fragment read
+// touches at one chunk land in 16 different bank groups
+__device__ __forceinline__ int fused_at(int r, int c) { return r * FH + (((c >> 3) ^ (r & 15)) << 3) + (c & 7); }
+
+// Weight fragments of FJ row blocks (rows wrow + 16 j K, K contiguous, K / 32
+// slices) go straight into registers through a ring of 4, three K slices
+// ahead.  fused_pre loads slices 0..2 (issued early, e.g. before the
+// previous layer's epilogue); fused_k then runs every slice: acc[i][j] +=
+// activation row block i (from LDS) x weight block j.  NK > 0: the slice
+// count, fully unrolled (the compiler's waits then leave exactly three
+// slices in flight); NK = 0: K / 32 at run time, in an unconditional loop of
+// 4 slices (rounded up: loads past the last slice repeat it and the
+// activations there are zero, so the extra MFMAs add exact zeros after the
+// real K range).
+template <int FJ>
+__device__ __forceinline__ void fused_wload(const uint16_t* __restrict__ wrow, int K, int s, u32x4_t (&b)[FJ]) {
+    s = min(s, (K >> 5) - 1);
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) b[j] = *(const u32x4_t*)(wrow + (int64_t)j * 16 * K + s * 32);
+}
+
+template <int FJ>
+__device__ __forceinline__ void fused_pre(const uint16_t* __restrict__ wrow, int K, u32x4_t (&w0)[FJ],
+                                          u32x4_t (&w1)[FJ], u32x4_t (&w2)[FJ]) {
+    fused_wload<FJ>(wrow, K, 0, w0);
+    fused_wload<FJ>(wrow, K, 1, w1);
+    fused_wload<FJ>(wrow, K, 2, w2);
+}
+
+template <int FI, int FJ, int NK>
+__device__ __forceinline__ void fused_k(f32x4_t (&acc)[FI][FJ], const uint16_t* __restrict__ wrow, int K,
+                                        const uint16_t* hs, u32x4_t (&w0)[FJ], u32x4_t (&w1)[FJ],
+                                        u32x4_t (&w2)[FJ], u32x4_t (&w3)[FJ]) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, q = lane >> 4;
+    auto step = [&](int s, const u32x4_t (&cur)[FJ], u32x4_t (&nxt)[FJ]) {
+        fused_wload<FJ>(wrow, K, s + 3, nxt);   // into the registers slice s - 1 used
+        // keep the loads here: left alone, the scheduler sinks them next to
+        // their first use a ring later, which exposes their latency
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < FI; ++i) {
+            const bf16x8_t af =
+                __builtin_bit_cast(bf16x8_t, *(const u32x4_t*)(hs + fused_at(i * 16 + r16, s * 32 + q * 8)));
+#pragma unroll
+            for (int j = 0; j < FJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, cur[j]), af,
+                                                                   acc[i][j], 0, 0, 0);
+        }
+    };
+    auto four = [&](int s) {
+        step(s, w0, w3);
+        step(s + 1, w1, w0);
+        step(s + 2, w2, w1);
+        step(s + 3, w3, w2);
+    };
+    if constexpr (NK > 0) {
+        static_assert(NK % 4 == 0, "whole rings");
+#pragma unroll
+        for (int s = 0; s < NK; s += 4) four(s);
+    } else {
+        const int nk4 = ((K >> 5) + 3) & ~3;
+        for (int s = 0; s < nk4; s += 4) four(s);
+    }
+}
+
+// TM rows per workgroup (32, 64 or 128): TM / 16 row blocks of 16 per wave
+template <int TM>
+__global__ __launch_bounds__(512) void mlp_infer_kernel(FusedArgs a) {
+    constexpr int FI = TM / 16;
+    __shared__ __attribute__((aligned(1024))) uint16_t hs[TM * FH];
+    __shared__ f32x4_t tab[GELU_PIECES];
+    __shared__ f32x4_t bs[(MAX_LAYERS - 1) * FH / 4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int m0 = xcd_swizzle((int)blockIdx.x, (int)gridDim.x) * TM;
+    const int n0 = w * 16;   // the output layer's columns of this wave
+    const int lo = a.L - 1;
+    // hidden weight rows 64 w + 16 j + r16, output weight rows n0 + r16
+    // (present up to the padded row count), 8 K values at 32 s + 8 q
+    auto hrow = [&](int l) { return a.W[l] + (int64_t)(w * 64 + r16) * (l == 0 ? a.kin : FH) + q * 8; };
+    const uint16_t* orow = a.W[lo] + (int64_t)(n0 + r16) * FH + q * 8;
+    u32x4_t w0[4], w1[4], w2[4], w3[4];
+    fused_pre<4>(hrow(0), a.kin, w0, w1, w2);
+    // input rows (rows past M repeat row M - 1; their outputs are not
+    // stored), zeros up to the first layer's K rounded to 4 slices
+    const int cpr = a.kin >> 3, cpz = (((a.kin >> 5) + 3) & ~3) * 4;
+    for (int e = tid; e < TM * cpz; e += 512) {
+        const int r = e / cpz, c = e - r * cpz;
+        const int row = min(m0 + r, a.M - 1);
+        u32x4_t v = {0u, 0u, 0u, 0u};
+        if (c < cpr) v = *(const u32x4_t*)(a.X + (int64_t)row * a.kin + c * 8);
+        *(u32x4_t*)(hs + fused_at(r, c * 8)) = v;
+    }
+    static_assert(GELU_PIECES == 512, "one table piece per thread");
+    tab[tid] = a.gelu_tab[tid];
+    // hidden biases in LDS too (read at each layer's start without waiting
+    // for weight loads in flight)
+    for (int e = tid; e < (a.L - 1) * (FH / 4); e += 512) {
+        const float* b = a.bias[e / (FH / 4)] + 4 * (e % (FH / 4));
+        bs[e] = f32x4_t{b[0], b[1], b[2], b[3]};
+    }
+    __syncthreads();
+
+    u32x4_t o0[1], o1[1], o2[1], o3[1];
+    for (int l = 0; l < lo; ++l) {
+        f32x4_t acc[FI][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const f32x4_t b0 = bs[l * (FH / 4) + w * 16 + j * 4 + q];
+#pragma unroll
+            for (int i = 0; i < FI; ++i) acc[i][j] = b0;
+        }
+        fused_k<FI, 4, 0>(acc, hrow(l), l == 0 ? a.kin : FH, hs, w0, w1, w2, w3);
+        // the next layer's first weight slices travel during the epilogue
+        if (l + 1 < lo)
+            fused_pre<4>(hrow(l + 1), FH, w0, w1, w2);
+        else if (n0 < a.d_out)
+            fused_pre<1>(orow, FH, o0, o1, o2);
+        __syncthreads();   // every wave has read this layer's inputs
+#pragma unroll
+        for (int i = 0; i < FI; ++i) {
+            const int r = i * 16 + r16;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = w * 64 + j * 16 + 4 * q;
+                const uint2 h = make_uint2(pack_bf16(gelu_tab(tab, acc[i][j][0]), gelu_tab(tab, acc[i][j][1])),
+                                           pack_bf16(gelu_tab(tab, acc[i][j][2]), gelu_tab(tab, acc[i][j][3])));
+                *(uint2*)(hs + fused_at(r, c)) = h;
+            }
+        }
+        __syncthreads();
+    }
+
+    // output layer: wave w, columns n0 .. n0 + 15
+    if (n0 >= a.d_out) return;
+    f32x4_t acc[FI][1];
+    {
+        f32x4_t b0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = n0 + 4 * q + r;
+            b0[r] = n < a.d_out ? a.bias[lo][n] : 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < FI; ++i) acc[i][0] = b0;
+    }
+    fused_k<FI, 1, 0>(acc, orow, FH, hs, o0, o1, o2, o3);
+    const bool vec_out = (a.d_out & 3) == 0;
+#pragma unroll
+    for (int i = 0; i < FI; ++i) {
+        const int m = m0 + i * 16 + r16, n = n0 + 4 * q;
+        if (m >= a.M) continue;
+        float* dst = a.Y + (int64_t)m * a.d_out + n;
+        if (vec_out && n + 4 <= a.d_out) {
+            *(f32x4_t*)dst = acc[i][0];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (n + r < a.d_out) dst[r] = acc[i][0][r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // input rows: [features | noise | zero padding] in BF16
 
 struct InputArgs {

@@ -38,6 +38,7 @@ SHAPES = {
     # d_feat, d_noise, hidden, depth, d_out
     "small": (8, 8, 64, 2, 5),
     "proposer": (120, 32, 512, 3, 84),
+    "narrow": (64, 32, 512, 1, 21),
 }
 
 
@@ -66,12 +67,14 @@ def _elementwise(got, want, axis=None):
     return float(np.max(np.abs(got - want) / (ULP_BF16 * (np.abs(want) + rms) + 1e-30)))
 
 
-def _setup(name, rows, seed=0):
+def _setup(name, rows, seed=0, noise_gain=1.0, draws=1):
     shape = SHAPES[name]
     d_feat, d_noise, hidden, depth, d_out = shape
-    m = _mlp(shape, max_rows=max(4096, ((rows + 63) // 64) * 64))
+    m = _mlp(shape, max_rows=max(4096, ((rows * draws + 63) // 64) * 64))
     dims = MO.layer_dims(d_feat + d_noise, hidden, depth, d_out)
     p = I.mlp_init(dims, seed)
+    i, o = dims[0]
+    p[:i * o].reshape(o, i)[:, d_feat:] *= noise_gain   # first-layer weights of the noise inputs
     m.set_params(_dev(p))
     rng = np.random.default_rng(seed)
     feats = rng.standard_normal((5, d_feat)).astype(np.float32)
@@ -90,15 +93,20 @@ def test_noise_matches_oracle():
     m.close()
 
 
+# keep=True runs the training forward, layer by layer (Z, H and H^T kept):
 # 16384 and more rows take the 256 x 256 hidden and 128 x 128 output tiles
-# of the pipelined kernel, fewer rows its 32 x 64 and 32 x 32 tiles; 4100,
-# 5000 and 16400 leave ragged last tiles.  keep=False runs the inference
-# epilogues (transposed accumulators, stores from registers), keep=True the
-# training ones (Z, H and H^T kept).
+# of the pipelined kernel, fewer rows its 32 x 64 and 32 x 32 tiles.
+# keep=False runs inference: from 8192 rows width-512 networks run in one
+# launch for all layers, in 32-row blocks below 16384 rows, 64-row blocks
+# up to 32767, 128-row blocks from there (narrow: one hidden layer, 21
+# outputs); fewer rows and the width-64 network run layer by layer with the
+# inference epilogues.  200, 4100, 5000, 8200, 16400, 32800 and 33000 rows
+# leave ragged last tiles.
 @pytest.mark.parametrize("keep", [True, False])
 @pytest.mark.parametrize("name,rows", [("small", 100), ("small", 64), ("proposer", 4096), ("proposer", 200),
                                        ("proposer", 4100), ("small", 5000), ("proposer", 16400),
-                                       ("small", 16384)])
+                                       ("small", 16384), ("proposer", 8200), ("proposer", 32800),
+                                       ("narrow", 300), ("narrow", 33000)])
 def test_forward_matches_oracle(name, rows, keep):
     m, dims, p, feats, fr, draw = _setup(name, rows)
     Y = m.forward(_dev(feats), rows, 77, _dev(fr, torch.int32), _dev(draw, torch.int32), keep=keep).cpu().numpy()
@@ -152,10 +160,17 @@ def test_backward_rejects_rows_other_than_forward():
     m.close()
 
 
+# the proposer's selection forward: 2,048 draws layer by layer, the
+# training step's 1,024 targets x 32 draws in the one-launch inference
+# kernel (128-row blocks)
 @pytest.mark.parametrize("weighted", [False, True])
-def test_imle_step_matches_oracle(weighted):
-    name, rows, S = "small", 128, 4
-    m, dims, p, feats, fr, _ = _setup(name, rows, seed=2)
+@pytest.mark.parametrize("name,rows,S", [("small", 128, 4), ("proposer", 256, 8), ("proposer", 1024, 32)])
+def test_imle_step_matches_oracle(weighted, name, rows, S):
+    # at the default initialization the wide network's draws differ too
+    # little for most nearest-draw choices to be clear; larger noise weights
+    # spread them
+    m, dims, p, feats, fr, _ = _setup(name, rows, seed=2, noise_gain=16.0 if name == "proposer" else 1.0,
+                                       draws=S)
     rng = np.random.default_rng(12)
     T = rng.standard_normal((rows, m.d_out)).astype(np.float32)
     W = rng.integers(0, 2, (rows, m.d_out)).astype(np.float32) if weighted else None

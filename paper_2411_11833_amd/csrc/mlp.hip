@@ -170,9 +170,10 @@ int infer_fused(ct_mlp* m, int64_t rows, hipStream_t st) {
     return err_of(hipGetLastError());
 }
 
-// inputs + every layer; train keeps Z, H, H^T and X0^T for the backward pass
+// inputs + every layer (out_layer false: the hidden layers only); train
+// keeps Z, H, H^T and X0^T for the backward pass
 int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
-            int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st) {
+            int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st, bool out_layer = true) {
     InputArgs a{};
     a.feats = feats;
     a.n_feats = n_feats;
@@ -195,7 +196,7 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
         m->fwd_rows = -1;
         return rc == CT_OK ? infer_fused(m, rows, st) : rc;
     }
-    for (int l = 0; l < m->L && rc == CT_OK; ++l) {
+    for (int l = 0; l < (out_layer ? m->L : m->L - 1) && rc == CT_OK; ++l) {
         GemmArgs g{};
         g.A = l == 0 ? m->X0 : m->H[l - 1];
         g.lda = l == 0 ? m->in_pad : m->s.hidden;
@@ -497,8 +498,9 @@ int ct_mlp_infer(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t
 int ct_mlp_backward(ct_mlp* mlp, const float* dY, int64_t rows, void* stream) {
     if (!mlp || !dY || rows <= 0 || rows % 64 != 0 || rows != mlp->fwd_rows) return CT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const float*)nullptr,
-                       (const float*)nullptr, mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY, mlp->GYT, mlp->rows_cap, (float*)nullptr);
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const int32_t*)nullptr, 1,
+                       (const float*)nullptr, (const float*)nullptr, mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY,
+                       mlp->GYT, mlp->rows_cap, (float*)nullptr);
     const int rc = err_of(hipGetLastError());
     return rc != CT_OK ? rc : backward(mlp, rows, st);
 }
@@ -523,12 +525,15 @@ int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int
     hipLaunchKernelGGL(imle_select_kernel, dim3((unsigned)rows), dim3(256), 0, st, mlp->Y, targets, weights,
                        mlp->s.d_out, rows, n_draws, sel);
     rc = err_of(hipGetLastError());
-    // 3. the kept draws again, keeping activations; 4. squared error
-    if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st);
+    // 3. the kept draws' hidden layers again, keeping activations (their
+    // outputs are the selection forward's: same inputs, same weights);
+    // 4. squared error at those outputs
+    if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st, false);
     if (rc != CT_OK) return rc;
     const float scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
-    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, targets, weights,
-                       mlp->s.d_out, mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap, mlp->row_loss);
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, sel, n_draws, targets,
+                       weights, mlp->s.d_out, mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap,
+                       mlp->row_loss);
     rc = err_of(hipGetLastError());
     // 5. backward (and the loss) and Adam
     if (rc == CT_OK) rc = backward(mlp, rows, st, loss, (float)(1.0 / ((double)rows * mlp->s.d_out)));

@@ -950,8 +950,10 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
 
 // Upstream gradient of the output layer in BF16, both orientations.  With
 // targets: g = scale w (y - t) and the row's sum of w (y - t)^2 (w = 1 when
-// W is null); without: g = y.
-__global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+// W is null); without: g = y.  Row b's y is row b of Y, or with sel row
+// b draws + sel[b] (the chosen draw's output of a forward over all draws).
+__global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const int32_t* __restrict__ sel,
+                                                       int draws, const float* __restrict__ T,
                                                        const float* __restrict__ W, int d_out, int out_pad,
                                                        int64_t rows, float scale,
                                                        uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT,
@@ -959,11 +961,12 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__
     const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (b >= rows) return;
+    const int64_t yr = sel ? b * draws + sel[b] : b;
     float acc = 0.f;
     for (int d = lane; d < out_pad; d += 64) {
         float gv = 0.f;
         if (d < d_out) {
-            const float y = Y[b * d_out + d];
+            const float y = Y[yr * d_out + d];
             if (T) {
                 const float w = W ? W[b * d_out + d] : 1.f;
                 const float df = y - T[b * d_out + d];

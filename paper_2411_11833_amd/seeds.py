@@ -338,11 +338,13 @@ class TrainLog:
 
 def step_flops(dims, rows: int, n_draws: int) -> float:
     """Matrix-product flops of one IMLE step (2 per multiply-add): a forward
-    over rows * n_draws draws, a forward over rows, and the two backward
+    over rows * n_draws draws, the hidden layers again over the rows kept
+    (their outputs come from the first forward), and the two backward
     products (dW, dH) per layer; the first layer has no dH."""
     fwd = sum(2.0 * i * o for i, o in dims)
+    hid = sum(2.0 * i * o for i, o in dims[:-1])
     bwd = sum(2.0 * i * o for i, o in dims) + sum(2.0 * i * o for i, o in dims[1:])
-    return rows * (n_draws * fwd + fwd + bwd)
+    return rows * (n_draws * fwd + hid + bwd)
 
 
 def train(mlp: GpuMlp, data: Dataset, stats: Stats, steps: int = 2000, batch: int = 4096, n_draws: int = 8,

@@ -624,14 +624,12 @@ __device__ __forceinline__ int fused_at(int r, int c) { return r * FH + (((c >> 
 
 // Weight fragments of FJ row blocks (rows wrow + 16 j K, K contiguous, K / 32
 // slices) go straight into registers through a ring of 4, three K slices
-// ahead.  fused_pre loads slices 0..2 (issued early, e.g. before the
-// previous layer's epilogue); fused_k then runs every slice: acc[i][j] +=
-// activation row block i (from LDS) x weight block j.  NK > 0: the slice
-// count, fully unrolled (the compiler's waits then leave exactly three
-// slices in flight); NK = 0: K / 32 at run time, in an unconditional loop of
-// 4 slices (rounded up: loads past the last slice repeat it and the
-// activations there are zero, so the extra MFMAs add exact zeros after the
-// real K range).
+// ahead (loads past the last slice repeat it, unused).  fused_pre loads
+// slices 0..2 (issued early, e.g. before the previous layer's epilogue);
+// fused_k then runs every slice: acc[i][j] += activation row block i (from
+// LDS) x weight block j.  NK > 0: the slice count, fully unrolled; NK = 0:
+// K / 32 at run time, in an unconditional loop of 4 slices (so the
+// compiler's waits leave three slices in flight) and a remainder.
 template <int FJ>
 __device__ __forceinline__ void fused_wload(const uint16_t* __restrict__ wrow, int K, int s, u32x4_t (&b)[FJ]) {
     s = min(s, (K >> 5) - 1);
@@ -678,8 +676,13 @@ __device__ __forceinline__ void fused_k(f32x4_t (&acc)[FI][FJ], const uint16_t* 
 #pragma unroll
         for (int s = 0; s < NK; s += 4) four(s);
     } else {
-        const int nk4 = ((K >> 5) + 3) & ~3;
-        for (int s = 0; s < nk4; s += 4) four(s);
+        // whole rings, then the last nk mod 4 slices (the ring ends where it
+        // started, so they take the same registers)
+        const int nk = K >> 5, n4 = nk & ~3;
+        for (int s = 0; s < n4; s += 4) four(s);
+        if (nk - n4 > 0) step(n4, w0, w3);
+        if (nk - n4 > 1) step(n4 + 1, w1, w0);
+        if (nk - n4 > 2) step(n4 + 2, w2, w1);
     }
 }
 
@@ -701,15 +704,12 @@ __global__ __launch_bounds__(512) void mlp_infer_kernel(FusedArgs a) {
     const uint16_t* orow = a.W[lo] + (int64_t)(n0 + r16) * FH + q * 8;
     u32x4_t w0[4], w1[4], w2[4], w3[4];
     fused_pre<4>(hrow(0), a.kin, w0, w1, w2);
-    // input rows (rows past M repeat row M - 1; their outputs are not
-    // stored), zeros up to the first layer's K rounded to 4 slices
-    const int cpr = a.kin >> 3, cpz = (((a.kin >> 5) + 3) & ~3) * 4;
-    for (int e = tid; e < TM * cpz; e += 512) {
-        const int r = e / cpz, c = e - r * cpz;
+    // input rows (rows past M repeat row M - 1; their outputs are not stored)
+    const int cpr = a.kin >> 3;
+    for (int e = tid; e < TM * cpr; e += 512) {
+        const int r = e / cpr, c = e - r * cpr;
         const int row = min(m0 + r, a.M - 1);
-        u32x4_t v = {0u, 0u, 0u, 0u};
-        if (c < cpr) v = *(const u32x4_t*)(a.X + (int64_t)row * a.kin + c * 8);
-        *(u32x4_t*)(hs + fused_at(r, c * 8)) = v;
+        *(u32x4_t*)(hs + fused_at(r, c * 8)) = *(const u32x4_t*)(a.X + (int64_t)row * a.kin + c * 8);
     }
     static_assert(GELU_PIECES == 512, "one table piece per thread");
     tab[tid] = a.gelu_tab[tid];

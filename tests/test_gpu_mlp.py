@@ -39,6 +39,7 @@ SHAPES = {
     "small": (8, 8, 64, 2, 5),
     "proposer": (120, 32, 512, 3, 84),
     "narrow": (64, 32, 512, 1, 21),
+    "deep": (8, 8, 512, 8, 7),
 }
 
 
@@ -99,14 +100,14 @@ def test_noise_matches_oracle():
 # keep=False runs inference: from 8192 rows width-512 networks run in one
 # launch for all layers, in 32-row blocks below 16384 rows, 64-row blocks
 # up to 32767, 128-row blocks from there (narrow: one hidden layer, 21
-# outputs); fewer rows and the width-64 network run layer by layer with the
-# inference epilogues.  200, 4100, 5000, 8200, 16400, 32800 and 33000 rows
-# leave ragged last tiles.
+# outputs; deep: the most hidden layers, 7 outputs); fewer rows and the
+# width-64 network run layer by layer with the inference epilogues.  200,
+# 4100, 5000, 8200, 16400, 32800 and 33000 rows leave ragged last tiles.
 @pytest.mark.parametrize("keep", [True, False])
 @pytest.mark.parametrize("name,rows", [("small", 100), ("small", 64), ("proposer", 4096), ("proposer", 200),
                                        ("proposer", 4100), ("small", 5000), ("proposer", 16400),
                                        ("small", 16384), ("proposer", 8200), ("proposer", 32800),
-                                       ("narrow", 300), ("narrow", 33000)])
+                                       ("narrow", 300), ("narrow", 33000), ("deep", 8200)])
 def test_forward_matches_oracle(name, rows, keep):
     m, dims, p, feats, fr, draw = _setup(name, rows)
     Y = m.forward(_dev(feats), rows, 77, _dev(fr, torch.int32), _dev(draw, torch.int32), keep=keep).cpu().numpy()

@@ -510,9 +510,10 @@ int ct_mlp_noise(const ct_mlp *mlp, uint64_t seed, const int32_t *draw, int64_t 
  */
 int ct_mlp_forward(ct_mlp *mlp, const float *feats, int64_t n_feats, const int32_t *feat_of_row,
                    const int32_t *draw, int64_t rows, uint64_t seed, float *Y, void *stream);
-/* The same Y without keeping activations (the inference epilogues the
- * nearest-draw selection and seeding use; invalidates the activations a
- * previous ct_mlp_forward kept). */
+/* The same Y without keeping activations, by the kernels the nearest-draw
+ * selection and seeding use (from 8,192 rows, for hidden width 512 and at
+ * most 128 outputs, every layer in one launch); invalidates the
+ * activations a previous ct_mlp_forward kept. */
 int ct_mlp_infer(ct_mlp *mlp, const float *feats, int64_t n_feats, const int32_t *feat_of_row,
                  const int32_t *draw, int64_t rows, uint64_t seed, float *Y, void *stream);
 

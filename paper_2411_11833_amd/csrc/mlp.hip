@@ -170,10 +170,9 @@ int infer_fused(ct_mlp* m, int64_t rows, hipStream_t st) {
     return err_of(hipGetLastError());
 }
 
-// inputs + every layer (out_layer false: the hidden layers only); train
-// keeps Z, H, H^T and X0^T for the backward pass
-int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
-            int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st, bool out_layer = true) {
+// where the input rows go (X0, and X0^T when training) and what they hold
+InputArgs input_args(const ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row,
+                     const int32_t* draw, int draws, int64_t rows, uint64_t seed, bool train) {
     InputArgs a{};
     a.feats = feats;
     a.n_feats = n_feats;
@@ -189,9 +188,22 @@ int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_
     a.X0 = m->X0;
     a.X0T = train ? m->X0T : nullptr;
     a.ldt = m->rows_cap;
-    const int ng = m->s.d_noise / 4, nf = m->in_pad / 4 - ng;
-    hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * std::max(ng, nf), 256), 2), dim3(256), 0, st, a);
-    int rc = err_of(hipGetLastError());
+    return a;
+}
+
+// inputs + every layer (out_layer false: the hidden layers only; build
+// false: the input rows are already in X0 / X0^T); train keeps Z, H, H^T
+// and X0^T for the backward pass
+int forward(ct_mlp* m, const float* feats, int64_t n_feats, const int32_t* feat_of_row, const int32_t* draw,
+            int draws, int64_t rows, uint64_t seed, bool train, hipStream_t st, bool out_layer = true,
+            bool build = true) {
+    int rc = CT_OK;
+    if (build) {
+        const InputArgs a = input_args(m, feats, n_feats, feat_of_row, draw, draws, rows, seed, train);
+        const int ng = m->s.d_noise / 4, nf = m->in_pad / 4 - ng;
+        hipLaunchKernelGGL(build_inputs_kernel, dim3(blocks(rows * std::max(ng, nf), 256), 2), dim3(256), 0, st, a);
+        rc = err_of(hipGetLastError());
+    }
     if (!train && fused_ok(m, rows)) {
         m->fwd_rows = -1;
         return rc == CT_OK ? infer_fused(m, rows, st) : rc;
@@ -498,9 +510,9 @@ int ct_mlp_infer(ct_mlp* mlp, const float* feats, int64_t n_feats, const int32_t
 int ct_mlp_backward(ct_mlp* mlp, const float* dY, int64_t rows, void* stream) {
     if (!mlp || !dY || rows <= 0 || rows % 64 != 0 || rows != mlp->fwd_rows) return CT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const int32_t*)nullptr, 1,
-                       (const float*)nullptr, (const float*)nullptr, mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY,
-                       mlp->GYT, mlp->rows_cap, (float*)nullptr);
+    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, dY, (const float*)nullptr,
+                       (const float*)nullptr, mlp->s.d_out, mlp->out_pad, rows, 1.f, mlp->GY, mlp->GYT, mlp->rows_cap,
+                       (float*)nullptr);
     const int rc = err_of(hipGetLastError());
     return rc != CT_OK ? rc : backward(mlp, rows, st);
 }
@@ -519,23 +531,32 @@ int ct_mlp_imle_step(ct_mlp* mlp, const float* feats, int64_t n_feats, const int
     hipStream_t st = (hipStream_t)stream;
     const int64_t nf = n_feats < 1 ? 1 : n_feats;
     int32_t* sel = chosen ? chosen : mlp->chosen;
-    // 1. every draw, inference only; 2. the nearest draw per target
+    // 1. every draw, inference only; 2. the nearest draw per target, with
+    // the squared-error gradient at its output and its input row for 3.
     int rc = forward(mlp, feats, nf, feat_of_row, nullptr, n_draws, rows * n_draws, seed, false, st);
     if (rc != CT_OK) return rc;
-    hipLaunchKernelGGL(imle_select_kernel, dim3((unsigned)rows), dim3(256), 0, st, mlp->Y, targets, weights,
-                       mlp->s.d_out, rows, n_draws, sel);
+    SelectArgs sa{};
+    sa.Y = mlp->Y;
+    sa.T = targets;
+    sa.W = weights;
+    sa.d_out = mlp->s.d_out;
+    sa.B = rows;
+    sa.S = n_draws;
+    sa.chosen = sel;
+    sa.out_pad = mlp->out_pad;
+    sa.scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
+    sa.GY = mlp->GY;
+    sa.GYT = mlp->GYT;
+    sa.ldt = mlp->rows_cap;
+    sa.row_loss = mlp->row_loss;
+    sa.in = input_args(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true);
+    hipLaunchKernelGGL(imle_select_kernel, dim3((unsigned)rows), dim3(256), 0, st, sa);
     rc = err_of(hipGetLastError());
     // 3. the kept draws' hidden layers again, keeping activations (their
-    // outputs are the selection forward's: same inputs, same weights);
-    // 4. squared error at those outputs
-    if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st, false);
+    // outputs are the selection forward's: same inputs, same weights)
+    if (rc == CT_OK) rc = forward(mlp, feats, nf, feat_of_row, sel, 0, rows, seed, true, st, false, false);
     if (rc != CT_OK) return rc;
-    const float scale = (float)(2.0 / ((double)rows * mlp->s.d_out));
-    hipLaunchKernelGGL(out_grad_kernel, dim3(blocks(rows, 4)), dim3(256), 0, st, mlp->Y, sel, n_draws, targets,
-                       weights, mlp->s.d_out, mlp->out_pad, rows, scale, mlp->GY, mlp->GYT, mlp->rows_cap,
-                       mlp->row_loss);
-    rc = err_of(hipGetLastError());
-    // 5. backward (and the loss) and Adam
+    // 4. backward (and the loss) and Adam
     if (rc == CT_OK) rc = backward(mlp, rows, st, loss, (float)(1.0 / ((double)rows * mlp->s.d_out)));
     if (rc == CT_OK) rc = adam(mlp, t, adam_args, st);
     return rc;

@@ -875,6 +875,49 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Upstream gradient of the output layer in BF16, both orientations, for
+// row b, by one wave.  With targets: g = scale w (y - t) and the row's sum
+// of w (y - t)^2 (w = 1 when wt is null); without: g = y.
+__device__ __forceinline__ void out_grad_row(const float* __restrict__ y, const float* __restrict__ t,
+                                             const float* __restrict__ wt, int d_out, int out_pad, float scale,
+                                             uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT, int64_t ldt,
+                                             int64_t b, float* __restrict__ row_loss) {
+    const int lane = threadIdx.x & 63;
+    float acc = 0.f;
+    for (int d = lane; d < out_pad; d += 64) {
+        float gv = 0.f;
+        if (d < d_out) {
+            if (t) {
+                const float w = wt ? wt[d] : 1.f;
+                const float df = y[d] - t[d];
+                acc += w * df * df;
+                gv = scale * (w * df);
+            } else {
+                gv = y[d];
+            }
+        }
+        const uint16_t h = to_bf16(gv);
+        GY[b * out_pad + d] = h;
+        GYT[(int64_t)d * ldt + b] = h;
+    }
+    if (t && row_loss) {
+        acc = wave_sum(acc);
+        if (lane == 0) row_loss[b] = acc;
+    }
+}
+
+// the same for every row of Y (a wave per row)
+__global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                       const float* __restrict__ W, int d_out, int out_pad,
+                                                       int64_t rows, float scale,
+                                                       uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT,
+                                                       int64_t ldt, float* __restrict__ row_loss) {
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= rows) return;
+    out_grad_row(Y + b * d_out, T ? T + b * d_out : nullptr, W ? W + b * d_out : nullptr, d_out, out_pad, scale,
+                 GY, GYT, ldt, b, row_loss);
+}
+
 // Nearest draw per target (IMLE): chosen[b] = argmin over the S draws s of
 // sum_d w_d (Y[b S + s][d] - T[b][d])^2 (w = 1 when W is null; lowest s
 // among equals).  One workgroup per target: with S <= 256 the draws are
@@ -882,22 +925,63 @@ __device__ __forceinline__ float wave_sum(float v) {
 // P-th dimension), so four waves' loads are in flight together and each
 // lane's chain is d_out / P long; the P partial sums of a draw are added in
 // lane order through LDS and the first wave finds the minimum.  More than
-// 256 draws: the first wave takes one draw after another.
-__global__ __launch_bounds__(256) void imle_select_kernel(const float* __restrict__ Y, const float* __restrict__ T,
-                                                          const float* __restrict__ W, int d_out, int64_t B, int S,
-                                                          int32_t* __restrict__ chosen) {
+// 256 draws: the first wave takes one draw after another.  The first wave
+// then writes, for the chosen draw, what the rest of a training step needs
+// of it: the squared-error gradient of its output (out_grad_row, from the
+// output already in Y) and its input row for the second pass (the values
+// build_inputs_kernel would write for logical row b, draw chosen[b]).
+struct SelectArgs {
+    const float* Y;       // [B S][d_out]
+    const float* T;       // [B][d_out]
+    const float* W;       // [B][d_out] or null
+    int d_out;
+    int64_t B;
+    int S;
+    int32_t* chosen;      // [B]
+    int out_pad;          // gradient rows [B][out_pad] and columns [out_pad][ldt]
+    float scale;
+    uint16_t *GY, *GYT;
+    int64_t ldt;
+    float* row_loss;      // [B]
+    InputArgs in;         // X0, X0T (ldt) for rows b = 0..B-1
+};
+
+__device__ __forceinline__ void select_finish(const SelectArgs& a, int64_t b, int s) {
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) a.chosen[b] = s;
+    out_grad_row(a.Y + (b * a.S + s) * a.d_out, a.T + b * a.d_out, a.W ? a.W + b * a.d_out : nullptr, a.d_out,
+                 a.out_pad, a.scale, a.GY, a.GYT, a.ldt, b, a.row_loss);
+    const InputArgs& in = a.in;
+    for (int gi = lane; gi < in.in_pad / 4; gi += 64) {
+        const int c = 4 * gi;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (c >= in.d_feat && c < in.d_feat + in.d_noise) {
+            normal4((uint32_t)b, (uint32_t)s, (uint32_t)(c - in.d_feat) / 4u, in.k0, in.k1, v);
+        } else if (c < in.d_feat) {
+            int64_t f = in.feat_of_row ? (int64_t)in.feat_of_row[b] : 0;
+            f = f < 0 ? 0 : (f >= in.n_feats ? in.n_feats - 1 : f);
+            const float* src = in.feats + f * in.d_feat + c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = src[q];
+        }
+        put_group(in, (uint32_t)b, c, pack4_bf16(v));
+    }
+}
+
+__global__ __launch_bounds__(256) void imle_select_kernel(SelectArgs a) {
     __shared__ float part[256];
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
-    if (b >= B) return;   // workgroup-uniform
-    const float* t = T + b * d_out;
-    const float* wt = W ? W + b * d_out : nullptr;
+    if (b >= a.B) return;   // workgroup-uniform
+    const int d_out = a.d_out, S = a.S;
+    const float* t = a.T + b * d_out;
+    const float* wt = a.W ? a.W + b * d_out : nullptr;
     if (S <= 256) {
         const int P = 256 / S;
         const int s = tid / P, q = tid - s * P;
         float acc = 0.f;
         if (s < S) {
-            const float* y = Y + (b * S + s) * d_out;
+            const float* y = a.Y + (b * S + s) * d_out;
             for (int d = q; d < d_out; d += P) {
                 const float df = y[d] - t[d];
                 acc += (wt ? wt[d] : 1.f) * df * df;
@@ -916,7 +1000,8 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
                 idx = i;
             }
         }
-        // argmin across the wave, lowest draw among equal distances
+        // argmin across the wave (every lane ends with it), lowest draw among
+        // equal distances
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             const float od = __shfl_xor(dist, o);
@@ -926,14 +1011,14 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
                 idx = oi;
             }
         }
-        if (lane == 0) chosen[b] = idx;
+        select_finish(a, b, idx);
         return;
     }
     if (tid >= 64) return;
     float best = 0.f;
     int bi = 0;
     for (int s = 0; s < S; ++s) {
-        const float* y = Y + (b * S + s) * d_out;
+        const float* y = a.Y + (b * S + s) * d_out;
         float acc = 0.f;
         for (int d = lane; d < d_out; d += 64) {
             const float df = y[d] - t[d];
@@ -945,45 +1030,7 @@ __global__ __launch_bounds__(256) void imle_select_kernel(const float* __restric
             bi = s;
         }
     }
-    if (lane == 0) chosen[b] = bi;
-}
-
-// Upstream gradient of the output layer in BF16, both orientations.  With
-// targets: g = scale w (y - t) and the row's sum of w (y - t)^2 (w = 1 when
-// W is null); without: g = y.  Row b's y is row b of Y, or with sel row
-// b draws + sel[b] (the chosen draw's output of a forward over all draws).
-__global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__ Y, const int32_t* __restrict__ sel,
-                                                       int draws, const float* __restrict__ T,
-                                                       const float* __restrict__ W, int d_out, int out_pad,
-                                                       int64_t rows, float scale,
-                                                       uint16_t* __restrict__ GY, uint16_t* __restrict__ GYT,
-                                                       int64_t ldt, float* __restrict__ row_loss) {
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (b >= rows) return;
-    const int64_t yr = sel ? b * draws + sel[b] : b;
-    float acc = 0.f;
-    for (int d = lane; d < out_pad; d += 64) {
-        float gv = 0.f;
-        if (d < d_out) {
-            const float y = Y[yr * d_out + d];
-            if (T) {
-                const float w = W ? W[b * d_out + d] : 1.f;
-                const float df = y - T[b * d_out + d];
-                acc += w * df * df;
-                gv = scale * (w * df);
-            } else {
-                gv = y;
-            }
-        }
-        const uint16_t h = to_bf16(gv);
-        GY[b * out_pad + d] = h;
-        GYT[(int64_t)d * ldt + b] = h;
-    }
-    if (T && row_loss) {
-        acc = wave_sum(acc);
-        if (lane == 0) row_loss[b] = acc;
-    }
+    select_finish(a, b, bi);
 }
 
 // The end of a backward pass, every layer in one launch: blockIdx.y = 0

@@ -193,14 +193,25 @@ def test_imle_step_matches_oracle(weighted, name, rows, S):
     got_c = chosen.cpu().numpy()
     assert clear.mean() > 0.9
     np.testing.assert_array_equal(got_c[clear], wc[clear])
-    if np.all(got_c == wc):
-        assert abs(loss.item() - wl) <= 1e-3 * wl
-        assert _rel(g, wg) <= 5e-3
-        # first Adam step moves each parameter by about lr * sign(g): compare
-        # where the gradient is not tiny
-        big = np.abs(wg) > 1e-3 * np.abs(wg).max()
-        assert np.max(np.abs(p1 - w1)[big]) <= 2e-5
-        assert np.max(np.abs(p1 - w1)) <= 2.1e-3
+    # where two draws are equally near within rounding either is a valid
+    # choice: every choice must be a nearest draw to that precision, and the
+    # rest of the step is compared from the GPU's choices
+    d2all = (Wb * (Yall.reshape(rows, S, -1) - T[:, None, :]) ** 2).sum(-1)
+    assert np.all(d2all[np.arange(rows), got_c] <= d2all.min(axis=1) * (1 + 1e-3))
+    if not np.all(got_c == wc):
+        layers = MO.unflatten(p, dims)
+        Xc = MO.input_rows(feats, fr, 99, np.arange(rows), got_c, m.d_noise)
+        Yc, cache = MO.forward(layers, Xc, bf16=True)
+        wl, dYc = MO.mse(Yc, T, W)
+        wg = MO.backward(layers, cache, dYc, bf16=True)
+        w1, _, _ = MO.adam(p, zero, zero, wg, 1, 1e-3)
+    assert abs(loss.item() - wl) <= 1e-3 * wl
+    assert _rel(g, wg) <= 5e-3
+    # first Adam step moves each parameter by about lr * sign(g): compare
+    # where the gradient is not tiny
+    big = np.abs(wg) > 1e-3 * np.abs(wg).max()
+    assert np.max(np.abs(p1 - w1)[big]) <= 2e-5
+    assert np.max(np.abs(p1 - w1)) <= 2.1e-3
     m.close()
 
 

@@ -925,11 +925,12 @@ __global__ __launch_bounds__(256) void out_grad_kernel(const float* __restrict__
 // P-th dimension), so four waves' loads are in flight together and each
 // lane's chain is d_out / P long; the P partial sums of a draw are added in
 // lane order through LDS and the first wave finds the minimum.  More than
-// 256 draws: the first wave takes one draw after another.  The first wave
-// then writes, for the chosen draw, what the rest of a training step needs
-// of it: the squared-error gradient of its output (out_grad_row, from the
-// output already in Y) and its input row for the second pass (the values
-// build_inputs_kernel would write for logical row b, draw chosen[b]).
+// 256 draws: the first wave takes one draw after another.  Then, for the
+// chosen draw, what the rest of a training step needs of it: the first
+// wave writes the squared-error gradient of its output (out_grad_row, from
+// the output already in Y), the second its input row for the second pass
+// (the values build_inputs_kernel would write for logical row b, draw
+// chosen[b]).
 struct SelectArgs {
     const float* Y;       // [B S][d_out]
     const float* T;       // [B][d_out]
@@ -946,12 +947,10 @@ struct SelectArgs {
     InputArgs in;         // X0, X0T (ldt) for rows b = 0..B-1
 };
 
-__device__ __forceinline__ void select_finish(const SelectArgs& a, int64_t b, int s) {
+// the kept row's input row for draw s (what build_inputs_kernel writes for
+// logical row b, draw s), one wave
+__device__ __forceinline__ void select_input_row(const InputArgs& in, int64_t b, int s) {
     const int lane = threadIdx.x & 63;
-    if (lane == 0) a.chosen[b] = s;
-    out_grad_row(a.Y + (b * a.S + s) * a.d_out, a.T + b * a.d_out, a.W ? a.W + b * a.d_out : nullptr, a.d_out,
-                 a.out_pad, a.scale, a.GY, a.GYT, a.ldt, b, a.row_loss);
-    const InputArgs& in = a.in;
     for (int gi = lane; gi < in.in_pad / 4; gi += 64) {
         const int c = 4 * gi;
         float v[4] = {0.f, 0.f, 0.f, 0.f};
@@ -970,6 +969,7 @@ __device__ __forceinline__ void select_finish(const SelectArgs& a, int64_t b, in
 
 __global__ __launch_bounds__(256) void imle_select_kernel(SelectArgs a) {
     __shared__ float part[256];
+    __shared__ int pick;
     const int64_t b = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     if (b >= a.B) return;   // workgroup-uniform
@@ -989,48 +989,57 @@ __global__ __launch_bounds__(256) void imle_select_kernel(SelectArgs a) {
         }
         part[tid] = acc;
         __syncthreads();
-        if (tid >= 64) return;
-        float dist = INFINITY;
-        int idx = 256;
-        for (int i = lane; i < S; i += 64) {   // increasing draws: strict < keeps the lowest among equals
-            float sum = 0.f;
-            for (int j = 0; j < P; ++j) sum += part[i * P + j];
-            if (sum < dist) {
-                dist = sum;
-                idx = i;
+        if (tid < 64) {
+            float dist = INFINITY;
+            int idx = 256;
+            for (int i = lane; i < S; i += 64) {   // increasing draws: strict < keeps the lowest among equals
+                float sum = 0.f;
+                for (int j = 0; j < P; ++j) sum += part[i * P + j];
+                if (sum < dist) {
+                    dist = sum;
+                    idx = i;
+                }
             }
-        }
-        // argmin across the wave (every lane ends with it), lowest draw among
-        // equal distances
+            // argmin across the wave, lowest draw among equal distances
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const float od = __shfl_xor(dist, o);
-            const int oi = __shfl_xor(idx, o);
-            if (od < dist || (od == dist && oi < idx)) {
-                dist = od;
-                idx = oi;
+            for (int o = 32; o > 0; o >>= 1) {
+                const float od = __shfl_xor(dist, o);
+                const int oi = __shfl_xor(idx, o);
+                if (od < dist || (od == dist && oi < idx)) {
+                    dist = od;
+                    idx = oi;
+                }
+            }
+            if (lane == 0) pick = idx;
+        }
+    } else if (tid < 64) {
+        float best = 0.f;
+        int bi = 0;
+        for (int s = 0; s < S; ++s) {
+            const float* y = a.Y + (b * S + s) * d_out;
+            float acc = 0.f;
+            for (int d = lane; d < d_out; d += 64) {
+                const float df = y[d] - t[d];
+                acc += (wt ? wt[d] : 1.f) * df * df;
+            }
+            acc = wave_sum(acc);
+            if (s == 0 || acc < best) {
+                best = acc;
+                bi = s;
             }
         }
-        select_finish(a, b, idx);
-        return;
+        if (lane == 0) pick = bi;
     }
-    if (tid >= 64) return;
-    float best = 0.f;
-    int bi = 0;
-    for (int s = 0; s < S; ++s) {
-        const float* y = a.Y + (b * S + s) * d_out;
-        float acc = 0.f;
-        for (int d = lane; d < d_out; d += 64) {
-            const float df = y[d] - t[d];
-            acc += (wt ? wt[d] : 1.f) * df * df;
-        }
-        acc = wave_sum(acc);
-        if (s == 0 || acc < best) {
-            best = acc;
-            bi = s;
-        }
+    __syncthreads();
+    // the chosen draw: its loss gradient (first wave), its input row (second)
+    const int s = pick;
+    if (tid < 64) {
+        if (lane == 0) a.chosen[b] = s;
+        out_grad_row(a.Y + (b * S + s) * d_out, t, wt, d_out, a.out_pad, a.scale, a.GY, a.GYT, a.ldt, b,
+                     a.row_loss);
+    } else if (tid < 128) {
+        select_input_row(a.in, b, s);
     }
-    select_finish(a, b, bi);
 }
 
 // The end of a backward pass, every layer in one launch: blockIdx.y = 0

@@ -74,7 +74,7 @@ bool shape_ok(const ct_mlp_shape& s) {
 }
 
 // rows from which the 256 x 256 tiles keep at least half the compute units
-// busy at N = 512 (128 workgroups); below, the 32 x 64 tiles
+// busy at N = 512 (128 workgroups); below, the 32 x 32 tiles
 constexpr int BIG_ROWS = 16384;
 
 template <int TILE, int BK>
@@ -102,10 +102,12 @@ int gemm_pipe(int epi, const GemmArgs& g, hipStream_t st) {
 
 // Forward and backward products run the direct-to-LDS pipelined kernel:
 // 256 x 256 tiles (8 waves) for hidden layers over many rows, 128 x 128 for
-// the output layer there, and 32 x 64 tiles of two waves below (the fitted
-// passes of a training step: 256 workgroups at 1,024 x 512).  Weight
-// gradients take split-K over the double-buffered 64 x 64 kernel (K slices
-// 64 deep where the chunk allows).
+// the output layer there, and below (the fitted passes of a training step)
+// 32 x 32 tiles of four 16 x 16 waves with a 3-slice ring: these passes are
+// bound by load latency, and 512 workgroups of 4 waves at 1,024 x 512 keep
+// more loads in flight than 32 x 64 tiles of two waves (a training step
+// 155 us instead of 180).  Weight gradients take split-K over the
+// double-buffered 64 x 64 kernel (K slices 64 deep where the chunk allows).
 int gemm(int epi, const GemmArgs& g, hipStream_t st) {
     if (epi == EPI_DW) {
         const bool deep = (g.K / g.ksplit) % 64 == 0;
@@ -116,8 +118,7 @@ int gemm(int epi, const GemmArgs& g, hipStream_t st) {
         if (g.N > 128) return gemm_pipe<256, 256, 4, 2, 4>(epi, g, st);
         return gemm_pipe<128, 128, 2, 2, 4>(epi, g, st);
     }
-    if (g.N > 64) return gemm_pipe<32, 64, 1, 2, 4>(epi, g, st);
-    return gemm_pipe<32, 32, 1, 2, 4>(epi, g, st);
+    return gemm_pipe<32, 32, 2, 2, 3>(epi, g, st);
 }
 
 // split-K factor of a weight-gradient product: enough workgroups to cover

@@ -96,7 +96,7 @@ def test_noise_matches_oracle():
 
 # keep=True runs the training forward, layer by layer (Z, H and H^T kept):
 # 16384 and more rows take the 256 x 256 hidden and 128 x 128 output tiles
-# of the pipelined kernel, fewer rows its 32 x 64 and 32 x 32 tiles.
+# of the pipelined kernel, fewer rows its 32 x 32 tiles of four waves.
 # keep=False runs inference: from 8192 rows width-512 networks run in one
 # launch for all layers, in 32-row blocks below 16384 rows, 64-row blocks
 # up to 32767, 128-row blocks from there (narrow: one hidden layer, 21

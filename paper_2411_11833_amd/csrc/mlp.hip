@@ -107,11 +107,13 @@ int gemm_pipe(int epi, const GemmArgs& g, hipStream_t st) {
 // bound by load latency, and 512 workgroups of 4 waves at 1,024 x 512 keep
 // more loads in flight than 32 x 64 tiles of two waves (a training step
 // 155 us instead of 180).  Weight gradients take split-K over the
-// double-buffered 64 x 64 kernel (K slices 64 deep where the chunk allows).
+// double-buffered kernel: 32 x 32 tiles with K slices 64 deep (a training
+// step 152 us instead of 155 with 64 x 64 tiles), 64 x 64 tiles with
+// slices 32 deep where a K chunk is not a multiple of 64.
 int gemm(int epi, const GemmArgs& g, hipStream_t st) {
     if (epi == EPI_DW) {
         const bool deep = (g.K / g.ksplit) % 64 == 0;
-        return deep ? gemm_tile<GT, 64>(g, st) : gemm_tile<GT, 32>(g, st);
+        return deep ? gemm_tile<GT, 64>(g, st) : gemm_tile<GT_SHALLOW, 32>(g, st);
     }
     if (g.ksplit != 1) return CT_ERR_INVALID_ARG;
     if (g.M >= BIG_ROWS && epi != EPI_BWD) {

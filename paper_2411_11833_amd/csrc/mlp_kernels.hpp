@@ -146,7 +146,8 @@ struct GemmArgs {
     const f32x4_t* gelu_tab;   // GELU_PIECES pieces (HID_*)
 };
 
-constexpr int GT = 64;    // workgroup tile (M and N) of the split-K weight-gradient products
+constexpr int GT = 32;    // workgroup tile (M and N) of the split-K weight-gradient products (K slices 64 deep)
+constexpr int GT_SHALLOW = 64;   // the same where a K chunk is not a multiple of 64 (slices 32 deep)
 constexpr int GK = 32;    // K per MFMA (and the granularity of K and of split-K chunks)
 constexpr int GPAD = 8;   // LDS row padding (BF16 elements)
 

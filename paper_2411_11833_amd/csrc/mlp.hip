@@ -324,8 +324,10 @@ int backward(ct_mlp* m, int64_t rows, hipStream_t st, float* loss = nullptr, flo
     }
     if (rc != CT_OK) return rc;
     for (int l = 0; l < m->L; ++l) {
-        fin.estart[l + 1] = fin.estart[l] + (fin.ksplit[l] > 1 ? (int64_t)m->dout[l] * m->din[l] : 0);
-        fin.ostart[l + 1] = fin.ostart[l] + m->dout[l];
+        fin.ecount[l] = fin.ksplit[l] > 1 ? (int64_t)m->dout[l] * m->din[l] : 0;
+        fin.dout[l] = m->dout[l];
+        fin.estart[l + 1] = fin.estart[l] + up(fin.ecount[l], 256);
+        fin.ostart[l + 1] = fin.ostart[l] + up(m->dout[l], 4);
     }
     const int64_t nb = std::max(blocks(fin.estart[m->L], 256), blocks(fin.ostart[m->L], 4));
     hipLaunchKernelGGL(grad_finish_kernel, dim3((unsigned)nb, loss ? 3 : 2), dim3(256), 0, st, fin);
@@ -349,8 +351,8 @@ int adam(ct_mlp* m, int64_t t, const ct_adam* ad, hipStream_t st) {
     a.bc2 = (float)bc2;
     a.L = m->L;
     for (int l = 0; l < m->L; ++l) {
-        a.wstart[l + 1] = a.wstart[l] + (int64_t)m->npad[l] * m->kpad[l];
-        a.bstart[l + 1] = a.bstart[l] + m->dout[l];
+        a.wstart[l + 1] = a.wstart[l] + up((int64_t)m->npad[l] * m->kpad[l], 256);
+        a.bstart[l + 1] = a.bstart[l] + up(m->dout[l], 256);
         a.din[l] = m->din[l];
         a.dout[l] = m->dout[l];
         a.kpad[l] = m->kpad[l];

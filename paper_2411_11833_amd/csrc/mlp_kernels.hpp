@@ -1052,8 +1052,11 @@ __global__ __launch_bounds__(256) void imle_select_kernel(SelectArgs a) {
 struct GradFinishArgs {
     int L;
     int64_t rows, ldt;
-    int64_t estart[MAX_LAYERS + 1];   // prefix sums of the split-K layers' M N (0 for the others)
-    int64_t ostart[MAX_LAYERS + 1];   // prefix sums of dout
+    int64_t estart[MAX_LAYERS + 1];   // prefix sums of the split-K layers' M N (0 for the others), each
+                                      // rounded up to a multiple of 256
+    int64_t ostart[MAX_LAYERS + 1];   // prefix sums of dout, each rounded up to a multiple of 4
+    int64_t ecount[MAX_LAYERS];       // M N of a split-K layer
+    int dout[MAX_LAYERS];
     int ksplit[MAX_LAYERS];
     const float* part[MAX_LAYERS];    // [ksplit][M N] partials of a split-K layer
     float* dW[MAX_LAYERS];
@@ -1079,28 +1082,33 @@ __device__ __forceinline__ void loss_reduce(const float* __restrict__ row_loss, 
     if (threadIdx.x == 0) *loss = red[0] * inv;
 }
 
+// Each layer's ranges start at multiples of 256 (partials) and 4 (bias
+// outputs, one wave each), so a workgroup lies in one layer and the layer
+// search runs on the workgroup index (scalar loads of the arguments).
 __global__ __launch_bounds__(256) void grad_finish_kernel(GradFinishArgs a) {
     if (blockIdx.y == 2) {
         if (blockIdx.x == 0 && a.row_loss) loss_reduce(a.row_loss, a.rows, a.loss_scale, a.loss);
         return;
     }
     if (blockIdx.y == 0) {
-        const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (e >= a.estart[a.L]) return;
+        const int64_t e0 = (int64_t)blockIdx.x * 256;
+        if (e0 >= a.estart[a.L]) return;
         int l = 0;
-        while (e >= a.estart[l + 1]) ++l;
-        const int64_t cnt = a.estart[l + 1] - a.estart[l], i = e - a.estart[l];
+        while (e0 >= a.estart[l + 1]) ++l;
+        const int64_t cnt = a.ecount[l], i = e0 + threadIdx.x - a.estart[l];
+        if (i >= cnt) return;
         float acc = 0.f;
         for (int s = 0; s < a.ksplit[l]; ++s) acc += a.part[l][(int64_t)s * cnt + i];
         a.dW[l][i] = acc;
         return;
     }
-    const int64_t ob = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t ob0 = (int64_t)blockIdx.x * 4;
     const int lane = threadIdx.x & 63;
-    if (ob >= a.ostart[a.L]) return;
+    if (ob0 >= a.ostart[a.L]) return;
     int l = 0;
-    while (ob >= a.ostart[l + 1]) ++l;
-    const int64_t o = ob - a.ostart[l];
+    while (ob0 >= a.ostart[l + 1]) ++l;
+    const int64_t o = ob0 + (threadIdx.x >> 6) - a.ostart[l];
+    if (o >= a.dout[l]) return;
     const uint16_t* src = a.DT[l] + o * a.ldt;
     float acc = 0.f;
     if (a.rows % 8 == 0 && a.ldt % 8 == 0) {
@@ -1128,8 +1136,8 @@ struct AdamRefreshArgs {
     const float* G;
     float lr, b1, b2, eps, gscale, bc1, bc2;
     int L;
-    int64_t wstart[MAX_LAYERS + 1];   // prefix sums of npad * kpad
-    int64_t bstart[MAX_LAYERS + 1];   // prefix sums of dout
+    int64_t wstart[MAX_LAYERS + 1];   // prefix sums of npad * kpad, each rounded up to a multiple of 256
+    int64_t bstart[MAX_LAYERS + 1];   // prefix sums of dout, each rounded up to a multiple of 256
     int din[MAX_LAYERS], dout[MAX_LAYERS], kpad[MAX_LAYERS], npad[MAX_LAYERS];
     int64_t woff[MAX_LAYERS], boff[MAX_LAYERS];
     uint16_t* Wb[MAX_LAYERS];
@@ -1147,24 +1155,29 @@ __device__ __forceinline__ float adam_one(const AdamRefreshArgs& a, int64_t idx)
     return p;
 }
 
+// Every layer's range starts at a multiple of 256, so a workgroup lies in
+// one layer: the layer search runs on the workgroup index (scalar loads of
+// the arguments), not per lane.
 __global__ __launch_bounds__(256) void adam_refresh_kernel(AdamRefreshArgs a) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < a.wstart[a.L]) {
+    const int64_t e0 = (int64_t)blockIdx.x * 256, e = e0 + threadIdx.x;
+    if (e0 < a.wstart[a.L]) {
         int l = 0;
-        while (e >= a.wstart[l + 1]) ++l;
+        while (e0 >= a.wstart[l + 1]) ++l;
         const int64_t loc = e - a.wstart[l];
-        const int o = (int)(loc / a.kpad[l]), i = (int)(loc % a.kpad[l]);
+        if (loc >= (int64_t)a.npad[l] * a.kpad[l]) return;
+        const int o = (int)loc / a.kpad[l], i = (int)loc - o * a.kpad[l];
         uint16_t v = 0;
         if (o < a.dout[l] && i < a.din[l]) v = to_bf16(adam_one(a, a.woff[l] + (int64_t)o * a.din[l] + i));
         a.Wb[l][loc] = v;
         if (a.WbT[l]) a.WbT[l][(int64_t)i * a.npad[l] + o] = v;
         return;
     }
-    const int64_t b = e - a.wstart[a.L];
-    if (b >= a.bstart[a.L]) return;
+    const int64_t b0 = e0 - a.wstart[a.L];
+    if (b0 >= a.bstart[a.L]) return;
     int l = 0;
-    while (b >= a.bstart[l + 1]) ++l;
-    adam_one(a, a.boff[l] + (b - a.bstart[l]));
+    while (b0 >= a.bstart[l + 1]) ++l;
+    const int64_t j = e - a.wstart[a.L] - a.bstart[l];
+    if (j < a.dout[l]) adam_one(a, a.boff[l] + j);
 }
 
 // BF16 copies of one layer's weights: Wb [npad][kpad] and WbT [kpad][npad]
